@@ -1,0 +1,412 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+No test here compares the oracle with itself: each checks it against an
+independent definition (Ewald2D, brute-force lattice sums, the interface
+conditions of electrostatics), an exact identity, an invariant, or a
+statistical property stated by the paper's theorems.
+"""
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
+
+
+def small_system(seed, N=6, L=10.0, H=4.0, margin=0.5, q=None):
+    rng = np.random.default_rng(seed)
+    pos = np.c_[rng.uniform(0, L, N), rng.uniform(0, L, N), rng.uniform(margin, H - margin, N)]
+    if q is None:
+        q = np.array([1.0, -1.0] * (N // 2))
+    return pos, q
+
+
+# --------------------------------------------------------------------------
+# Image series (Sec. 3.1): weights and positions
+# --------------------------------------------------------------------------
+
+def test_single_interface_is_one_jackson_image(orc):
+    """With gamma_top = 0 the only image is the one of the lower interface,
+    at -z with weight gamma_bot (textbook single dielectric interface)."""
+    H = 3.0
+    gp, gm = orc.image_coeffs(6, 0.0, 0.6)
+    assert np.all(gp == 0.0)
+    assert gm[0] == pytest.approx(0.6) and np.all(gm[1:] == 0.0)
+    assert orc.image_z(1, -1, 0.7, H) == pytest.approx(-0.7)
+    gp, gm = orc.image_coeffs(6, -0.3, 0.0)
+    assert np.all(gm == 0.0)
+    assert gp[0] == pytest.approx(-0.3) and np.all(gp[1:] == 0.0)
+    assert orc.image_z(1, +1, 0.7, H) == pytest.approx(2 * H - 0.7)
+
+
+def _layered_reflection(h, z, zp, H, g_top, g_bot):
+    """Reflected part of the xy-Fourier-transformed potential of a unit charge
+    at z' in the middle layer of a three-layer dielectric (eps_c = 1),
+    obtained by imposing continuity of phi and of eps dphi/dz at z = 0 and
+    z = H (4x4 linear solve).  Returns R(z) with phi_hat = 2pi/h e^{-h|z-z'|} + R."""
+    e_top = (1 - g_top) / (1 + g_top)
+    e_bot = (1 - g_bot) / (1 + g_bot)
+    G0 = 2 * np.pi / h
+    # unknowns [A (top: A e^{-hz}), B, C (middle: B e^{hz} + C e^{-hz}), D (bottom: D e^{hz})]
+    eH, emH = np.exp(h * H), np.exp(-h * H)
+    Amat = np.array([
+        [0.0, 1.0, 1.0, -1.0],                     # phi continuous at 0
+        [0.0, 1.0, -1.0, -e_bot],                  # eps dphi/dz continuous at 0 (divided by h)
+        [-emH, eH, emH, 0.0],                      # phi continuous at H
+        [e_top * emH, eH, -emH, 0.0],              # eps dphi/dz continuous at H (divided by h)
+    ])
+    rhs = np.array([
+        -G0 * np.exp(-h * zp),
+        -G0 * np.exp(-h * zp),
+        -G0 * np.exp(-h * (H - zp)),
+        G0 * np.exp(-h * (H - zp)),
+    ])
+    A, B, C, D = np.linalg.solve(Amat, rhs)
+    return B * np.exp(h * z) + C * np.exp(-h * z)
+
+
+@pytest.mark.parametrize("g_top,g_bot", [(0.7, -0.4), (-0.9, 0.95), (0.5, 0.5), (0.0, 0.8), (-0.6, 0.0)])
+def test_image_series_solves_interface_conditions(orc, g_top, g_bot):
+    """The image series with the oracle's weights and positions reproduces
+    the exact layered-medium response (this pins reading R1: the printed
+    exponent assignment fails this test whenever gamma_top != gamma_bot)."""
+    H = 1.3
+    M = 120
+    gp, gm = orc.image_coeffs(M, g_top, g_bot)
+    rng = np.random.default_rng(0)
+    for _ in range(20):
+        h = rng.uniform(0.2, 3.0)
+        z, zp = rng.uniform(0.05, H - 0.05, 2)
+        beta = sum(gp[l - 1] * np.exp(-h * abs(z - orc.image_z(l, +1, zp, H)))
+                   + gm[l - 1] * np.exp(-h * abs(z - orc.image_z(l, -1, zp, H)))
+                   for l in range(1, M + 1))
+        ref = _layered_reflection(h, z, zp, H, g_top, g_bot)
+        assert 2 * np.pi / h * beta == pytest.approx(ref, rel=1e-10, abs=1e-12)
+
+
+def test_image_series_matches_closed_form_beta(orc):
+    """Eqs. (3.6)-(3.8): the summed image series equals the closed form
+    beta_ij(h) = [g_b e^{-h|zi+zj|} + g_t e^{-h|2H-(zi+zj)|}
+                  + g_t g_b (e^{-h|2H-zij|} + e^{-h|2H+zij|})] zeta(h)."""
+    H, gt, gb = 2.0, 0.8, -0.6
+    gp, gm = orc.image_coeffs(200, gt, gb)
+    for h, zi, zj in [(0.3, 0.4, 1.7), (1.1, 1.9, 0.2), (2.5, 1.0, 1.0)]:
+        s = sum(gp[l - 1] * np.exp(-h * abs(zi - orc.image_z(l, +1, zj, H)))
+                + gm[l - 1] * np.exp(-h * abs(zi - orc.image_z(l, -1, zj, H)))
+                for l in range(1, 201))
+        zij = zi - zj
+        closed = (gb * np.exp(-h * abs(zi + zj)) + gt * np.exp(-h * abs(2 * H - zi - zj))
+                  + gt * gb * (np.exp(-h * abs(2 * H - zij)) + np.exp(-h * abs(2 * H + zij)))) \
+            / (1 - gt * gb * np.exp(-2 * h * H))
+        assert s == pytest.approx(closed, rel=1e-12)
+
+
+# --------------------------------------------------------------------------
+# Host parameters
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("alpha,Lx,Ly,Lz", [(1.0, 20, 20, 49.0), (0.5, 50, 50, 199.9), (0.3, 800, 800, 2199.0),
+                                          (2.0, 3.0, 4.0, 5.0)])
+def test_S_by_poisson_summation(orc, alpha, Lx, Ly, Lz):
+    """S of Eq. (2.21) against the Poisson-dual form of each theta factor,
+    sum_n e^{-pi^2 n^2/(a L)^2} = (a L/sqrt(pi)) sum_m e^{-a^2 L^2 m^2}."""
+    S = orc.norm_S(alpha, Lx, Ly, Lz)
+
+    def dual(L):
+        return alpha * L / math.sqrt(math.pi) * (1 + 2 * sum(math.exp(-(alpha * L * m) ** 2) for m in range(1, 20)))
+
+    assert S == pytest.approx(dual(Lx) * dual(Ly) * dual(Lz) - 1.0, rel=1e-13)
+    # and the bound of Eq. (2.25)
+    assert S <= alpha ** 3 * Lx * Ly * Lz / math.pi ** 1.5 * (1 + 1e-9) or alpha * min(Lx, Ly, Lz) < 2
+
+
+def test_S_by_direct_lattice_sum(orc):
+    a, L = 0.9, (3.0, 3.5, 6.0)
+    S = orc.norm_S(a, *L)
+    rng = range(-40, 41)
+    direct = 0.0
+    for nx in rng:
+        for ny in rng:
+            for nz in rng:
+                if nx == ny == nz == 0:
+                    continue
+                k2 = sum((2 * math.pi * n / l) ** 2 for n, l in zip((nx, ny, nz), L))
+                direct += math.exp(-k2 / (4 * a * a))
+    assert S == pytest.approx(direct, rel=1e-13)
+
+
+# --------------------------------------------------------------------------
+# Exact definitions: Ewald2D with images vs brute-force lattice summation
+# --------------------------------------------------------------------------
+
+CASES = [(0.0, 0.0, 0), (0.7, -0.4, 3), (0.5, 0.5, 2), (-0.95, 0.9, 1)]
+
+
+@pytest.mark.parametrize("g_top,g_bot,M", CASES)
+def test_ewald2d_images_alpha_independent(orc, g_top, g_bot, M):
+    pos, q = small_system(1)
+    s = orc.Slab(Lx=10, Ly=10, H=4, g_top=g_top, g_bot=g_bot, alpha=1.0, rc=4.9, M=M, P=10)
+    u1 = orc.ewald2d_images(s, pos, q, alpha=1.0)
+    u2 = orc.ewald2d_images(s, pos, q, alpha=0.6, nreal=6)
+    assert u1 == pytest.approx(u2, rel=1e-12, abs=1e-13)
+
+
+@pytest.mark.parametrize("g_top,g_bot,M", CASES[:3])
+def test_ewald2d_images_equals_bruteforce(orc, g_top, g_bot, M):
+    """Eq. (3.2) truncated at M by direct 1/r summation over a disk of lattice
+    cells (radius R, 2R cells), Richardson-extrapolated, vs Ewald2D."""
+    pos, q = small_system(2, N=4)
+    s = orc.Slab(Lx=10, Ly=10, H=4, g_top=g_top, g_bot=g_bot, alpha=1.0, rc=4.9, M=M, P=10)
+    u = orc.ewald2d_images(s, pos, q)
+    ub = orc.richardson(orc.brute_force_images(s, pos, q, 80), orc.brute_force_images(s, pos, q, 160))
+    assert ub == pytest.approx(u, rel=2e-6)
+
+
+# --------------------------------------------------------------------------
+# The reformulation of Theorem 3.3 (oracle k-space + IBC + self + real)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("g_top,g_bot,M", CASES)
+def test_reformulation_converges_to_ewald2d(orc, g_top, g_bot, M):
+    """Deterministic k-sum + U_IBC^M + self + real space (the oracle's pieces,
+    all weights deterministic) tends to Ewald2D with images as the vacuum
+    layer grows, at the rate exp(-2 pi (Lz - (M+1)H)/L) of Eq. (3.21)."""
+    pos, q = small_system(3)
+    H = 4.0
+    s = orc.Slab(Lx=10, Ly=10, H=H, g_top=g_top, g_bot=g_bot, alpha=1.0, rc=4.9, M=M, P=10)
+    u = orc.ewald2d_images(s, pos, q)
+    errs = []
+    for extra in (8.0, 14.0, 26.0):
+        s2 = orc.Slab(Lx=10, Ly=10, H=H, g_top=g_top, g_bot=g_bot, alpha=1.0, rc=4.9, M=M, P=10,
+                      Lz=(M + 1) * H + extra)
+        errs.append(abs(orc.deterministic_energy(s2, pos, q).E_total - u))
+    assert errs[-1] < 2e-6 * max(1.0, abs(u))
+    assert errs[0] > errs[1] > errs[2] or errs[0] < 1e-9
+
+
+# --------------------------------------------------------------------------
+# Recalibration identity (Sec. 3.4): Y_odd / Y_even folding == explicit images
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("g_top,g_bot,M", [(0.7, -0.4, 3), (0.95, -0.95, 10), (0.9, 0.9, 8), (0.3, 0.0, 1)])
+def test_recalibration_equals_explicit_images(orc, g_top, g_bot, M):
+    pos, q = small_system(4, N=30, L=12.0, H=3.0)
+    s = orc.Slab(Lx=12, Ly=12, H=3, g_top=g_top, g_bot=g_bot, alpha=0.8, rc=5.0, M=M, P=40)
+    n = orc.draw_kset(s, seed=7)
+    c = orc.rbe_weights(s, n)
+    Ea, Fa, pa, _, _, rMa = orc.kspace(s, pos, q, n, c, explicit_images=True)
+    Eb, Fb, pb, _, _, rMb = orc.kspace(s, pos, q, n, c, explicit_images=False)
+    assert np.allclose(rMa, rMb, rtol=1e-12, atol=1e-12 * np.abs(rMa).max())
+    assert Ea == pytest.approx(Eb, rel=1e-12)
+    assert np.allclose(Fa, Fb, rtol=1e-11, atol=1e-12 * np.abs(Fa).max())
+    assert np.allclose(pa, pb, rtol=1e-11, atol=1e-12 * np.abs(pa).max())
+
+
+# --------------------------------------------------------------------------
+# Forces and gradients are the gradients of the energy (R2, R4, R5)
+# --------------------------------------------------------------------------
+
+def fd_system(seed=5):
+    """Eight charges; the tests use alpha = 1.5, rc = 4.9 so that
+    erfc(alpha rc) ~ 1e-24 and the hard cutoff cannot show up in a
+    difference quotient."""
+    return small_system(seed, N=8, L=10.0, H=4.0)
+
+
+@pytest.mark.parametrize("g_top,g_bot,M", [(0.0, 0.0, 0), (0.7, -0.4, 3), (0.9, 0.9, 4)])
+def test_total_force_is_minus_gradient(orc, g_top, g_bot, M):
+    pos, q = fd_system()
+    s = orc.Slab(Lx=10, Ly=10, H=4, g_top=g_top, g_bot=g_bot, alpha=1.5, rc=4.9, M=M, P=30)
+    n = orc.draw_kset(s, seed=11)
+    r = orc.evaluate(s, pos, q, n)
+    h = 1e-5
+    for part, getF in (("real", lambda x: x.F_real), ("kspace", lambda x: x.F_k), ("ibc", lambda x: x.F_ibc)):
+        ref = getF(orc.evaluate(s, pos, q, n, parts=(part,)))
+        for i in range(len(q)):
+            for d in range(3):
+                pp, pm = pos.copy(), pos.copy()
+                pp[i, d] += h
+                pm[i, d] -= h
+                ep = orc.evaluate(s, pp, q, n, parts=(part,)).E_total
+                em = orc.evaluate(s, pm, q, n, parts=(part,)).E_total
+                fd = -(ep - em) / (2 * h)
+                scale = np.abs(ref).max() + 1e-30
+                assert abs(fd - ref[i, d]) < 2e-7 * scale + 1e-9, (part, i, d, fd, ref[i, d])
+    assert np.allclose(r.F, r.F_real + r.F_k + r.F_ibc)
+
+
+@pytest.mark.parametrize("g_top,g_bot,M", [(0.7, -0.4, 3), (0.0, 0.0, 0)])
+def test_dE_dq_is_derivative(orc, g_top, g_bot, M):
+    pos, q = fd_system()
+    s = orc.Slab(Lx=10, Ly=10, H=4, g_top=g_top, g_bot=g_bot, alpha=1.5, rc=4.9, M=M, P=30)
+    n = orc.draw_kset(s, seed=12)
+    r = orc.evaluate(s, pos, q, n)
+    h = 1e-4
+    for i in range(len(q)):
+        qp, qm = q.copy(), q.copy()
+        qp[i] += h
+        qm[i] -= h
+        fd = (orc.evaluate(s, pos, qp, n).E_total - orc.evaluate(s, pos, qm, n).E_total) / (2 * h)
+        assert fd == pytest.approx(r.phi[i], rel=1e-8, abs=1e-9)
+
+
+def test_dE_dgamma_is_derivative(orc):
+    pos, q = fd_system()
+    n = None
+    h = 1e-6
+    for gt, gb, M in [(0.7, -0.4, 3), (0.9, 0.9, 6), (0.3, -0.95, 1)]:
+        s = orc.Slab(Lx=10, Ly=10, H=4, g_top=gt, g_bot=gb, alpha=1.5, rc=4.9, M=M, P=30)
+        n = orc.draw_kset(s, seed=13)
+        c = orc.rbe_weights(s, n)
+        g = orc.dE_dgamma(s, pos, q, n, c)
+        for w in (0, 1):
+            sp = orc.Slab(**{**s.__dict__, "g_top": gt + h * (w == 0), "g_bot": gb + h * (w == 1)})
+            sm = orc.Slab(**{**s.__dict__, "g_top": gt - h * (w == 0), "g_bot": gb - h * (w == 1)})
+            fd = (orc.evaluate(sp, pos, q, n, c).E_total - orc.evaluate(sm, pos, q, n, c).E_total) / (2 * h)
+            assert fd == pytest.approx(g[w], rel=1e-6, abs=1e-8), (gt, gb, M, w)
+
+
+# --------------------------------------------------------------------------
+# Invariants
+# --------------------------------------------------------------------------
+
+def test_kspace_xy_momentum_conserved_per_k(orc):
+    """Each k alone gives sum_i F_xy = 0 for any gamma (lateral translation
+    invariance); at gamma = 0 also sum_i F_z = 0."""
+    pos, q = small_system(6, N=20)
+    for gt, gb, M in [(0.8, -0.7, 5), (0.0, 0.0, 0)]:
+        s = orc.Slab(Lx=10, Ly=10, H=4, g_top=gt, g_bot=gb, alpha=1.0, rc=4.9, M=M, P=25)
+        n = orc.draw_kset(s, seed=3)
+        c = orc.rbe_weights(s, n)
+        for l in range(5):
+            _, F, *_ = orc.kspace(s, pos, q, n[l:l + 1], c[l:l + 1])
+            tot = F.sum(axis=0)
+            sc = np.abs(F).sum()
+            assert abs(tot[0]) < 1e-12 * sc and abs(tot[1]) < 1e-12 * sc
+            if gt == 0 and gb == 0:
+                assert abs(tot[2]) < 1e-12 * sc
+
+
+def test_real_space_xy_momentum_conserved(orc):
+    pos, q = small_system(7, N=30)
+    s = orc.Slab(Lx=10, Ly=10, H=4, g_top=0.6, g_bot=-0.8, alpha=1.0, rc=4.0, M=4, P=10)
+    _, F, _, _ = orc.real_space(s, pos, q)
+    tot = F.sum(axis=0)
+    assert abs(tot[0]) < 1e-12 * np.abs(F).sum() and abs(tot[1]) < 1e-12 * np.abs(F).sum()
+
+
+def test_gamma0_reduces_to_homogeneous_rbe_force(orc):
+    """At gamma = 0 the k-space force is Eq. (2.20) without its Gaussian
+    factor (reading R3): -sum (S/P) 4 pi q_i k / (V k^2) Im(e^{-ik.r_i} rho(k))."""
+    pos, q = small_system(8, N=16)
+    s = orc.Slab(Lx=10, Ly=10, H=4, g_top=0.0, g_bot=0.0, alpha=1.0, rc=4.9, M=3, P=40)
+    n = orc.draw_kset(s, seed=5)
+    _, F, *_ = orc.kspace(s, pos, q, n, orc.rbe_weights(s, n))
+    S = orc.norm_S(s.alpha, s.Lx, s.Ly, s.Lz)
+    k = orc.kvectors(s, n)
+    rho = (q[None, :] * np.exp(1j * (k @ pos.T))).sum(axis=1)
+    ref = np.zeros_like(F)
+    for l in range(len(n)):
+        ph = np.exp(-1j * (pos @ k[l]))
+        ref -= (S / s.P) * 4 * np.pi * q[:, None] * k[l][None, :] / (s.V * (k[l] @ k[l])) * np.imag(ph * rho[l])[:, None]
+    assert np.allclose(F, ref, rtol=1e-11, atol=1e-13 * np.abs(ref).max())
+
+
+def test_mirror_symmetry(orc):
+    """z -> H - z with gamma_top <-> gamma_bot and n_z -> -n_z: E unchanged,
+    F_z -> -F_z, F_xy unchanged."""
+    pos, q = small_system(9, N=12)
+    s1 = orc.Slab(Lx=10, Ly=10, H=4, g_top=0.7, g_bot=-0.5, alpha=1.2, rc=4.5, M=5, P=30)
+    s2 = orc.Slab(Lx=10, Ly=10, H=4, g_top=-0.5, g_bot=0.7, alpha=1.2, rc=4.5, M=5, P=30)
+    n = orc.draw_kset(s1, seed=9)
+    n2 = n * np.array([1, 1, -1], dtype=np.int32)
+    pos2 = pos.copy()
+    pos2[:, 2] = 4.0 - pos[:, 2]
+    r1 = orc.evaluate(s1, pos, q, n)
+    r2 = orc.evaluate(s2, pos2, q, n2)
+    assert r1.E_total == pytest.approx(r2.E_total, rel=1e-11)
+    assert np.allclose(r1.F * [1, 1, -1], r2.F, rtol=1e-9, atol=1e-11 * np.abs(r1.F).max())
+
+
+def test_lateral_translation_and_charge_scaling(orc):
+    pos, q = small_system(10, N=12)
+    s = orc.Slab(Lx=10, Ly=10, H=4, g_top=0.4, g_bot=0.9, alpha=1.2, rc=4.5, M=4, P=30)
+    n = orc.draw_kset(s, seed=10)
+    r = orc.evaluate(s, pos, q, n)
+    sh = pos + np.array([3.3, -7.1, 0.0])
+    r2 = orc.evaluate(s, sh, q, n)
+    assert r.E_total == pytest.approx(r2.E_total, rel=1e-10)
+    assert np.allclose(r.F, r2.F, rtol=1e-8, atol=1e-10 * np.abs(r.F).max())
+    r3 = orc.evaluate(s, pos, 2.5 * q, n)
+    assert r3.E_total == pytest.approx(6.25 * r.E_total, rel=1e-12)
+    assert np.allclose(r3.F, 6.25 * r.F, rtol=1e-11)
+
+
+# --------------------------------------------------------------------------
+# Statistics of the random batch estimator (Theorem 2.2 and Sec. 3.4)
+# --------------------------------------------------------------------------
+
+def test_rbe_estimator_is_unbiased_and_variance_scales_as_1_over_P(orc):
+    pos, q = small_system(11, N=20, L=8.0, H=3.0)
+    s = orc.Slab(Lx=8, Ly=8, H=3, g_top=0.6, g_bot=-0.7, alpha=0.9, rc=3.9, M=4, P=20)
+    nfull, cfull = orc.full_kset(s)
+    Eref, Fref, *_ = orc.kspace(s, pos, q, nfull, cfull)
+    S = orc.norm_S(s.alpha, s.Lx, s.Ly, s.Lz)
+    samples = {}
+    for P in (10, 40):
+        Es, Fs = [], []
+        for r in range(300):
+            n = orc.draw_kset(s, seed=1000 + r, stream=P, P=P)
+            E, F, *_ = orc.kspace(s, pos, q, n, orc.rbe_weights(s, n, S))
+            Es.append(E)
+            Fs.append(F[0])
+        Es, Fs = np.array(Es), np.array(Fs)
+        samples[P] = (Es, Fs)
+        z = (Es.mean() - Eref) / (Es.std(ddof=1) / math.sqrt(len(Es)))
+        assert abs(z) < 4.5, (P, z)
+        zf = (Fs.mean(axis=0) - Fref[0]) / (Fs.std(axis=0, ddof=1) / math.sqrt(len(Fs)))
+        assert np.all(np.abs(zf) < 4.5), (P, zf)
+    ratio = samples[10][1].var(axis=0).sum() / samples[40][1].var(axis=0).sum()
+    assert 2.5 < ratio < 6.5, ratio
+
+
+# --------------------------------------------------------------------------
+# The k-sampler's distribution (Sec. 2.3)
+# --------------------------------------------------------------------------
+
+def test_sampler_marginals_chi2(orc):
+    from scipy.stats import chi2
+    s = orc.Slab(Lx=6, Ly=9, H=2, g_top=0, g_bot=0, alpha=0.8, rc=2.9, M=0, P=6000, Lz=12.0)
+    n = orc.draw_kset(s, seed=2024)
+    assert not np.any(np.all(n == 0, axis=1))
+    Ls = (s.Lx, s.Ly, s.Lz)
+    w = [lambda v, L=L: math.exp(-(math.pi * v / (s.alpha * L)) ** 2) for L in Ls]
+    Z = [sum(f(v) for v in range(-200, 201)) for f in w]
+    p0 = [f(0) / z for f, z in zip(w, Z)]
+    for d in range(3):
+        others0 = np.prod([p0[e] for e in range(3) if e != d])
+        vals, counts = np.unique(n[:, d], return_counts=True)
+        cmap = dict(zip(vals.tolist(), counts.tolist()))
+        top = int(max(abs(vals.min()), abs(vals.max())))
+        exp_, obs = [], []
+        for v in range(-top, top + 1):
+            p = w[d](v) / Z[d] * (1 - (others0 if v == 0 else 0.0)) / (1 - np.prod(p0))
+            exp_.append(p * len(n))
+            obs.append(cmap.get(v, 0))
+        exp_, obs = np.array(exp_), np.array(obs)
+        # pool bins with expected count < 5 into the tails
+        big = exp_ >= 5
+        e2 = np.append(exp_[big], exp_[~big].sum())
+        o2 = np.append(obs[big], obs[~big].sum())
+        if e2[-1] < 5:
+            e2, o2 = e2[:-1], o2[:-1]
+        stat = ((o2 - e2) ** 2 / e2).sum()
+        assert stat < chi2.ppf(0.9999, len(e2) - 1), (d, stat)
+
+
+def test_sampler_is_deterministic_per_seed_and_stream(orc):
+    s = orc.Slab(Lx=20, Ly=20, H=5, g_top=0, g_bot=0, alpha=1.0, rc=4, M=0, P=50)
+    a = orc.draw_kset(s, seed=0)
+    b = orc.draw_kset(s, seed=0)
+    c = orc.draw_kset(s, seed=0, stream=1)
+    assert np.array_equal(a, b) and not np.array_equal(a, c)
