@@ -1,0 +1,215 @@
+"""Throughput benchmark of the RBE2D hot path on one MI355X.
+
+One step = one velocity-Verlet MD step of the 1e6-ion slab (800 x 800 x 40,
+gamma_top = +0.95, gamma_bot = -0.95, M = 10, alpha = 0.3, r_c = 10, P = 500,
+FP32 phases with FP64 accumulation): half kick + drift, a fresh k-set drawn
+on the device, real space (cell list + erfc pairs with images), k-space
+(structure factors, recalibration, force scatter), IBC, half kick.
+
+Prints one JSON line: particle-steps/s, the live roofline of the dominant
+kernel (HIP events around its launches in the timed region) and the CPU
+oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "RBE2D force+grad particle-steps/s at N=1e6 and 64-replica batch vs plain FP64"
+
+# MI355X published peaks and the VALU issue rate (256 CUs x 64 lanes x 2.4 GHz)
+PEAK_HBM_GBS = 8000.0
+VALU_LANE_SLOTS = 256 * 64 * 2.4e9          # lane-instruction slots per second
+# algorithmic VALU lane-slots per (particle, k) pair; a transcendental
+# (v_sin/v_cos/v_exp/v_rsq/v_rcp) occupies 2 slots (half rate on gfx950)
+SLOTS_SF = 16      # k.r (3), khat.r (1), sin+cos of both (8), 4 accumulating FMAs
+SLOTS_FORCE = 21   # k.r (3), khat.r (1), sin+cos of both (8), 2 Im parts (4), X+-Y (2), 3 force FMAs
+SLOTS_REAL = 24    # per pair within r_c: d2 (5), cutoff (1), rsqrt (2), exp (2+1), erfc fit
+                   # (rcp 2 + 9 FMA), force factor (2); pairs outside r_c not counted
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--fp64-steps", type=int, default=3, help="steps of the plain FP64 path (0 = skip)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=20000, help="particles in the oracle's rho sample")
+    ap.add_argument("--cpu-targets", type=int, default=32, help="oracle force targets")
+    return ap.parse_args()
+
+
+def expected_real_pairs(w, nz=4000):
+    """Expected number of (target, source) pairs within r_c for uniform
+    density in [margin, H - margin], real sources plus first images."""
+    rho = w.N / (w.Lx * w.Ly * (w.H - 2 * w.margin))
+    z = np.linspace(w.margin, w.H - w.margin, nz)
+    rc = w.r_c
+
+    def cap_volume(zc, lo, hi):
+        # volume of the ball of radius rc at height zc inside the layer lo < z < hi
+        a = np.clip(lo - zc, -rc, rc)
+        b = np.clip(hi - zc, -rc, rc)
+        f = lambda t: math.pi * (rc * rc * t - t ** 3 / 3.0)  # noqa: E731
+        return f(b) - f(a)
+
+    lo, hi = w.margin, w.H - w.margin
+    direct = cap_volume(z, lo, hi)
+    img = cap_volume(-z, lo, hi) + cap_volume(2 * w.H - z, lo, hi)   # first-order images
+    return float(rho * w.N * np.mean(direct + img))
+
+
+def run_md(R, torch, w, precision, steps, warmup, profile):
+    from paper_2405_06333_amd import inputs
+    pos, q = inputs.sample(w)
+    dev = "cuda"
+    P_ = torch.as_tensor(pos, device=dev)
+    Q_ = torch.as_tensor(q, device=dev)
+    V_ = torch.zeros_like(P_)
+    F_ = torch.zeros_like(P_)
+    slab = R.Slab(**w.slab_kwargs(), precision=precision, n_max=w.N)
+    slab.sample_kset(w.seed, 0)
+    slab.forces(P_, Q_, out=F_)
+    zlo, zhi = w.margin, w.H - w.margin
+    step = 1
+    slab.md_run(P_, V_, Q_, F_, w.dt, zlo, zhi, w.seed, step, warmup)
+    step += warmup
+    torch.cuda.synchronize()
+    slab.check()
+    if profile:
+        slab.profile_enable(steps + 4)
+        slab.profile_read()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    slab.md_run(P_, V_, Q_, F_, w.dt, zlo, zhi, w.seed, step, steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = slab.profile_read() if profile else None
+    slab.check()
+    finite = bool(torch.isfinite(F_).all().item() and torch.isfinite(P_).all().item())
+    return (t1 - t0), prof, finite
+
+
+def cpu_baseline(w, n_sample, n_targets):
+    """The CPU oracle on a bounded sample of the workload: rho over n_sample
+    particles and the full force (k-space + real space + IBC) on n_targets
+    particles of the N-particle system; scaled to one full step."""
+    from oracle import oracle as orc
+    from paper_2405_06333_amd import inputs
+    pos, q = inputs.sample(w)
+    o = orc.Slab(Lx=w.Lx, Ly=w.Ly, H=w.H, g_top=w.gamma_top, g_bot=w.gamma_bot, alpha=w.alpha, rc=w.r_c,
+                 M=w.M, P=w.P)
+    n = orc.draw_kset(o, w.seed, 0)
+    c = orc.rbe_weights(o, n)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    sub = slice(0, n_sample)
+    t0 = time.perf_counter()
+    orc.kspace(o, pos[sub], q[sub], n, c, targets=np.zeros(0, dtype=np.int64))
+    t_rho = time.perf_counter() - t0
+    rng = np.random.default_rng(5)
+    tg = np.sort(rng.choice(w.N, n_targets, replace=False))
+    t0 = time.perf_counter()
+    orc.evaluate(o, pos, q, n, c, targets=tg)
+    t_full_targets = time.perf_counter() - t0
+    # the targets run also recomputed rho over all N once: remove that share
+    t_rho_all = t_rho * w.N / n_sample
+    t_per_target = max(t_full_targets - t_rho_all, 0.0) / n_targets
+    t_step = t_rho_all + t_per_target * w.N
+    return {
+        "value": w.N / t_step,
+        "unit": "particle-steps/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": (f"oracle rho(k) over {n_sample} of the {w.N} particles ({t_rho:.2f} s) and full "
+                   f"forces on {n_targets} sampled particles of the whole system ({t_full_targets:.2f} s), "
+                   f"scaled to one step of all {w.N} particles ({t_step:.3g} s/step)"),
+    }
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only; --gpus {a.gpus} is not supported", file=sys.stderr)
+        return 2
+    import torch
+    from paper_2405_06333_amd import inputs, rbe2d as R
+    R.lib()
+    w = inputs.LARGE_MD
+    secs, prof, finite = run_md(R, torch, w, a.precision, a.steps, a.warmup, profile=True)
+    ms_step = secs * 1e3 / a.steps
+    value = w.N * a.steps / secs
+
+    # per-kernel breakdown and the roofline of the dominant kernel
+    kern = {k: {"ms_per_launch": (t / n if n else None), "launches": n} for k, (t, n) in prof.items()}
+    dom = max(prof, key=lambda k: prof[k][0])
+    t_dom = prof[dom][0] / max(prof[dom][1], 1) * 1e-3
+    NP = w.N * w.P
+    pairs_real = expected_real_pairs(w)
+    if dom == "sf_pass":
+        work = SLOTS_SF * NP
+    elif dom == "force_scatter":
+        work = SLOTS_FORCE * NP
+    elif dom == "real_pairs":
+        work = SLOTS_REAL * pairs_real
+    else:
+        work = None
+    roof = None
+    if work is not None:
+        ach = work / t_dom / 1e12
+        peak = VALU_LANE_SLOTS / 1e12
+        roof = {"bound": "alu", "kernel": dom, "achieved": round(ach, 3), "peak": round(peak, 3),
+                "unit": "Tlane-slot/s", "frac": round(ach / peak, 4), "traffic": None}
+    for k, slots, units in (("sf_pass", SLOTS_SF, NP), ("force_scatter", SLOTS_FORCE, NP),
+                            ("real_pairs", SLOTS_REAL, pairs_real)):
+        t, n = prof[k]
+        if n:
+            kern[k]["valu_frac"] = round(slots * units / (t / n * 1e-3) / VALU_LANE_SLOTS, 4)
+    t, n = prof["real_pairs"]
+    if n:   # algorithmic HBM bytes of the pair kernel: read (x, y, z, q) + index, write F and phi
+        kern["real_pairs"]["hbm_GBs"] = round(w.N * (32 + 4 + 32) / (t / n * 1e-3) / 1e9, 1)
+
+    fp64 = None
+    if a.fp64_steps > 0 and a.precision != "fp64":
+        s64, _, _ = run_md(R, torch, w, "fp64", a.fp64_steps, 1, profile=False)
+        fp64 = {"value": w.N * a.fp64_steps / s64, "unit": "particle-steps/s", "steps": a.fp64_steps}
+
+    cpu = None if a.no_cpu_baseline else cpu_baseline(w, a.cpu_sample, a.cpu_targets)
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if a.precision == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": (f"large_md: N={w.N} 1:1 ions, {w.Lx:g}x{w.Ly:g}x{w.H:g} slab, "
+                                f"gamma_top={w.gamma_top}, gamma_bot={w.gamma_bot}, M={w.M}, alpha={w.alpha}, "
+                                f"r_c={w.r_c}, P={w.P}, velocity-Verlet dt={w.dt}"),
+                   "precision": "FP32 phases and transcendentals, FP64 geometry and accumulation"
+                   if a.precision == "fp32" else "FP64"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "plain_fp64_gpu": fp64,
+        "kernels": kern,
+        "finite": finite,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

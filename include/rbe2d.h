@@ -1,0 +1,206 @@
+/*
+ * rbe2d.h -- C ABI of librbe2d.so, an MI355X (gfx950) implementation of the
+ * random batch Ewald method for charges in a doubly periodic slab with
+ * dielectric jumps at its two faces (RBE2D; Gan, Gao, Liang, Xu,
+ * arXiv:2405.06333, Algorithm 2).
+ *
+ * Physics and notation
+ *   N point charges q_i at r_i = (x_i, y_i, z_i) with 0 < z_i < H, periodic
+ *   in x (period Lx) and y (Ly); dielectric contrast gamma_bot at z = 0 and
+ *   gamma_top at z = H (Eq. (3.1)); image series truncated at order M
+ *   (Eqs. (3.2)-(3.3)): the order-l image above the slab has weight
+ *   gamma_top^ceil(l/2) gamma_bot^floor(l/2) and z = (-1)^l z + 2 ceil(l/2) H,
+ *   the one below gamma_bot^ceil(l/2) gamma_top^floor(l/2) and
+ *   z = (-1)^l z - 2 floor(l/2) H.  Coulomb constant 1, eps_c = 1 (Eq. (2.1));
+ *   every energy, force and gradient is multiplied by coulomb_prefactor.
+ *
+ *   Energy (Eq. (3.11)-(3.18), ELC and remainder terms dropped):
+ *     E = E_real + E_k + E_self + E_ibc
+ *     E_real  erfc real-space sum over real charges and images with d < r_c
+ *             (Eq. (3.12); minimum image in x, y; hard cutoff)
+ *     E_k     random batch estimator of the first term of Eq. (3.16):
+ *             sum_l c_l Re(rho(k_l) conj(rho^M(k_l))), c_l = 2 pi S/(V P |k_l|^2),
+ *             rho(k) = sum_j q_j e^{i k.r_j}, rho^M = (1 + Y_even) rho + Y_odd rhohat
+ *             (Sec. 3.4), k_l = 2 pi (nx/Lx, ny/Ly, nz/Lz_ext)
+ *     E_self  -alpha/sqrt(pi) sum_i q_i^2
+ *     E_ibc   U_IBC^M of Theorem 3.3
+ *   Forces are -grad E at fixed k-set (k-space: Eq. (3.25)-(3.26)).
+ *   V = Lx Ly Lz_ext, S = sum_{k != 0} exp(-k^2/4 alpha^2) (Eq. (2.21)).
+ *
+ * Conventions
+ *   - Every function returns rbe2d_status (0 = OK, < 0 = error) and never
+ *     aborts or exits.  A message for the last error of a handle is returned
+ *     by rbe2d_last_error.
+ *   - Arrays marked "device" are device pointers (hipMalloc / torch CUDA
+ *     tensors) owned by the caller, FP64, contiguous: positions and forces
+ *     are N x 3 row-major (x, y, z per particle).  The handle owns its
+ *     workspaces; they are sized at create time from n_max and nothing is
+ *     allocated afterwards.
+ *   - `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *     Compute calls only enqueue work on it and never synchronise, so they
+ *     can be captured into a hipGraph; only rbe2d_check and rbe2d_get_kset
+ *     synchronise.
+ *   - x and y may take any value (they are wrapped); z must lie in (0, H).
+ *     A z outside that range sets a device error word that the next
+ *     rbe2d_check reports as RBE2D_E_RANGE; the results of that call are
+ *     then undefined (but the kernels stay in bounds).
+ *   - A handle is not thread-safe; distinct handles are independent.
+ *     Overlapping calls on one handle from different streams race.
+ */
+#ifndef RBE2D_H
+#define RBE2D_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rbe2d_ctx *rbe2d_handle;
+
+typedef enum {
+    RBE2D_OK = 0,
+    RBE2D_E_INVAL = -1,   /* bad argument or parameter                    */
+    RBE2D_E_NOMEM = -2,   /* device or host allocation failed             */
+    RBE2D_E_HIP = -3,     /* a HIP runtime call failed                    */
+    RBE2D_E_STATE = -4,   /* call not valid in the handle's current state */
+    RBE2D_E_RANGE = -5    /* a particle was outside 0 < z < H             */
+} rbe2d_status;
+
+/* Precision of the k-space phases and transcendentals. */
+enum {
+    RBE2D_PREC_FP64 = 0,        /* FP64 throughout                                   */
+    RBE2D_PREC_FP32_PHASE = 1   /* FP32 phases, sin/cos, erfc/exp; FP64 geometry,
+                                   FP64 rho(k) accumulation across particle tiles,
+                                   FP64 per-k coefficients                          */
+};
+
+/* Flags of rbe2d_forces. */
+enum {
+    RBE2D_KSPACE = 1,        /* random batch k-space term           */
+    RBE2D_REAL = 2,          /* real-space erfc term with images     */
+    RBE2D_IBC = 4,           /* IBC term (and the self energy)       */
+    RBE2D_ALL = 7,
+    RBE2D_ACCUMULATE = 16    /* add to F instead of overwriting it   */
+};
+
+typedef struct {
+    double Lx, Ly, H;          /* box: periods in x, y and slab thickness (> 0)           */
+    double Lz_ext;             /* extended periodic height; <= 0 selects the smallest
+                                  value allowed by Eq. (3.23) at tolerance eps_lz        */
+    double eps_lz;             /* tolerance for the automatic Lz_ext (<= 0 -> 1e-6)      */
+    double gamma_top;          /* contrast at z = H, |gamma_top| <= 1                    */
+    double gamma_bot;          /* contrast at z = 0, |gamma_bot| <= 1                    */
+    double alpha;              /* Ewald splitting parameter (> 0)                        */
+    double r_c;                /* real-space cutoff, 0 < r_c <= min(Lx, Ly)/2            */
+    int32_t P;                 /* wave vectors per batch, 1 <= P <= 65536                */
+    int32_t M;                 /* image order, 0 <= M <= 64                              */
+    int32_t precision;         /* RBE2D_PREC_*                                           */
+    int32_t reserved;          /* must be 0                                              */
+    int64_t n_max;             /* largest N a call may pass (>= 0)                       */
+    double coulomb_prefactor;  /* scale of all energies/forces (0 -> 1.0)                */
+} rbe2d_params;
+
+/* Validates *p, derives Lz_ext, V and S (Eq. (2.21)), uploads the image and
+ * sampling tables, allocates every workspace for up to p->n_max particles on
+ * the current HIP device, and returns a handle in *out.  The k-set starts
+ * out undefined: set one with rbe2d_set_kset or rbe2d_sample_kset.
+ * Errors: RBE2D_E_INVAL (parameters, out == NULL), RBE2D_E_NOMEM,
+ * RBE2D_E_HIP.  On error *out is set to NULL. */
+rbe2d_status rbe2d_create(const rbe2d_params *p, rbe2d_handle *out);
+
+/* Frees the handle and its device memory (after synchronising the device).
+ * NULL is ignored. */
+void rbe2d_destroy(rbe2d_handle h);
+
+/* Returns the derived extended height, V = Lx Ly Lz_ext and S (Eq. (2.21)).
+ * Any output pointer may be NULL. */
+rbe2d_status rbe2d_query(rbe2d_handle h, double *Lz_ext, double *V, double *S);
+
+/* Pure host function.  Draws P integer vectors n != 0, i.i.d. with
+ * probability proportional to exp(-|k|^2/(4 alpha^2)), k = 2 pi (nx/Lx,
+ * ny/Ly, nz/Lz_ext) -- the importance distribution of Sec. 2.3, sampled
+ * exactly (with replacement) instead of by a Metropolis chain.  Each axis is
+ * drawn by inverse CDF over |n| <= ceil(10 sigma) + 1, sigma = alpha L /
+ * (sqrt(2) pi), from a counter-based SplitMix64 stream keyed by (seed,
+ * stream_id); a zero vector is redrawn (at most 64 attempts, else
+ * RBE2D_E_STATE).  Writes P x 3 int32 to n_out (host).  The device sampler
+ * (rbe2d_sample_kset) draws the identical vectors. */
+rbe2d_status rbe2d_draw_kset(const rbe2d_params *p, uint64_t seed, uint64_t stream_id,
+                             int32_t *n_out);
+
+/* Makes n (P x 3 int32, host or device per n_is_device) the handle's k-set.
+ * Entries must be nonzero vectors with |n_d| < 2^20; a host array is
+ * checked (RBE2D_E_INVAL), a device array is not. */
+rbe2d_status rbe2d_set_kset(rbe2d_handle h, const int32_t *n, int n_is_device, void *stream);
+
+/* Draws the handle's k-set on the device (same vectors as rbe2d_draw_kset
+ * with the same seed and stream_id).  Enqueued only; graph-capturable. */
+rbe2d_status rbe2d_sample_kset(rbe2d_handle h, uint64_t seed, uint64_t stream_id, void *stream);
+
+/* Copies the current k-set to n_host (P x 3 int32) and synchronises. */
+rbe2d_status rbe2d_get_kset(rbe2d_handle h, int32_t *n_host, void *stream);
+
+/* Forces (and optionally energies) for N <= n_max charges.
+ *   pos    device, N x 3      q      device, N
+ *   F      device, N x 3, written (or accumulated with RBE2D_ACCUMULATE)
+ *   energy device, 5 doubles or NULL: {total, real, kspace, self, ibc}
+ *          (parts excluded by flags are 0; self goes with RBE2D_KSPACE)
+ * N == 0 is valid (energy set to 0).  Errors: RBE2D_E_INVAL (N < 0,
+ * N > n_max, NULL pointers with N > 0, bad flags), RBE2D_E_STATE (no
+ * k-set), RBE2D_E_HIP (launch failure). */
+rbe2d_status rbe2d_forces(rbe2d_handle h, int64_t N, const double *pos, const double *q,
+                          double *F, double *energy, uint32_t flags, void *stream);
+
+/* Energy only: energy (device, 5 doubles) as in rbe2d_forces with
+ * RBE2D_ALL.  Same errors. */
+rbe2d_status rbe2d_energy(rbe2d_handle h, int64_t N, const double *pos, const double *q,
+                          double *energy, void *stream);
+
+/* Adjoint of rbe2d_energy at the current k-set: given gE = dL/dE (device
+ * scalar), writes dL/dr (device N x 3), dL/dq (device N) and
+ * dL/dgamma (device 2: top, bot); any output may be NULL.  rho(k) is
+ * recomputed, not stored.  dE/dq_i = phi_i, the electrostatic potential at
+ * r_i of all other charges, all images (own images included) and the
+ * k-space/IBC/self terms, taken literally (no neutralising background). */
+rbe2d_status rbe2d_energy_backward(rbe2d_handle h, int64_t N, const double *pos,
+                                   const double *q, const double *gE, double *dEdr,
+                                   double *dEdq, double *dEdgamma, void *stream);
+
+/* n_steps velocity-Verlet steps (Algorithm 2 without thermostat) with unit
+ * masses: v += dt/2 F; r += dt v; x, y wrapped; z reflected specularly at
+ * z_lo and z_hi (0 < z_lo < z_hi < H); a fresh k-set drawn on the device
+ * from (seed, stream_id = step0 + step); F recomputed (RBE2D_ALL);
+ * v += dt/2 F.  F must hold the forces of the initial positions on entry.
+ * pos, vel, F (device N x 3) are updated in place.  Enqueued only. */
+rbe2d_status rbe2d_md_run(rbe2d_handle h, int64_t N, double *pos, double *vel, const double *q,
+                          double *F, double dt, double z_lo, double z_hi, uint64_t seed,
+                          int64_t step0, int32_t n_steps, void *stream);
+
+/* Kernel timing (tracing).  rbe2d_profile_enable(h, n) creates n event
+ * pairs per kernel class and from then on brackets every launch of each
+ * class with HIP events on the launch stream (n = 0 turns timing off and
+ * frees the events).  rbe2d_profile_read synchronises the device and
+ * writes, for each of the first n_slots classes, the summed duration in
+ * milliseconds and the number of launches timed since the last read (a
+ * class launched more than n times between reads keeps its first n).
+ * Classes: 0 prep, 1 structure-factor pass, 2 per-k reduce/assemble,
+ * 3 cell-list build, 4 real-space pairs, 5 force scatter, 6 energies,
+ * 7 integrator, 8 k-sampler.  Not to be used while a graph is captured. */
+enum { RBE2D_PROF_SLOTS = 9 };
+rbe2d_status rbe2d_profile_enable(rbe2d_handle h, int32_t n_events);
+rbe2d_status rbe2d_profile_read(rbe2d_handle h, double *ms, int64_t *launches, int32_t n_slots);
+
+/* Synchronises `stream` and reports asynchronous errors: RBE2D_E_RANGE if a
+ * call since the last check saw z outside (0, H), RBE2D_E_HIP for a failed
+ * kernel.  Clears the device error word. */
+rbe2d_status rbe2d_check(rbe2d_handle h, void *stream);
+
+/* Message of the handle's last error ("" if none).  With h == NULL, the
+ * message of the last failed rbe2d_create in this thread. */
+const char *rbe2d_last_error(rbe2d_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RBE2D_H */

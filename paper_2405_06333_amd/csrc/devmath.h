@@ -1,0 +1,100 @@
+// Device helpers shared by the kernels of librbe2d: FP64 sincos on
+// revolutions, wave and block reductions with a fixed summation order.
+#pragma once
+
+#include "rbe2d_internal.h"
+
+namespace rbe2d {
+
+// sin and cos of 2 pi r: r is reduced to the nearest quarter turn
+// (r - q/4 is exact by Sterbenz' lemma), then Taylor polynomials of sin
+// (to t^15) and cos (to t^16) on |t| <= pi/4, whose truncation errors are
+// below 5e-17.
+__device__ __forceinline__ void sincos_rev64(double r, double *s_out, double *c_out) {
+    const double qd = rint(4.0 * r);
+    const double f = fma(-0.25, qd, r);
+    const int qi = (int)(((long long)qd) & 3);
+    const double t = f * (2.0 * kPi);
+    const double t2 = t * t;
+    double ps = -1.0 / 1307674368000.0;           // -1/15!
+    ps = fma(ps, t2, 1.0 / 6227020800.0);         // 1/13!
+    ps = fma(ps, t2, -1.0 / 39916800.0);          // -1/11!
+    ps = fma(ps, t2, 1.0 / 362880.0);             // 1/9!
+    ps = fma(ps, t2, -1.0 / 5040.0);              // -1/7!
+    ps = fma(ps, t2, 1.0 / 120.0);                // 1/5!
+    ps = fma(ps, t2, -1.0 / 6.0);                 // -1/3!
+    const double sn = fma(t * t2, ps, t);
+    double pc = 1.0 / 20922789888000.0;           // 1/16!
+    pc = fma(pc, t2, -1.0 / 87178291200.0);       // -1/14!
+    pc = fma(pc, t2, 1.0 / 479001600.0);          // 1/12!
+    pc = fma(pc, t2, -1.0 / 3628800.0);           // -1/10!
+    pc = fma(pc, t2, 1.0 / 40320.0);              // 1/8!
+    pc = fma(pc, t2, -1.0 / 720.0);               // -1/6!
+    pc = fma(pc, t2, 1.0 / 24.0);                 // 1/4!
+    pc = fma(pc, t2, -0.5);
+    const double cs = fma(t2, pc, 1.0);
+    const bool swap = qi & 1;
+    const double s0 = swap ? cs : sn;
+    const double c0 = swap ? sn : cs;
+    *s_out = (qi & 2) ? -s0 : s0;
+    *c_out = ((qi + 1) & 2) ? -c0 : c0;
+}
+
+__device__ __forceinline__ float fractf(float x) { return __builtin_amdgcn_fractf(x); }
+__device__ __forceinline__ float sin_rev(float x) { return __builtin_amdgcn_sinf(x); }
+__device__ __forceinline__ float cos_rev(float x) { return __builtin_amdgcn_cosf(x); }
+
+// Butterfly reduction of NV values held by every lane of a wave64: after it,
+// lane L holds (in v[0]) the wave-wide sum of value index L mod NV.  At each
+// stage a lane keeps one half of its values and swaps the other half with
+// the partner lane (lane ^ half).  Fixed order, so deterministic.
+template <int HALF, int NV, typename T>
+struct TransposeStage {
+    __device__ __forceinline__ static void run(T (&v)[NV], int lane) {
+        const bool upper = (lane & HALF) != 0;
+#pragma unroll
+        for (int i = 0; i < HALF; i++) {
+            const T send = upper ? v[i] : v[i + HALF];
+            const T keep = upper ? v[i + HALF] : v[i];
+            v[i] = keep + __shfl_xor(send, HALF, 64);
+        }
+        TransposeStage<HALF / 2, NV, T>::run(v, lane);
+    }
+};
+template <int NV, typename T>
+struct TransposeStage<0, NV, T> {
+    __device__ __forceinline__ static void run(T (&)[NV], int) {}
+};
+
+template <int NV, typename T>
+__device__ __forceinline__ void wave_transpose_reduce(T (&v)[NV], int lane) {
+    static_assert(NV >= 1 && NV <= 64 && (NV & (NV - 1)) == 0, "NV must be a power of two <= 64");
+    TransposeStage<NV / 2, NV, T>::run(v, lane);
+    // lanes L and L ^ NV, L ^ 2NV, ... hold partial sums of the same index
+#pragma unroll
+    for (int o = NV; o < 64; o <<= 1) v[0] += __shfl_xor(v[0], o, 64);
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// deterministic block sum (blockDim.x = kBlock) of one double; result valid in thread 0
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < (int)(blockDim.x >> 6); k++) r += sh[k];
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ double block_sum_r(double v, double *sh) { return block_sum(v, sh); }
+
+}  // namespace rbe2d

@@ -1,0 +1,560 @@
+// k-space half of RBE2D on gfx950: particle preparation, the N x P
+// structure-factor pass, the FP64 reduction/recalibration per k, the force
+// scatter and the energy reduction.
+//
+// Phases are carried in revolutions: k.r / 2pi = nx fx + ny fy + nz fz with
+// fx = x/Lx wrapped into [0,1), fy = y/Ly, fz = z/Lz_ext.
+//  * FP32 path: f is split into fh (fh_bits fraction bits, so n*fh is exact
+//    in FP32 for |n| < 2^(24-fh_bits)) and fl = f - fh; the phase
+//    fract(nx fxh) + nx fxl + ... keeps ~1e-8 revolution accuracy, and the
+//    hardware v_sin_f32/v_cos_f32 take revolutions directly.
+//  * FP64 path: plain FP64 phase and a quarter-turn-reduced Taylor sincos.
+#include "devmath.h"
+#include "rbe2d_internal.h"
+
+namespace rbe2d {
+
+// ---------------------------------------------------------------------------
+// 1. particle preparation
+// ---------------------------------------------------------------------------
+
+struct PrepArgs {
+    const double *pos, *q;
+    int64_t N, N_pad;
+    double Lx, Ly, Lz, H, scale_h;   // scale_h = 2^fh_bits
+    float4 *p32;
+    double4 *p64;
+    double *bpart;
+    int *err;
+};
+
+template <bool FP32>
+__global__ __launch_bounds__(kBlock) void k_prep(PrepArgs a) {
+    __shared__ double sh[kBlock / 64];
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    double sqz = 0.0, sq = 0.0, sq2 = 0.0;
+    if (i < a.N_pad) {
+        double fx = 0, fy = 0, fz = 0, qi = 0;
+        if (i < a.N) {
+            const double x = a.pos[3 * i], y = a.pos[3 * i + 1], z = a.pos[3 * i + 2];
+            qi = a.q[i];
+            if (!(z > 0.0 && z < a.H)) atomicOr(a.err, 1);
+            fx = x / a.Lx; fx -= floor(fx);
+            fy = y / a.Ly; fy -= floor(fy);
+            fz = z / a.Lz;
+            sqz = qi * z; sq = qi; sq2 = qi * qi;
+        }
+        if (FP32) {
+            const double hx = rint(fx * a.scale_h) / a.scale_h;
+            const double hy = rint(fy * a.scale_h) / a.scale_h;
+            const double hz = rint(fz * a.scale_h) / a.scale_h;
+            a.p32[2 * i] = make_float4((float)hx, (float)(fx - hx), (float)hy, (float)(fy - hy));
+            a.p32[2 * i + 1] = make_float4((float)hz, (float)(fz - hz), (float)qi, 0.0f);
+        } else {
+            a.p64[i] = make_double4(fx, fy, fz, qi);
+        }
+    }
+    double t0 = block_sum(sqz, sh);
+    double t1 = block_sum(sq, sh);
+    double t2 = block_sum(sq2, sh);
+    if (threadIdx.x == 0) {
+        a.bpart[4 * blockIdx.x] = t0;
+        a.bpart[4 * blockIdx.x + 1] = t1;
+        a.bpart[4 * blockIdx.x + 2] = t2;
+        a.bpart[4 * blockIdx.x + 3] = 0.0;
+    }
+}
+
+// scal layout: 0 mu=sum qz, 1 Q=sum q, 2 sum q^2, 3 muM, 4 fibc, 5 pot_ibc offset,
+//              6 dmuM/dg_top, 7 dmuM/dg_bot
+struct ScalArgs {
+    const double *bpart;
+    int nb;
+    double g1, cgam, dg1t, dg1b, dcgt, dcgb, twopi_over_V, pref;
+    double *scal;
+};
+
+__global__ __launch_bounds__(kBlock) void k_scalars(ScalArgs a) {
+    __shared__ double sh[kBlock / 64];
+    double v[3] = {0, 0, 0};
+    for (int b = threadIdx.x; b < a.nb; b += kBlock)
+        for (int c = 0; c < 3; c++) v[c] += a.bpart[4 * b + c];
+    double s0 = block_sum(v[0], sh), s1 = block_sum(v[1], sh), s2 = block_sum(v[2], sh);
+    if (threadIdx.x == 0) {
+        const double mu = s0, Q = s1;
+        const double muM = a.g1 * mu + a.cgam * Q;
+        a.scal[0] = mu;
+        a.scal[1] = Q;
+        a.scal[2] = s2;
+        a.scal[3] = muM;
+        a.scal[4] = -a.twopi_over_V * a.pref * (muM + a.g1 * mu);
+        a.scal[5] = a.twopi_over_V * a.pref * mu * a.cgam;
+        a.scal[6] = a.dg1t * mu + a.dcgt * Q;
+        a.scal[7] = a.dg1b * mu + a.dcgb * Q;
+    }
+}
+
+hipError_t launch_prep(rbe2d_ctx *h, int64_t N, int64_t N_pad, const double *pos, const double *q,
+                       hipStream_t s) {
+    PrepArgs a;
+    a.pos = pos; a.q = q; a.N = N; a.N_pad = N_pad;
+    a.Lx = h->p.Lx; a.Ly = h->p.Ly; a.Lz = h->Lz; a.H = h->p.H;
+    a.scale_h = ldexp(1.0, h->fh_bits);
+    a.p32 = h->w.p32; a.p64 = h->w.p64; a.bpart = h->w.bpart; a.err = h->w.err;
+    const int nb = (int)((N_pad + kBlock - 1) / kBlock);
+    prof_begin(h, 0, s);
+    if (nb > 0) {
+        if (h->p.precision == RBE2D_PREC_FP32_PHASE)
+            hipLaunchKernelGGL(k_prep<true>, dim3(nb), dim3(kBlock), 0, s, a);
+        else
+            hipLaunchKernelGGL(k_prep<false>, dim3(nb), dim3(kBlock), 0, s, a);
+    }
+    ScalArgs b;
+    b.bpart = h->w.bpart; b.nb = nb; b.g1 = h->g1; b.cgam = h->cgam;
+    b.dg1t = h->dg1[0]; b.dg1b = h->dg1[1]; b.dcgt = h->dcgam[0]; b.dcgb = h->dcgam[1];
+    b.twopi_over_V = 2.0 * kPi / h->V; b.pref = h->pref; b.scal = h->w.scal;
+    hipLaunchKernelGGL(k_scalars, dim3(1), dim3(kBlock), 0, s, b);
+    prof_end(h, 0, s);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// 2. k-vector table (nx, ny, nz as floats / doubles, padded with zeros)
+// ---------------------------------------------------------------------------
+
+__global__ void k_ktable(const int32_t *kset, int P, int P_pad, float4 *kn32, double4 *kn64) {
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= P_pad) return;
+    int nx = 0, ny = 0, nz = 0;
+    if (l < P) { nx = kset[3 * l]; ny = kset[3 * l + 1]; nz = kset[3 * l + 2]; }
+    kn32[l] = make_float4((float)nx, (float)ny, (float)nz, 0.0f);
+    kn64[l] = make_double4((double)nx, (double)ny, (double)nz, 0.0);
+}
+
+// ---------------------------------------------------------------------------
+// 3. structure-factor pass: per (particle tile, k-chunk) partial sums of
+//    rho(k) = sum q e^{2 pi i phi} and rhohat(k) = sum q e^{2 pi i phihat}
+//    with phi = phi_xy + phi_z, phihat = phi_xy - phi_z.
+//    Lanes own particles, the k-chunk is wave-uniform (scalar loads).
+// ---------------------------------------------------------------------------
+
+template <int KC>
+__global__ __launch_bounds__(kBlock) void k_sf32(const float4 *__restrict__ p32,
+                                                 const float4 *__restrict__ kn, int per_thread,
+                                                 int P_pad, float *__restrict__ part) {
+    __shared__ float sh[kBlock / 64][64];
+    const int kc0 = blockIdx.y * KC;
+    float acc[4 * KC];
+#pragma unroll
+    for (int v = 0; v < 4 * KC; v++) acc[v] = 0.0f;
+    const int64_t base = (int64_t)blockIdx.x * kBlock * per_thread + threadIdx.x;
+    for (int m = 0; m < per_thread; m++) {
+        const int64_t i = base + (int64_t)m * kBlock;
+        const float4 a = p32[2 * i];
+        const float4 b = p32[2 * i + 1];
+#pragma unroll
+        for (int kk = 0; kk < KC; kk++) {
+            const float4 n = kn[kc0 + kk];
+            float pxy = fractf(n.x * a.x) + fractf(n.y * a.z);
+            pxy = fmaf(n.x, a.y, pxy);
+            pxy = fmaf(n.y, a.w, pxy);
+            const float pz = fmaf(n.z, b.y, fractf(n.z * b.x));
+            const float ph = pxy + pz, phh = pxy - pz;
+            acc[4 * kk + 0] = fmaf(b.z, cos_rev(ph), acc[4 * kk + 0]);
+            acc[4 * kk + 1] = fmaf(b.z, sin_rev(ph), acc[4 * kk + 1]);
+            acc[4 * kk + 2] = fmaf(b.z, cos_rev(phh), acc[4 * kk + 2]);
+            acc[4 * kk + 3] = fmaf(b.z, sin_rev(phh), acc[4 * kk + 3]);
+        }
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    wave_transpose_reduce<4 * KC>(acc, lane);
+    sh[wid][lane] = acc[0];
+    __syncthreads();
+    if (threadIdx.x < 4 * KC) {
+        float t = 0.0f;
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; w++) t += sh[w][threadIdx.x];
+        part[((int64_t)blockIdx.x * P_pad + kc0) * 4 + threadIdx.x] = t;
+    }
+}
+
+template <int KC>
+__global__ __launch_bounds__(kBlock) void k_sf64(const double4 *__restrict__ p64,
+                                                 const double4 *__restrict__ kn, int per_thread,
+                                                 int P_pad, double *__restrict__ part) {
+    __shared__ double sh[kBlock / 64][4 * KC];
+    const int kc0 = blockIdx.y * KC;
+    double acc[4 * KC];
+#pragma unroll
+    for (int v = 0; v < 4 * KC; v++) acc[v] = 0.0;
+    const int64_t base = (int64_t)blockIdx.x * kBlock * per_thread + threadIdx.x;
+    for (int m = 0; m < per_thread; m++) {
+        const int64_t i = base + (int64_t)m * kBlock;
+        const double4 a = p64[i];
+#pragma unroll
+        for (int kk = 0; kk < KC; kk++) {
+            const double4 n = kn[kc0 + kk];
+            const double pxy = fma(n.y, a.y, n.x * a.x);
+            const double pz = n.z * a.z;
+            double c1, s1, c2, s2;
+            sincos_rev64(pxy + pz, &s1, &c1);
+            sincos_rev64(pxy - pz, &s2, &c2);
+            acc[4 * kk + 0] = fma(a.w, c1, acc[4 * kk + 0]);
+            acc[4 * kk + 1] = fma(a.w, s1, acc[4 * kk + 1]);
+            acc[4 * kk + 2] = fma(a.w, c2, acc[4 * kk + 2]);
+            acc[4 * kk + 3] = fma(a.w, s2, acc[4 * kk + 3]);
+        }
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    wave_transpose_reduce<4 * KC>(acc, lane);
+    if (lane < 4 * KC) sh[wid][lane] = acc[0];
+    __syncthreads();
+    if (threadIdx.x < 4 * KC) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; w++) t += sh[w][threadIdx.x];
+        part[((int64_t)blockIdx.x * P_pad + kc0) * 4 + threadIdx.x] = t;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 4. reduce over tiles (FP64, fixed order) and recalibrate (Sec. 3.4):
+//    rho^M = (1 + Y_even) rho + Y_odd rhohat,
+//    A = rho^M + (1 + conj Y_even) rho,  B = conj(Y_odd) rho,
+//    c = 2 pi S pref / (V P |k|^2),  e = c Re(rho conj rho^M).
+//    One wave per k; lanes split the tiles and the image orders.
+// ---------------------------------------------------------------------------
+
+struct AssembleArgs {
+    const void *part;
+    int fp32_part;
+    int n_tiles, P, P_pad, M;
+    const int32_t *kset;
+    const ImgTable *img;      // image weights and exponents (index l-1)
+    double g_top, g_bot;
+    double Lx, Ly, Lz, H, cfac;   // cfac = 2 pi S pref / (V P)
+    double *krec;
+    float4 *kf32;
+};
+
+__device__ __forceinline__ double dmono(int e_self, double g_self, int e_other, double g_other) {
+    // d/dg_self of g_self^e_self g_other^e_other
+    if (e_self == 0) return 0.0;
+    double r = (double)e_self;
+    for (int i = 0; i < e_self - 1; i++) r *= g_self;
+    for (int i = 0; i < e_other; i++) r *= g_other;
+    return r;
+}
+
+__global__ __launch_bounds__(64) void k_assemble(AssembleArgs a) {
+    const int l = blockIdx.x;
+    const int lane = threadIdx.x;
+    double s[4] = {0, 0, 0, 0};
+    for (int t = lane; t < a.n_tiles; t += 64) {
+        const int64_t o = ((int64_t)t * a.P_pad + l) * 4;
+        if (a.fp32_part) {
+            const float *p = (const float *)a.part;
+            for (int c = 0; c < 4; c++) s[c] += (double)p[o + c];
+        } else {
+            const double *p = (const double *)a.part;
+            for (int c = 0; c < 4; c++) s[c] += p[o + c];
+        }
+    }
+    for (int c = 0; c < 4; c++) s[c] = wave_sum(s[c]);
+    // Y_odd, Y_even and their gamma derivatives; lane handles order o = lane+1, lane+65, ...
+    const int nx = a.kset[3 * l], ny = a.kset[3 * l + 1], nz = a.kset[3 * l + 2];
+    const double rev_per_H = (double)nz * a.H / a.Lz;   // kz H / (2 pi)
+    double y[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};  // Yo, Ye, dYo/dt, dYe/dt, dYo/db, dYe/db
+    for (int o = lane + 1; o <= a.M; o += 64) {
+        const double gpl = a.img->gp[o - 1], gml = a.img->gm[o - 1];
+        double mp, mm;   // multiples of kz H in the exponents of the + and - terms
+        int slot;
+        if (o & 1) { mp = (double)(o + 1); mm = -(double)(o - 1); slot = 0; }
+        else       { mp = (double)o;       mm = -(double)o;       slot = 2; }
+        double sp, cp, sm, cm;
+        sincos_rev64(mp * rev_per_H, &sp, &cp);
+        sincos_rev64(mm * rev_per_H, &sm, &cm);
+        y[slot] += gpl * cp + gml * cm;
+        y[slot + 1] += gpl * sp + gml * sm;
+        const ImgTable &it = *a.img;
+        const double dpt = dmono(it.ea_p[o - 1], a.g_top, it.eb_p[o - 1], a.g_bot);
+        const double dmt = dmono(it.ea_m[o - 1], a.g_top, it.eb_m[o - 1], a.g_bot);
+        const double dpb = dmono(it.eb_p[o - 1], a.g_bot, it.ea_p[o - 1], a.g_top);
+        const double dmb = dmono(it.eb_m[o - 1], a.g_bot, it.ea_m[o - 1], a.g_top);
+        y[4 + slot] += dpt * cp + dmt * cm;
+        y[5 + slot] += dpt * sp + dmt * sm;
+        y[8 + slot] += dpb * cp + dmb * cm;
+        y[9 + slot] += dpb * sp + dmb * sm;
+    }
+    for (int c = 0; c < 12; c++) y[c] = wave_sum(y[c]);
+    if (lane != 0) return;
+    const double rr = s[0], ri = s[1], hr = s[2], hi = s[3];
+    const double kx = 2.0 * kPi * nx / a.Lx, ky = 2.0 * kPi * ny / a.Ly, kz = 2.0 * kPi * nz / a.Lz;
+    const double k2 = kx * kx + ky * ky + kz * kz;
+    const double c = a.cfac / k2;
+    // rho^M = (1 + Ye) rho + Yo rhohat
+    const double er = 1.0 + y[2], ei = y[3];
+    const double mr = er * rr - ei * ri + y[0] * hr - y[1] * hi;
+    const double mi = er * ri + ei * rr + y[0] * hi + y[1] * hr;
+    // A = rho^M + (1 + conj Ye) rho ; B = conj(Yo) rho
+    const double Ar = mr + er * rr + ei * ri;
+    const double Ai = mi + er * ri - ei * rr;
+    const double Br = y[0] * rr + y[1] * ri;
+    const double Bi = y[0] * ri - y[1] * rr;
+    const double e = c * (rr * mr + ri * mi);
+    // d e / d gamma = c Re(rho conj(dYe rho + dYo rhohat))
+    double de[2];
+    for (int w = 0; w < 2; w++) {
+        const double *d = y + 4 + 4 * w;
+        const double tr = d[2] * rr - d[3] * ri + d[0] * hr - d[1] * hi;
+        const double ti = d[2] * ri + d[3] * rr + d[0] * hi + d[1] * hr;
+        de[w] = c * (rr * tr + ri * ti);
+    }
+    double *rec = a.krec + (int64_t)l * kKRec;
+    rec[0] = kx; rec[1] = ky; rec[2] = kz;
+    rec[3] = c * Ar; rec[4] = c * Ai; rec[5] = c * Br; rec[6] = c * Bi;
+    rec[7] = e; rec[8] = de[0]; rec[9] = de[1];
+    rec[10] = nx; rec[11] = ny; rec[12] = nz;
+    rec[13] = rr; rec[14] = ri; rec[15] = 0.0;
+    a.kf32[2 * l] = make_float4((float)kx, (float)ky, (float)kz, 0.0f);
+    a.kf32[2 * l + 1] = make_float4((float)(c * Ar), (float)(c * Ai), (float)(c * Br), (float)(c * Bi));
+}
+
+int choose_tile(int64_t N, int n_kchunks) {
+    // particles per thread: fill the chip with >= ~4096 blocks if N allows,
+    // but keep tiles long enough to amortise the block reduction.
+    int per = kMaxTileThreads;
+    while (per > 1) {
+        const int64_t tiles = (N + (int64_t)kBlock * per - 1) / ((int64_t)kBlock * per);
+        if (tiles * n_kchunks >= 4096) break;
+        per >>= 1;
+    }
+    return per;
+}
+
+hipError_t launch_kcoef_sf(rbe2d_ctx *h, int64_t N_pad, int per, hipStream_t s) {
+    const bool fp32 = h->p.precision == RBE2D_PREC_FP32_PHASE;
+    hipLaunchKernelGGL(k_ktable, dim3((h->P_pad + 63) / 64), dim3(64), 0, s, h->w.kset, h->P,
+                       h->P_pad, h->w.kn32, h->w.kn64);
+    const int tile = kBlock * per;
+    const int n_tiles = (int)((N_pad + tile - 1) / tile);
+    prof_begin(h, 1, s);
+    if (n_tiles > 0) {
+        if (fp32) {
+            dim3 g(n_tiles, h->P_pad / kKChunk32);
+            hipLaunchKernelGGL(k_sf32<kKChunk32>, g, dim3(kBlock), 0, s, h->w.p32, h->w.kn32, per,
+                               h->P_pad, (float *)h->w.sfpart);
+        } else {
+            dim3 g(n_tiles, h->P_pad / kKChunk64);
+            hipLaunchKernelGGL(k_sf64<kKChunk64>, g, dim3(kBlock), 0, s, h->w.p64, h->w.kn64, per,
+                               h->P_pad, (double *)h->w.sfpart);
+        }
+    }
+    prof_end(h, 1, s);
+    AssembleArgs a;
+    a.part = h->w.sfpart; a.fp32_part = fp32; a.n_tiles = n_tiles; a.P = h->P; a.P_pad = h->P_pad;
+    a.M = h->M; a.kset = h->w.kset;
+    a.img = h->w.img;
+    a.g_top = h->p.gamma_top; a.g_bot = h->p.gamma_bot;
+    a.Lx = h->p.Lx; a.Ly = h->p.Ly; a.Lz = h->Lz; a.H = h->p.H;
+    a.cfac = 2.0 * kPi * h->S * h->pref / (h->V * h->P);
+    a.krec = h->w.krec; a.kf32 = h->w.kf32;
+    prof_begin(h, 2, s);
+    hipLaunchKernelGGL(k_assemble, dim3(h->P), dim3(64), 0, s, a);
+    prof_end(h, 2, s);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// 5. force scatter: one thread per particle, all k (or a k-range) uniform:
+//    F_i = -q_i sum_l [k_l Im(e^{-i phi} cA_l) + khat_l Im(e^{-i phihat} cB_l)]
+//    pot_i = sum_l [Re(e^{-i phi} cA_l) + Re(e^{-i phihat} cB_l)]   (dE_k/dq_i)
+// ---------------------------------------------------------------------------
+
+struct ForceArgs {
+    const float4 *p32;
+    const double4 *p64;
+    const float4 *kn32;
+    const double4 *kn64;
+    const float4 *kf32;
+    const double *krec;
+    int64_t N;
+    int P, k_per_split;
+    const double *pos;       // for the IBC potential (z_i)
+    const double *q;
+    const double *scal;
+    const double4 *freal;    // added when add_real
+    double *fpart;           // [split][N][4] when splitting
+    double *F;               // final output (N x 3) when not splitting
+    double *dEdq;            // final dE/dq (N) when want_pot and not splitting
+    const double *gE;        // scale of the backward outputs (device scalar) or null
+    double alpha_self;       // -2 alpha pref / sqrt(pi): d E_self / d q_i = alpha_self q_i
+    int accumulate, add_real, want_pot, do_kspace, do_ibc, split;
+};
+
+__device__ __forceinline__ void finish_particle(const ForceArgs &a, int64_t i, double fx,
+                                                double fy, double fz, double pot) {
+    const double qi = a.q[i];
+    double Fx = 0, Fy = 0, Fz = 0, ph = 0;
+    if (a.do_kspace) {
+        Fx = -qi * fx; Fy = -qi * fy; Fz = -qi * fz;
+        ph = pot + a.alpha_self * qi;
+    }
+    if (a.do_ibc) {
+        Fz += qi * a.scal[4];
+        ph += -a.scal[4] * a.pos[3 * i + 2] + a.scal[5];
+    }
+    if (a.add_real) {
+        const double4 r = a.freal[i];
+        Fx += r.x; Fy += r.y; Fz += r.z; ph += r.w;
+    }
+    if (a.want_pot) {
+        // backward: dL/dr = -gE F, dL/dq = gE phi
+        const double g = a.gE ? *a.gE : 1.0;
+        if (a.F) {
+            a.F[3 * i] = -g * Fx; a.F[3 * i + 1] = -g * Fy; a.F[3 * i + 2] = -g * Fz;
+        }
+        if (a.dEdq) a.dEdq[i] = g * ph;
+        return;
+    }
+    if (a.accumulate) {
+        a.F[3 * i] += Fx; a.F[3 * i + 1] += Fy; a.F[3 * i + 2] += Fz;
+    } else {
+        a.F[3 * i] = Fx; a.F[3 * i + 1] = Fy; a.F[3 * i + 2] = Fz;
+    }
+}
+
+template <bool WANT_POT>
+__global__ __launch_bounds__(kBlock) void k_force32(ForceArgs a) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= a.N) return;
+    const float4 pa = a.p32[2 * i];
+    const float4 pb = a.p32[2 * i + 1];
+    const int l0 = blockIdx.y * a.k_per_split;
+    const int l1 = min(a.P, l0 + a.k_per_split);
+    double Fx = 0, Fy = 0, Fz = 0, Pt = 0;
+    if (a.do_kspace) {
+        for (int c0 = l0; c0 < l1; c0 += 64) {
+            const int c1 = min(l1, c0 + 64);
+            float fx = 0, fy = 0, fz = 0, pt = 0;
+            for (int l = c0; l < c1; l++) {
+                const float4 n = a.kn32[l];
+                const float4 kv = a.kf32[2 * l];
+                const float4 ab = a.kf32[2 * l + 1];
+                float pxy = fractf(n.x * pa.x) + fractf(n.y * pa.z);
+                pxy = fmaf(n.x, pa.y, pxy);
+                pxy = fmaf(n.y, pa.w, pxy);
+                const float pz = fmaf(n.z, pb.y, fractf(n.z * pb.x));
+                const float ph = pxy + pz, phh = pxy - pz;
+                const float c1f = cos_rev(ph), s1f = sin_rev(ph);
+                const float c2f = cos_rev(phh), s2f = sin_rev(phh);
+                const float X = fmaf(ab.y, c1f, -ab.x * s1f);   // Im(e^{-i ph} cA)
+                const float Y = fmaf(ab.w, c2f, -ab.z * s2f);   // Im(e^{-i phh} cB)
+                const float sp = X + Y, sm = X - Y;
+                fx = fmaf(kv.x, sp, fx);
+                fy = fmaf(kv.y, sp, fy);
+                fz = fmaf(kv.z, sm, fz);
+                if (WANT_POT) {
+                    pt = fmaf(ab.x, c1f, pt); pt = fmaf(ab.y, s1f, pt);
+                    pt = fmaf(ab.z, c2f, pt); pt = fmaf(ab.w, s2f, pt);
+                }
+            }
+            Fx += fx; Fy += fy; Fz += fz; Pt += pt;
+        }
+    }
+    if (a.split) {
+        double *o = a.fpart + ((int64_t)blockIdx.y * a.N + i) * 4;
+        o[0] = Fx; o[1] = Fy; o[2] = Fz; o[3] = Pt;
+    } else {
+        finish_particle(a, i, Fx, Fy, Fz, Pt);
+    }
+}
+
+template <bool WANT_POT>
+__global__ __launch_bounds__(kBlock) void k_force64(ForceArgs a) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= a.N) return;
+    const double4 p = a.p64[i];
+    const int l0 = blockIdx.y * a.k_per_split;
+    const int l1 = min(a.P, l0 + a.k_per_split);
+    double fx = 0, fy = 0, fz = 0, pt = 0;
+    if (a.do_kspace) {
+        for (int l = l0; l < l1; l++) {
+            const double4 n = a.kn64[l];
+            const double *rec = a.krec + (int64_t)l * kKRec;
+            const double pxy = fma(n.y, p.y, n.x * p.x);
+            const double pz = n.z * p.z;
+            double c1, s1, c2, s2;
+            sincos_rev64(pxy + pz, &s1, &c1);
+            sincos_rev64(pxy - pz, &s2, &c2);
+            const double X = fma(rec[4], c1, -rec[3] * s1);
+            const double Y = fma(rec[6], c2, -rec[5] * s2);
+            const double sp = X + Y, sm = X - Y;
+            fx = fma(rec[0], sp, fx);
+            fy = fma(rec[1], sp, fy);
+            fz = fma(rec[2], sm, fz);
+            if (WANT_POT) {
+                pt = fma(rec[3], c1, pt); pt = fma(rec[4], s1, pt);
+                pt = fma(rec[5], c2, pt); pt = fma(rec[6], s2, pt);
+            }
+        }
+    }
+    if (a.split) {
+        double *o = a.fpart + ((int64_t)blockIdx.y * a.N + i) * 4;
+        o[0] = fx; o[1] = fy; o[2] = fz; o[3] = pt;
+    } else {
+        finish_particle(a, i, fx, fy, fz, pt);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_force_combine(ForceArgs a, int nsplit) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= a.N) return;
+    double fx = 0, fy = 0, fz = 0, pt = 0;
+    for (int sidx = 0; sidx < nsplit; sidx++) {
+        const double *o = a.fpart + ((int64_t)sidx * a.N + i) * 4;
+        fx += o[0]; fy += o[1]; fz += o[2]; pt += o[3];
+    }
+    finish_particle(a, i, fx, fy, fz, pt);
+}
+
+int choose_ksplit(int64_t N, int P) {
+    // split the k-loop across blocks when there are too few particles to fill the chip
+    const int64_t nb = (N + kBlock - 1) / kBlock;
+    int split = 1;
+    while (nb * split < 2048 && split * 2 <= 64 && (P + split * 2 - 1) / (split * 2) >= 8) split *= 2;
+    return split;
+}
+
+hipError_t launch_kforce(rbe2d_ctx *h, int64_t N, const double *pos, const double *q, double *F,
+                         double *dEdq, uint32_t flags, bool accumulate, bool want_pot,
+                         bool add_real, const double *gE, hipStream_t s) {
+    if (N == 0) return hipSuccess;
+    ForceArgs a;
+    a.p32 = h->w.p32; a.p64 = h->w.p64; a.kn32 = h->w.kn32; a.kn64 = h->w.kn64;
+    a.kf32 = h->w.kf32; a.krec = h->w.krec; a.N = N; a.P = h->P;
+    a.pos = pos; a.q = q; a.scal = h->w.scal; a.freal = h->w.freal;
+    a.fpart = h->w.fpart; a.F = F; a.dEdq = dEdq; a.gE = gE;
+    a.alpha_self = -2.0 * h->p.alpha * h->pref / sqrt(kPi);
+    a.accumulate = accumulate; a.add_real = add_real; a.want_pot = want_pot;
+    a.do_kspace = (flags & RBE2D_KSPACE) != 0; a.do_ibc = (flags & RBE2D_IBC) != 0;
+    const int split = a.do_kspace ? choose_ksplit(N, h->P) : 1;
+    a.k_per_split = (h->P + split - 1) / split;
+    a.split = split > 1;
+    const int nb = (int)((N + kBlock - 1) / kBlock);
+    const bool fp32 = h->p.precision == RBE2D_PREC_FP32_PHASE;
+    dim3 g(nb, split);
+    prof_begin(h, 5, s);
+    if (fp32) {
+        if (want_pot) hipLaunchKernelGGL(k_force32<true>, g, dim3(kBlock), 0, s, a);
+        else hipLaunchKernelGGL(k_force32<false>, g, dim3(kBlock), 0, s, a);
+    } else {
+        if (want_pot) hipLaunchKernelGGL(k_force64<true>, g, dim3(kBlock), 0, s, a);
+        else hipLaunchKernelGGL(k_force64<false>, g, dim3(kBlock), 0, s, a);
+    }
+    if (a.split) hipLaunchKernelGGL(k_force_combine, dim3(nb), dim3(kBlock), 0, s, a, split);
+    prof_end(h, 5, s);
+    return hipGetLastError();
+}
+
+}  // namespace rbe2d

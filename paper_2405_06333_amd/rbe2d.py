@@ -1,0 +1,260 @@
+"""Python binding of librbe2d.so (ctypes): argument marshalling only.
+
+Every step of the RBE2D evaluation runs in the HIP kernels of the library;
+this module converts torch tensors into device pointers and the current
+torch stream into a hipStream_t.  There is no CPU fallback: if the library
+is not built, importing a handle raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librbe2d.so")
+
+RBE2D_OK, RBE2D_E_INVAL, RBE2D_E_NOMEM, RBE2D_E_HIP, RBE2D_E_STATE, RBE2D_E_RANGE = 0, -1, -2, -3, -4, -5
+PREC_FP64, PREC_FP32_PHASE = 0, 1
+KSPACE, REAL, IBC, ALL, ACCUMULATE = 1, 2, 4, 7, 16
+
+# every symbol include/rbe2d.h declares
+EXPORTS = ("rbe2d_create", "rbe2d_destroy", "rbe2d_query", "rbe2d_draw_kset", "rbe2d_set_kset",
+           "rbe2d_sample_kset", "rbe2d_get_kset", "rbe2d_forces", "rbe2d_energy",
+           "rbe2d_energy_backward", "rbe2d_md_run", "rbe2d_profile_enable", "rbe2d_profile_read",
+           "rbe2d_check", "rbe2d_last_error")
+PROF_SLOTS = ("prep", "sf_pass", "assemble", "cell_build", "real_pairs", "force_scatter", "energy",
+              "integrator", "ksample")
+
+
+class RBE2DError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"rbe2d error {status}: {msg}")
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("Lx", ctypes.c_double), ("Ly", ctypes.c_double), ("H", ctypes.c_double),
+                ("Lz_ext", ctypes.c_double), ("eps_lz", ctypes.c_double),
+                ("gamma_top", ctypes.c_double), ("gamma_bot", ctypes.c_double),
+                ("alpha", ctypes.c_double), ("r_c", ctypes.c_double),
+                ("P", ctypes.c_int32), ("M", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("n_max", ctypes.c_int64),
+                ("coulomb_prefactor", ctypes.c_double)]
+
+
+_lib = None
+_vp = ctypes.c_void_p
+
+
+def lib():
+    """Load librbe2d.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2405_06333_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        L.rbe2d_create.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(_vp)]
+        L.rbe2d_destroy.argtypes = [_vp]
+        L.rbe2d_destroy.restype = None
+        L.rbe2d_query.argtypes = [_vp, _vp, _vp, _vp]
+        L.rbe2d_draw_kset.argtypes = [ctypes.POINTER(Params), ctypes.c_uint64, ctypes.c_uint64, _vp]
+        L.rbe2d_set_kset.argtypes = [_vp, _vp, ctypes.c_int, _vp]
+        L.rbe2d_sample_kset.argtypes = [_vp, ctypes.c_uint64, ctypes.c_uint64, _vp]
+        L.rbe2d_get_kset.argtypes = [_vp, _vp, _vp]
+        L.rbe2d_forces.argtypes = [_vp, ctypes.c_int64, _vp, _vp, _vp, _vp, ctypes.c_uint32, _vp]
+        L.rbe2d_energy.argtypes = [_vp, ctypes.c_int64, _vp, _vp, _vp, _vp]
+        L.rbe2d_energy_backward.argtypes = [_vp, ctypes.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+        L.rbe2d_md_run.argtypes = [_vp, ctypes.c_int64, _vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_double,
+                                   ctypes.c_double, ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32, _vp]
+        L.rbe2d_profile_enable.argtypes = [_vp, ctypes.c_int32]
+        L.rbe2d_profile_read.argtypes = [_vp, _vp, _vp, ctypes.c_int32]
+        L.rbe2d_check.argtypes = [_vp, _vp]
+        L.rbe2d_last_error.argtypes = [_vp]
+        L.rbe2d_last_error.restype = ctypes.c_char_p
+        for name in EXPORTS:
+            if name != "rbe2d_destroy" and name != "rbe2d_last_error":
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def make_params(Lx, Ly, H, gamma_top, gamma_bot, alpha, r_c, P, M, precision="fp64", n_max=0,
+                Lz_ext=0.0, eps_lz=1e-6, coulomb_prefactor=1.0) -> Params:
+    prec = {"fp64": PREC_FP64, "fp32": PREC_FP32_PHASE, PREC_FP64: PREC_FP64,
+            PREC_FP32_PHASE: PREC_FP32_PHASE}[precision]
+    return Params(float(Lx), float(Ly), float(H), float(Lz_ext), float(eps_lz), float(gamma_top),
+                  float(gamma_bot), float(alpha), float(r_c), int(P), int(M), prec, 0, int(n_max),
+                  float(coulomb_prefactor))
+
+
+def draw_kset(params: Params, seed: int, stream_id: int = 0) -> np.ndarray:
+    """Host k-sampler of the library (P x 3 int32)."""
+    out = np.zeros((params.P, 3), dtype=np.int32)
+    st = lib().rbe2d_draw_kset(ctypes.byref(params), ctypes.c_uint64(seed & (2**64 - 1)),
+                               ctypes.c_uint64(stream_id & (2**64 - 1)), out.ctypes.data)
+    if st != RBE2D_OK:
+        raise RBE2DError(st, lib().rbe2d_last_error(None).decode())
+    return out
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dptr(t, dtype=None, shape=None, name="tensor"):
+    import torch
+    if t is None:
+        return None
+    if not (isinstance(t, torch.Tensor) and t.is_cuda):
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Slab:
+    """One dielectrically confined slab: a handle of librbe2d with its workspaces."""
+
+    def __init__(self, Lx, Ly, H, gamma_top, gamma_bot, alpha, r_c, P, M, precision="fp64",
+                 n_max=0, Lz_ext=0.0, eps_lz=1e-6, coulomb_prefactor=1.0):
+        self.params = make_params(Lx, Ly, H, gamma_top, gamma_bot, alpha, r_c, P, M, precision, n_max,
+                                  Lz_ext, eps_lz, coulomb_prefactor)
+        self._h = ctypes.c_void_p()
+        st = lib().rbe2d_create(ctypes.byref(self.params), ctypes.byref(self._h))
+        if st != RBE2D_OK:
+            raise RBE2DError(st, lib().rbe2d_last_error(None).decode())
+        Lz, V, S = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        lib().rbe2d_query(self._h, ctypes.byref(Lz), ctypes.byref(V), ctypes.byref(S))
+        self.Lz_ext, self.V, self.S = Lz.value, V.value, S.value
+        self.P = int(P)
+        self.n_max = int(n_max)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.rbe2d_destroy(h)
+            self._h = None
+
+    def close(self):
+        self.__del__()
+
+    def _ok(self, st):
+        if st != RBE2D_OK:
+            raise RBE2DError(st, lib().rbe2d_last_error(self._h).decode())
+
+    @property
+    def handle(self):
+        return self._h
+
+    # k-set -----------------------------------------------------------------
+    def draw_kset(self, seed, stream_id=0):
+        return draw_kset(self.params, seed, stream_id)
+
+    def set_kset(self, n):
+        import torch
+        if isinstance(n, torch.Tensor) and n.is_cuda:
+            self._ok(lib().rbe2d_set_kset(self._h, _dptr(n, torch.int32, (self.P, 3), "n"), 1, _stream()))
+        else:
+            a = np.ascontiguousarray(n, dtype=np.int32).reshape(self.P, 3)
+            self._ok(lib().rbe2d_set_kset(self._h, ctypes.c_void_p(a.ctypes.data), 0, _stream()))
+
+    def sample_kset(self, seed, stream_id=0):
+        self._ok(lib().rbe2d_sample_kset(self._h, ctypes.c_uint64(seed), ctypes.c_uint64(stream_id), _stream()))
+
+    def get_kset(self):
+        out = np.zeros((self.P, 3), dtype=np.int32)
+        self._ok(lib().rbe2d_get_kset(self._h, ctypes.c_void_p(out.ctypes.data), _stream()))
+        return out
+
+    # evaluation ------------------------------------------------------------
+    def forces(self, pos, q, flags=ALL, want_energy=False, out=None, energy_out=None):
+        import torch
+        N = int(q.shape[0])
+        P_ = _dptr(pos, torch.float64, (N, 3), "pos")
+        Q_ = _dptr(q, torch.float64, (N,), "q")
+        F = torch.empty((N, 3), dtype=torch.float64, device=pos.device) if out is None else out
+        E = None
+        if want_energy:
+            E = torch.empty(5, dtype=torch.float64, device=pos.device) if energy_out is None else energy_out
+        self._ok(lib().rbe2d_forces(self._h, N, P_, Q_, _dptr(F, torch.float64, (N, 3), "F"),
+                                    _dptr(E, torch.float64, (5,), "energy"), flags, _stream()))
+        return (F, E) if want_energy else F
+
+    def energy(self, pos, q, out=None):
+        import torch
+        N = int(q.shape[0])
+        E = torch.empty(5, dtype=torch.float64, device=pos.device) if out is None else out
+        self._ok(lib().rbe2d_energy(self._h, N, _dptr(pos, torch.float64, (N, 3), "pos"),
+                                    _dptr(q, torch.float64, (N,), "q"),
+                                    _dptr(E, torch.float64, (5,), "energy"), _stream()))
+        return E
+
+    def energy_backward(self, pos, q, gE, want=(True, True, True)):
+        import torch
+        N = int(q.shape[0])
+        dev = pos.device
+        dr = torch.empty((N, 3), dtype=torch.float64, device=dev) if want[0] else None
+        dq = torch.empty((N,), dtype=torch.float64, device=dev) if want[1] else None
+        dg = torch.empty((2,), dtype=torch.float64, device=dev) if want[2] else None
+        self._ok(lib().rbe2d_energy_backward(
+            self._h, N, _dptr(pos, torch.float64, (N, 3), "pos"), _dptr(q, torch.float64, (N,), "q"),
+            _dptr(gE, torch.float64, (), "gE"), _dptr(dr, torch.float64, (N, 3), "dEdr"),
+            _dptr(dq, torch.float64, (N,), "dEdq"), _dptr(dg, torch.float64, (2,), "dEdgamma"), _stream()))
+        return dr, dq, dg
+
+    def md_run(self, pos, vel, q, F, dt, z_lo, z_hi, seed, step0, n_steps):
+        import torch
+        N = int(q.shape[0])
+        self._ok(lib().rbe2d_md_run(
+            self._h, N, _dptr(pos, torch.float64, (N, 3), "pos"), _dptr(vel, torch.float64, (N, 3), "vel"),
+            _dptr(q, torch.float64, (N,), "q"), _dptr(F, torch.float64, (N, 3), "F"), float(dt),
+            float(z_lo), float(z_hi), ctypes.c_uint64(seed), int(step0), int(n_steps), _stream()))
+
+    def profile_enable(self, n_events):
+        self._ok(lib().rbe2d_profile_enable(self._h, int(n_events)))
+
+    def profile_read(self):
+        """{kernel class: (total ms, launches)} since the last read."""
+        n = len(PROF_SLOTS)
+        ms = np.zeros(n)
+        cnt = np.zeros(n, dtype=np.int64)
+        self._ok(lib().rbe2d_profile_read(self._h, ctypes.c_void_p(ms.ctypes.data),
+                                          ctypes.c_void_p(cnt.ctypes.data), n))
+        return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(PROF_SLOTS)}
+
+    def check(self):
+        self._ok(lib().rbe2d_check(self._h, _stream()))
+
+
+def energy_function():
+    """torch.autograd.Function whose forward returns the RBE2D energy
+    (total) and whose backward runs the library's adjoint kernels."""
+    import torch
+
+    class RBE2DEnergy(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, pos, q, gamma, slab):
+            g = gamma.detach().cpu().tolist()
+            if abs(g[0] - slab.params.gamma_top) > 0 or abs(g[1] - slab.params.gamma_bot) > 0:
+                raise ValueError("gamma must equal the slab's (gamma_top, gamma_bot)")
+            E = slab.energy(pos.detach(), q.detach())
+            ctx.slab = slab
+            ctx.save_for_backward(pos, q)
+            return E[0]
+
+        @staticmethod
+        def backward(ctx, gE):
+            pos, q = ctx.saved_tensors
+            gE = gE.detach().to(torch.float64).contiguous().reshape(())
+            want = ctx.needs_input_grad[:3]
+            dr, dq, dg = ctx.slab.energy_backward(pos.detach(), q.detach(), gE, want=want)
+            return dr, dq, dg, None
+
+    return RBE2DEnergy

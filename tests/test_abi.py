@@ -1,0 +1,71 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every symbol the header declares, validates parameters in the pure host
+sampler, and draws the same k-set as the oracle's sampler."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2405_06333_amd import inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def R():
+    from paper_2405_06333_amd import rbe2d
+    rbe2d.lib()
+    return rbe2d
+
+
+def header_symbols():
+    src = open(os.path.join(ROOT, "include", "rbe2d.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(rbe2d_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol(R):
+    syms = header_symbols()
+    assert len(syms) >= 13
+    L = R.lib()
+    for name in syms:
+        assert hasattr(L, name), name
+    assert set(syms) == set(R.EXPORTS)
+
+
+def test_params_struct_layout_matches_header(R):
+    # 9 doubles, 4 int32, 1 int64, 1 double
+    assert R.Params.n_max.offset == 9 * 8 + 4 * 4
+    assert __import__("ctypes").sizeof(R.Params) == 9 * 8 + 4 * 4 + 8 + 8
+
+
+@pytest.mark.parametrize("w", [inputs.SMALL_FP64, inputs.DIELECTRIC, inputs.LARGE_MD, inputs.GRADIENT])
+def test_host_sampler_matches_oracle_sampler(R, orc, w):
+    p = R.make_params(**w.slab_kwargs(), n_max=10)
+    for stream in (0, 1, 99):
+        a = R.draw_kset(p, w.seed, stream)
+        o = orc.Slab(Lx=w.Lx, Ly=w.Ly, H=w.H, g_top=w.gamma_top, g_bot=w.gamma_bot, alpha=w.alpha,
+                     rc=w.r_c, M=w.M, P=w.P)
+        b = orc.draw_kset(o, w.seed, stream)
+        assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("bad", [dict(r_c=50.0), dict(gamma_top=1.2), dict(alpha=0.0), dict(P=0),
+                                 dict(M=65), dict(H=-1.0), dict(Lz_ext=10.0, M=8)])
+def test_invalid_parameters_rejected_on_host(R, bad):
+    kw = inputs.DIELECTRIC.slab_kwargs()
+    kw.update(bad)
+    p = R.make_params(**kw, n_max=10)
+    with pytest.raises(R.RBE2DError) as ei:
+        R.draw_kset(p, 0, 0) if "Lz_ext" not in bad else _create(R, p)
+    assert ei.value.status == R.RBE2D_E_INVAL
+
+
+def _create(R, p):
+    import ctypes
+    h = ctypes.c_void_p()
+    st = R.lib().rbe2d_create(ctypes.byref(p), ctypes.byref(h))
+    if st != 0:
+        raise R.RBE2DError(st, R.lib().rbe2d_last_error(None).decode())
+    R.lib().rbe2d_destroy(h)

@@ -1,0 +1,204 @@
+"""GPU parity: librbe2d (through its C ABI) against the FP64 CPU oracle on the
+same seeded inputs and the same k-set.
+
+Tolerances (relative RMS over all force components, and energy error
+relative to the sum of the magnitudes of the energy components):
+  FP64 path        1e-9
+  FP32-phase path  1e-5
+"""
+import numpy as np
+import pytest
+
+from paper_2405_06333_amd import inputs
+from tests.gpu_common import energy_scale, gpu_slab, oracle_slab, rel_rms, to_dev
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-9, "fp32": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a GPU"
+    return t
+
+
+@pytest.fixture(scope="module")
+def R():
+    from paper_2405_06333_amd import rbe2d
+    rbe2d.lib()
+    return rbe2d
+
+
+def run_pair(torch, R, orc, w, precision, kset=None, flags=7, targets=None, seed_stream=0):
+    """Evaluate workload w on the GPU and with the oracle; returns (F_gpu,
+    E_gpu, oracle result)."""
+    pos, q = inputs.sample(w)
+    slab = gpu_slab(R, w, precision)
+    if kset is None:
+        kset = slab.draw_kset(w.seed, seed_stream)
+    slab.set_kset(kset)
+    F, E = slab.forces(to_dev(torch, pos), to_dev(torch, q), flags=flags, want_energy=True)
+    slab.check()
+    F = F.cpu().numpy()
+    E = E.cpu().numpy()
+    o = oracle_slab(orc, w, slab.Lz_ext)
+    parts = tuple(p for p, b in (("real", 2), ("kspace", 1), ("ibc", 4)) if flags & b)
+    ref = orc.evaluate(o, pos, q, kset, targets=targets, parts=parts)
+    return F, E, ref, slab
+
+
+def assert_parity(F, E, ref, tol, targets=None):
+    Fs = F if targets is None else F[np.asarray(targets)]
+    err = rel_rms(Fs, ref.F)
+    assert err <= tol, f"force rel-RMS {err:.3e} > {tol:g}"
+    scale = energy_scale(ref)
+    for k, (eg, er) in enumerate(zip(E, ref.energies())):
+        assert abs(eg - er) <= tol * scale, f"energy[{k}] {eg!r} vs {er!r}"
+
+
+# ---------------------------------------------------------------------------
+
+def test_host_and_device_sampler_identical(torch, R, orc):
+    for w in (inputs.SMALL_FP64, inputs.DIELECTRIC, inputs.LARGE_MD):
+        slab = gpu_slab(R, w, n_max=16)
+        for stream in (0, 7):
+            host = slab.draw_kset(w.seed, stream)
+            slab.sample_kset(w.seed, stream)
+            dev = slab.get_kset()
+            assert np.array_equal(host, dev)
+            o = oracle_slab(orc, w, slab.Lz_ext)
+            assert np.array_equal(host, orc.draw_kset(o, w.seed, stream))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_small_no_dielectric(torch, R, orc, precision):
+    w = inputs.SMALL_FP64
+    F, E, ref, _ = run_pair(torch, R, orc, w, precision)
+    assert_parity(F, E, ref, TOL[precision])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_dielectric_slab(torch, R, orc, precision):
+    w = inputs.DIELECTRIC
+    F, E, ref, _ = run_pair(torch, R, orc, w, precision)
+    assert_parity(F, E, ref, TOL[precision])
+
+
+@pytest.mark.parametrize("flags", [1, 2, 4, 5, 6])
+def test_parts_separately(torch, R, orc, flags):
+    w = inputs.small_random(3, 300, L=12.0, H=5.0, gamma_top=0.6, gamma_bot=-0.8, alpha=0.9, r_c=5.0,
+                            P=37, M=4)
+    F, E, ref, _ = run_pair(torch, R, orc, w, "fp64", flags=flags)
+    assert_parity(F, E, ref, 1e-9)
+
+
+RAGGED = [
+    # N, P, M, H, r_c, gammas
+    (1, 1, 0, 4.0, 3.0, (0.0, 0.0)),
+    (2, 7, 1, 4.0, 3.0, (0.5, -0.5)),
+    (63, 16, 2, 4.0, 3.0, (0.9, 0.9)),
+    (65, 17, 3, 2.0, 3.0, (0.7, -0.6)),     # H < r_c: second-order images enter real space
+    (257, 33, 5, 1.2, 3.5, (-0.9, 0.8)),    # several image orders within r_c
+    (1000, 100, 8, 4.0, 3.0, (1.0, 1.0)),   # perfect conductors-like contrasts
+    (4097, 9, 6, 4.0, 3.0, (-1.0, -1.0)),
+]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", RAGGED, ids=[f"N{c[0]}P{c[1]}M{c[2]}" for c in RAGGED])
+def test_ragged_and_degenerate(torch, R, orc, precision, case):
+    N, P, M, H, rc, (gt, gb) = case
+    w = inputs.small_random(100 + N, N, L=10.0, H=H, gamma_top=gt, gamma_bot=gb, alpha=1.1, r_c=rc,
+                            P=P, M=M, margin=0.05)
+    F, E, ref, _ = run_pair(torch, R, orc, w, precision)
+    assert_parity(F, E, ref, TOL[precision] * (3 if precision == "fp32" else 1))
+
+
+def test_small_box_minimum_image(torch, R, orc):
+    """Lx < 3 r_c: fewer than three cells per axis, minimum image per pair."""
+    w = inputs.small_random(5, 200, L=7.0, H=3.0, gamma_top=0.3, gamma_bot=0.2, alpha=1.2, r_c=3.4,
+                            P=20, M=2)
+    F, E, ref, _ = run_pair(torch, R, orc, w, "fp64")
+    assert_parity(F, E, ref, 1e-9)
+
+
+def test_empty_input(torch, R):
+    w = inputs.SMALL_FP64
+    slab = gpu_slab(R, w, "fp64", n_max=10)
+    slab.set_kset(slab.draw_kset(0))
+    pos = torch.zeros((0, 3), dtype=torch.float64, device="cuda")
+    q = torch.zeros((0,), dtype=torch.float64, device="cuda")
+    F, E = slab.forces(pos, q, want_energy=True)
+    slab.check()
+    assert F.shape == (0, 3)
+    assert np.all(E.cpu().numpy() == 0.0)
+
+
+def test_accumulate_flag(torch, R):
+    w = inputs.small_random(8, 500, L=12.0, H=4.0, gamma_top=0.5, gamma_bot=0.5, P=24, M=3)
+    pos, q = inputs.sample(w)
+    slab = gpu_slab(R, w, "fp64")
+    slab.set_kset(slab.draw_kset(1))
+    P_, Q_ = to_dev(torch, pos), to_dev(torch, q)
+    F1 = slab.forces(P_, Q_)
+    F2 = torch.ones_like(F1)
+    slab.forces(P_, Q_, flags=7 | 16, out=F2)
+    assert torch.allclose(F2, F1 + 1.0, rtol=0, atol=1e-12)
+
+
+def test_bitwise_reproducible(torch, R):
+    w = inputs.DIELECTRIC
+    pos, q = inputs.sample(w)
+    for prec in ("fp64", "fp32"):
+        slab = gpu_slab(R, w, prec)
+        slab.set_kset(slab.draw_kset(w.seed))
+        a = slab.forces(to_dev(torch, pos), to_dev(torch, q))
+        b = slab.forces(to_dev(torch, pos), to_dev(torch, q))
+        assert torch.equal(a, b)
+
+
+def test_range_error_reported(torch, R):
+    w = inputs.small_random(9, 100, P=8)
+    pos, q = inputs.sample(w)
+    pos[5, 2] = w.H + 0.25          # outside the slab: kernels stay in bounds, the call is flagged
+    slab = gpu_slab(R, w, "fp64")
+    slab.set_kset(slab.draw_kset(3))
+    slab.forces(to_dev(torch, pos), to_dev(torch, q))
+    with pytest.raises(R.RBE2DError) as ei:
+        slab.check()
+    assert ei.value.status == R.RBE2D_E_RANGE
+    slab.check()                    # the error word is cleared
+
+
+def test_invalid_arguments(torch, R):
+    w = inputs.SMALL_FP64
+    with pytest.raises(R.RBE2DError):
+        gpu_slab(R, w, r_c=11.0)            # r_c > L/2
+    with pytest.raises(R.RBE2DError):
+        gpu_slab(R, w, gamma_top=1.5)
+    slab = gpu_slab(R, w, n_max=10)
+    pos = torch.zeros((20, 3), dtype=torch.float64, device="cuda")
+    q = torch.zeros((20,), dtype=torch.float64, device="cuda")
+    with pytest.raises(R.RBE2DError) as ei:
+        slab.forces(pos[:5], q[:5])         # no k-set yet
+    assert ei.value.status == R.RBE2D_E_STATE
+    slab.set_kset(slab.draw_kset(0))
+    with pytest.raises(R.RBE2DError):
+        slab.forces(pos, q)                 # N > n_max
+    with pytest.raises(R.RBE2DError):
+        bad = np.zeros((w.P, 3), dtype=np.int32)
+        slab.set_kset(bad)                  # zero vectors
+
+
+def test_large_md_sampled_particles(torch, R, orc):
+    """The 1e6-ion slab in the launch configuration of the benchmark (FP32
+    phases): forces on 96 sampled particles against the oracle."""
+    w = inputs.LARGE_MD
+    rng = np.random.default_rng(11)
+    targets = np.sort(rng.choice(w.N, 96, replace=False))
+    F, E, ref, slab = run_pair(torch, R, orc, w, "fp32", targets=targets, seed_stream=0)
+    err = rel_rms(F[targets], ref.F)
+    assert err <= 1e-5, err
+    assert np.all(np.isfinite(F))
