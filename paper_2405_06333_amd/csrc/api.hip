@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdarg>
+#include <cstdlib>
 #include <cstring>
 
 #include "rbe2d_internal.h"
@@ -225,16 +226,19 @@ rbe2d_status rbe2d_create(const rbe2d_params *pin, rbe2d_handle *out) {
         return fail(nullptr, RBE2D_E_INVAL, "k-range too wide for FP32 phases (alpha L too large)");
     }
 
-    // cell grid: cells >= r_c in each direction, coarsened if there would be too many
-    h->ncx = std::max(1, (int)std::floor(p.Lx / p.r_c));
-    h->ncy = std::max(1, (int)std::floor(p.Ly / p.r_c));
-    h->ncz = std::max(1, (int)std::floor(p.H / p.r_c));
-    const int64_t cell_cap = std::max<int64_t>(4 * p.n_max, 4096);
-    while ((int64_t)h->ncx * h->ncy * h->ncz > cell_cap && (h->ncx > 3 || h->ncy > 3 || h->ncz > 1)) {
+    // cell grid: cells >= r_c / reach in x and y (searched +-reach columns),
+    // >= r_c / reach in z; coarsened if there would be too many cells
+    h->reach = 2;
+    h->ncx = std::max(1, (int)std::floor(h->reach * p.Lx / p.r_c));
+    h->ncy = std::max(1, (int)std::floor(h->reach * p.Ly / p.r_c));
+    h->ncz = std::max(1, (int)std::floor(h->reach * p.H / p.r_c));
+    const int64_t cell_cap = std::max<int64_t>(2 * p.n_max, 4096);
+    while ((int64_t)h->ncx * h->ncy * h->ncz > cell_cap && (h->ncx > 5 || h->ncy > 5 || h->ncz > 1)) {
         if (h->ncz > 1) h->ncz = (h->ncz + 1) / 2;
-        else { h->ncx = std::max(3, h->ncx / 2); h->ncy = std::max(3, h->ncy / 2); }
+        else { h->ncx = std::max(5, h->ncx / 2); h->ncy = std::max(5, h->ncy / 2); }
     }
     h->ncells = h->ncx * h->ncy * h->ncz;
+    if (const char *env = std::getenv("RBE2D_REAL_ROUND_MIN")) h->round_min = std::max(1, std::min(64, std::atoi(env)));
     h->hx = p.Lx / h->ncx; h->hy = p.Ly / h->ncy; h->hz = p.H / h->ncz;
 
     (void)hipGetDevice(&h->device);
@@ -256,8 +260,8 @@ rbe2d_status rbe2d_create(const rbe2d_params *pin, rbe2d_handle *out) {
     A(&w.krec, (size_t)h->P * kKRec);
     A(&w.kf32, 2 * (size_t)h->P);
     A(&w.fpart, (size_t)std::min<int64_t>(64 * ncap, 4096 * kBlock) * 4);
-    A(&w.cell, ncap); A(&w.slot, ncap); A(&w.tmp, ncap); A(&w.sidx, ncap);
-    A(&w.count, h->ncells); A(&w.start, h->ncells + 1);
+    A(&w.cell, ncap); A(&w.slot, ncap); A(&w.tmp, ncap); A(&w.sidx, ncap); A(&w.scell, ncap);
+    A(&w.count, h->ncells); A(&w.start, h->ncells + 1); A(&w.scanbuf, h->ncells / 1024 + 2);
     A(&w.sorted, ncap); A(&w.freal, ncap); A(&w.dgreal, ncap);
     A(&w.rpart, 3 * nblk);
     A(&w.fam, std::max<size_t>(1, h->fam.size()));

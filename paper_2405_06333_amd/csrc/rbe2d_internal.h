@@ -66,8 +66,10 @@ struct Workspace {
     double *fpart = nullptr;    // force-pass partials [ksplit][N][4]
     // real space
     int *cell = nullptr, *slot = nullptr, *count = nullptr, *start = nullptr, *tmp = nullptr;
-    double4 *sorted = nullptr;  // (x, y, z, q) in cell order, x and y wrapped
+    int *scanbuf = nullptr;     // per-scan-block totals of the cell counts
+    double4 *sorted = nullptr;  // (x, y, z, q) in cell order, x relative to the cell's x edge
     int *sidx = nullptr;        // original index of sorted particle
+    int *scell = nullptr;       // cell of sorted particle
     double4 *freal = nullptr;   // per original particle: F_real (x, y, z), phi_real
     double2 *dgreal = nullptr;  // per original particle: d phi_real / d gamma_{top,bot}
     double *rpart = nullptr;    // per real-space block: sum q phi, sum q dphi/dg_top, .../dg_bot
@@ -97,6 +99,8 @@ struct rbe2d_ctx {
     int n_tiles_cap = 0;
     // cell grid
     int ncx = 1, ncy = 1, ncz = 1, ncells = 1;
+    int reach = 2;                   // neighbour columns on each side; cells >= r_c / reach
+    int round_min = 40;              // real space: drain pair queues while >= this many lanes hold work
     double hx = 0, hy = 0, hz = 0;
     std::vector<rbe2d::Family> fam;
     rbe2d::Workspace w;

@@ -1,0 +1,179 @@
+"""Differentiable energy on the GPU: the adjoint kernels (dE/dr, dE/dq,
+dE/dgamma with rho(k) recomputed) against the oracle's analytic gradients
+and against central finite differences of the GPU energy, plus the
+torch.autograd.Function wrapper."""
+import numpy as np
+import pytest
+
+from paper_2405_06333_amd import inputs
+from tests.gpu_common import gpu_slab, oracle_slab, rel_rms, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+@pytest.fixture(scope="module")
+def R():
+    from paper_2405_06333_amd import rbe2d
+    rbe2d.lib()
+    return rbe2d
+
+
+def oracle_grads(orc, o, pos, q, n):
+    c = orc.rbe_weights(o, n)
+    r = orc.evaluate(o, pos, q, n, c)
+    dg = orc.dE_dgamma(o, pos, q, n, c)
+    return r, dg
+
+
+def gpu_grads(torch, slab, pos, q, gE=1.0):
+    g = torch.tensor(gE, dtype=torch.float64, device="cuda")
+    dr, dq, dg = slab.energy_backward(to_dev(torch, pos), to_dev(torch, q), g)
+    slab.check()
+    return dr.cpu().numpy(), dq.cpu().numpy(), dg.cpu().numpy()
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("fp32", 1e-5)])
+def test_adjoint_matches_oracle_small(torch, R, orc, precision, tol):
+    w = inputs.small_random(21, 600, L=14.0, H=5.0, gamma_top=0.7, gamma_bot=-0.5, alpha=0.8, r_c=5.0,
+                            P=50, M=5)
+    pos, q = inputs.sample(w)
+    slab = gpu_slab(R, w, precision)
+    n = slab.draw_kset(4)
+    slab.set_kset(n)
+    dr, dq, dg = gpu_grads(torch, slab, pos, q, gE=1.7)
+    r, dgo = oracle_grads(orc, oracle_slab(orc, w, slab.Lz_ext), pos, q, n)
+    assert rel_rms(dr, -1.7 * r.F) <= tol
+    assert rel_rms(dq, 1.7 * r.phi) <= tol
+    assert np.allclose(dg, 1.7 * dgo, rtol=tol, atol=tol * np.abs(dgo).max())
+
+
+def test_adjoint_gradient_workload(torch, R, orc):
+    """The 20,000-ion gradient workload (gamma = 0.8, M = 8, P = 300), FP64."""
+    w = inputs.GRADIENT
+    pos, q = inputs.sample(w)
+    slab = gpu_slab(R, w, "fp64")
+    n = slab.draw_kset(w.seed)
+    slab.set_kset(n)
+    dr, dq, dg = gpu_grads(torch, slab, pos, q)
+    r, dgo = oracle_grads(orc, oracle_slab(orc, w, slab.Lz_ext), pos, q, n)
+    assert rel_rms(dr, -r.F) <= 1e-9
+    assert rel_rms(dq, r.phi) <= 1e-9
+    assert np.allclose(dg, dgo, rtol=1e-9, atol=1e-9 * np.abs(dgo).max())
+
+
+class CutoffGuard:
+    """Detects perturbations that move a real or image pair across r_c (the
+    energy jumps there by ~erfc(alpha r_c)/r_c, which a difference quotient
+    would see).  Image heights follow Eq. (3.3)."""
+
+    def __init__(self, pos, w):
+        self.w = w
+        src, own, real = [pos], [np.arange(len(pos))], [np.ones(len(pos), bool)]
+        for l in range(1, w.M + 1):
+            s = 1.0 if l % 2 == 0 else -1.0
+            for zimg in (s * pos[:, 2] + 2 * ((l + 1) // 2) * w.H, s * pos[:, 2] - 2 * (l // 2) * w.H):
+                p = pos.copy()
+                p[:, 2] = zimg
+                src.append(p)
+                own.append(np.arange(len(pos)))
+                real.append(np.zeros(len(pos), bool))
+        self.src, self.own, self.real = np.concatenate(src), np.concatenate(own), np.concatenate(real)
+
+    def crosses(self, pos, idx, h):
+        for i in np.atleast_1d(idx):
+            d = pos[i] - self.src
+            d[:, 0] -= self.w.Lx * np.round(d[:, 0] / self.w.Lx)
+            d[:, 1] -= self.w.Ly * np.round(d[:, 1] / self.w.Ly)
+            dist = np.sqrt((d ** 2).sum(axis=1))
+            slack = np.where(self.own == i, 2 * h, 2 * h) * 1.01
+            keep = ~((self.own == i) & self.real)
+            if np.any(keep & (np.abs(dist - self.w.r_c) <= slack)):
+                return True
+        return False
+
+
+def test_adjoint_against_finite_differences(torch, R, orc):
+    w = inputs.GRADIENT
+    pos, q = inputs.sample(w)
+    slab = gpu_slab(R, w, "fp64")
+    n = slab.draw_kset(w.seed)
+    slab.set_kset(n)
+    dr, dq, dg = gpu_grads(torch, slab, pos, q)
+    Q = to_dev(torch, q)
+
+    def energy(p, qq=None, s=slab):
+        return s.energy(to_dev(torch, p), Q if qq is None else to_dev(torch, qq))[0].item()
+
+    rng = np.random.default_rng(0)
+    h = 1e-5
+    guard = CutoffGuard(pos, w)
+    checked = skipped = 0
+    for _ in range(256):
+        i = int(rng.integers(w.N))
+        d = int(rng.integers(3))
+        if guard.crosses(pos, i, h):
+            skipped += 1
+            continue
+        pp, pm = pos.copy(), pos.copy()
+        pp[i, d] += h
+        pm[i, d] -= h
+        fd = (energy(pp) - energy(pm)) / (2 * h)
+        assert abs(fd - dr[i, d]) <= 2e-6 * (1 + abs(dr[i, d])), (i, d, fd, dr[i, d])
+        checked += 1
+    assert checked >= 200, (checked, skipped)
+    # random directions over the coordinates of 32 particles at a time
+    done = 0
+    while done < 8:
+        sel = rng.choice(w.N, 32, replace=False)
+        if guard.crosses(pos, sel, h):
+            continue
+        u = np.zeros_like(pos)
+        u[sel] = rng.normal(size=(32, 3))
+        u /= np.linalg.norm(u)
+        fd = (energy(pos + h * u) - energy(pos - h * u)) / (2 * h)
+        an = (dr * u).sum()
+        assert abs(fd - an) <= 2e-6 * (1 + abs(an)), (fd, an)
+        done += 1
+    # charges: E is quadratic in q, the central difference is exact up to rounding
+    for i in rng.choice(w.N, 64, replace=False):
+        qp, qm = q.copy(), q.copy()
+        qp[i] += 1e-3
+        qm[i] -= 1e-3
+        fd = (energy(pos, qp) - energy(pos, qm)) / 2e-3
+        assert abs(fd - dq[i]) <= 1e-7 * (1 + abs(dq[i]))
+    # dielectric contrasts (same k-set, same Lz_ext)
+    for wi, key in ((0, "gamma_top"), (1, "gamma_bot")):
+        es = []
+        for sgn in (+1, -1):
+            s2 = gpu_slab(R, w, "fp64", **{key: getattr(w, key) + sgn * 1e-6}, Lz_ext=slab.Lz_ext)
+            s2.set_kset(n)
+            es.append(energy(pos, s=s2))
+        fd = (es[0] - es[1]) / 2e-6
+        assert abs(fd - dg[wi]) <= 1e-5 * (1 + abs(dg[wi])), (key, fd, dg[wi])
+
+
+def test_autograd_function(torch, R):
+    w = inputs.small_random(31, 400, L=12.0, H=5.0, gamma_top=0.6, gamma_bot=0.4, alpha=0.9, r_c=5.0, P=30,
+                            M=4)
+    pos, q = inputs.sample(w)
+    slab = gpu_slab(R, w, "fp64")
+    slab.set_kset(slab.draw_kset(2))
+    Fn = R.energy_function()
+    P_ = to_dev(torch, pos).requires_grad_(True)
+    Q_ = to_dev(torch, q).requires_grad_(True)
+    G_ = torch.tensor([w.gamma_top, w.gamma_bot], dtype=torch.float64, device="cuda", requires_grad=True)
+    E = Fn.apply(P_, Q_, G_, slab)
+    (3.0 * E).backward()
+    dr, dq, dg = gpu_grads(torch, slab, pos, q, gE=3.0)
+    assert np.array_equal(P_.grad.cpu().numpy(), dr)
+    assert np.array_equal(Q_.grad.cpu().numpy(), dq)
+    assert np.array_equal(G_.grad.cpu().numpy(), dg)
+    F = slab.forces(to_dev(torch, pos), to_dev(torch, q)).cpu().numpy()
+    assert np.allclose(dr, -3.0 * F, rtol=1e-12, atol=1e-12 * np.abs(F).max())
