@@ -172,10 +172,53 @@ rbe2d_status rbe2d_energy_backward(rbe2d_handle h, int64_t N, const double *pos,
  * z_lo and z_hi (0 < z_lo < z_hi < H); a fresh k-set drawn on the device
  * from (seed, stream_id = step0 + step); F recomputed (RBE2D_ALL);
  * v += dt/2 F.  F must hold the forces of the initial positions on entry.
- * pos, vel, F (device N x 3) are updated in place.  Enqueued only. */
+ * pos, vel, F (device N x 3) are updated in place.  Enqueued only.
+ * With use_graph != 0 one step is captured into a hipGraph (on a private
+ * stream, the step index read from a device counter) and replayed n_steps
+ * times on `stream`; the graph is kept and reused while the arrays, dt,
+ * walls, seed and particle counts stay the same (capturing it creates a
+ * stream and instantiates a graph: the only host-side allocations after
+ * create).  Both modes give bitwise identical results. */
 rbe2d_status rbe2d_md_run(rbe2d_handle h, int64_t N, double *pos, double *vel, const double *q,
                           double *F, double dt, double z_lo, double z_hi, uint64_t seed,
-                          int64_t step0, int32_t n_steps, void *stream);
+                          int64_t step0, int32_t n_steps, int32_t use_graph, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Batches of independent systems (replicas).  One handle holds n_sys slabs,
+ * each with its own rbe2d_params (box, contrasts, alpha, r_c, M, n_max); P
+ * and precision must be the same for all.  Every kernel of a call covers
+ * all systems at once: the particles of system r are rows
+ * offsets[r] .. offsets[r+1]-1 of the caller's arrays (offsets: host,
+ * n_sys + 1 int64, offsets[0] = 0, nondecreasing, each count <= that
+ * system's n_max).  The k-set of a batched handle is n_sys x P x 3 int32,
+ * system-major, in rbe2d_set_kset / rbe2d_get_kset; rbe2d_sample_kset
+ * draws system r from stream id (stream_id + r).  Results per system equal
+ * those of a single-system handle with the same params and k-set up to
+ * summation order.  The single-system calls (rbe2d_forces, rbe2d_energy,
+ * rbe2d_energy_backward, rbe2d_md_run) return RBE2D_E_STATE on a batched
+ * handle.
+ * ------------------------------------------------------------------------- */
+
+/* Creates a handle over n_sys (1..65536) systems; params is a host array of
+ * n_sys entries.  Workspaces are sized for the sum of the n_max. */
+rbe2d_status rbe2d_batch_create(int32_t n_sys, const rbe2d_params *params, rbe2d_handle *out);
+
+/* Lz_ext, V and S of system `sys` (rbe2d_query is system 0). */
+rbe2d_status rbe2d_query_system(rbe2d_handle h, int32_t sys, double *Lz_ext, double *V, double *S);
+
+/* rbe2d_forces for all systems: pos, q, F cover offsets[n_sys] rows; energy
+ * (device, 5 doubles per system, system-major) or NULL. */
+rbe2d_status rbe2d_batch_forces(rbe2d_handle h, const int64_t *offsets, const double *pos,
+                                const double *q, double *F, double *energy, uint32_t flags,
+                                void *stream);
+
+/* rbe2d_md_run for all systems, walls at z = wall_margin and
+ * z = H_r - wall_margin of each system (0 < wall_margin < min H / 2).  Step s
+ * of system r draws its k-set from stream id (step0 + s) * n_sys + r. */
+rbe2d_status rbe2d_batch_md_run(rbe2d_handle h, const int64_t *offsets, double *pos, double *vel,
+                                const double *q, double *F, double dt, double wall_margin,
+                                uint64_t seed, int64_t step0, int32_t n_steps, int32_t use_graph,
+                                void *stream);
 
 /* Kernel timing (tracing).  rbe2d_profile_enable(h, n) creates n event
  * pairs per kernel class and from then on brackets every launch of each

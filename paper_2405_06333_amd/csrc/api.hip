@@ -1,10 +1,11 @@
 // C ABI of librbe2d (declared in include/rbe2d.h): parameter validation,
-// derived constants, workspace management, the host k-sampler and the
-// launch sequences of one RBE2D evaluation (Algorithm 2 of the paper).
+// derived constants, workspace management, the host k-sampler, layouts of
+// one or many systems, and the launch sequences of one RBE2D evaluation
+// (Algorithm 2 of the paper) and of velocity-Verlet steps around it.
 #include <algorithm>
 #include <cmath>
-#include <cstdio>
 #include <cstdarg>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 
@@ -31,9 +32,9 @@ rbe2d_status hipfail(rbe2d_ctx *h, hipError_t e, const char *what) {
     return fail(h, RBE2D_E_HIP, "%s: %s", what, hipGetErrorString(e));
 }
 
-#define RBE2D_TRY(h, call, what)                       \
-    do {                                               \
-        hipError_t e_ = (call);                        \
+#define RBE2D_TRY(h, call, what)                           \
+    do {                                                   \
+        hipError_t e_ = (call);                            \
         if (e_ != hipSuccess) return hipfail(h, e_, what); \
     } while (0)
 
@@ -109,6 +110,107 @@ double auto_lz(const rbe2d_params *p) {
     return (p->M + 1) * p->H + std::max(std::max(p->Lx, p->Ly) / (2.0 * kPi) * lg, std::sqrt(lg) / p->alpha);
 }
 
+// Derived constants, image tables, real-space families, sampler tables and
+// cell grid of one system.
+rbe2d_status setup_system(const rbe2d_params *pin, SysHost &sh) {
+    rbe2d_status st = validate(pin, nullptr);
+    if (st) return st;
+    sh.p = *pin;
+    rbe2d_params &p = sh.p;
+    SysDesc &d = sh.d;
+    std::memset(&d, 0, sizeof d);
+    if (p.eps_lz <= 0.0) p.eps_lz = 1e-6;
+    if (p.coulomb_prefactor == 0.0) p.coulomb_prefactor = 1.0;
+    const double Lz = p.Lz_ext > 0.0 ? p.Lz_ext : auto_lz(&p);
+    if (Lz < (p.M + 1) * p.H)
+        return fail(nullptr, RBE2D_E_INVAL,
+                    "Lz_ext = %g < (M+1) H = %g: the z-replicas of the charges would overlap their images",
+                    p.Lz_ext, (p.M + 1) * p.H);
+    p.Lz_ext = Lz;
+    d.Lx = p.Lx; d.Ly = p.Ly; d.H = p.H; d.Lz = Lz;
+    d.V = p.Lx * p.Ly * Lz;
+    d.S = theta_axis(p.alpha, p.Lx) * theta_axis(p.alpha, p.Ly) * theta_axis(p.alpha, Lz) - 1.0;
+    d.alpha = p.alpha; d.rc = p.r_c; d.rc2 = p.r_c * p.r_c; d.pref = p.coulomb_prefactor;
+    d.g_top = p.gamma_top; d.g_bot = p.gamma_bot; d.M = p.M;
+    d.cfac = 2.0 * kPi * d.S * d.pref / (d.V * p.P);
+
+    // image weights, their derivatives, the IBC image-dipole coefficients and
+    // the real-space families that can come within r_c of the slab
+    std::memset(&sh.img, 0, sizeof sh.img);
+    sh.fam.clear();
+    d.g1 = 1.0; d.cgam = 0.0; d.dg1t = d.dg1b = d.dcgt = d.dcgb = 0.0;
+    for (int l = 1; l <= p.M; l++) {
+        int a, b;
+        exponents(l, +1, &a, &b);
+        sh.img.ea_p[l - 1] = a; sh.img.eb_p[l - 1] = b;
+        const double gpl = ipow(p.gamma_top, a) * ipow(p.gamma_bot, b);
+        const double dpt = dmono(a, p.gamma_top, b, p.gamma_bot), dpb = dmono(b, p.gamma_bot, a, p.gamma_top);
+        exponents(l, -1, &a, &b);
+        sh.img.ea_m[l - 1] = a; sh.img.eb_m[l - 1] = b;
+        const double gml = ipow(p.gamma_top, a) * ipow(p.gamma_bot, b);
+        const double dmt = dmono(a, p.gamma_top, b, p.gamma_bot), dmb = dmono(b, p.gamma_bot, a, p.gamma_top);
+        sh.img.gp[l - 1] = gpl; sh.img.gm[l - 1] = gml;
+        const double sgn = (l % 2 == 0) ? 1.0 : -1.0;
+        const double shp = 2.0 * ((l + 1) / 2) * p.H, shm = -2.0 * (l / 2) * p.H;
+        d.g1 += sgn * (gpl + gml);
+        d.cgam += shp * gpl + shm * gml;
+        d.dg1t += sgn * (dpt + dmt); d.dg1b += sgn * (dpb + dmb);
+        d.dcgt += shp * dpt + shm * dmt; d.dcgb += shp * dpb + shm * dmb;
+        if ((l - 1) * p.H < p.r_c) {
+            for (int side = 1; side >= -1; side -= 2) {
+                Family f;
+                if (l % 2) {   // reflection: target seen at sz = -1
+                    f.sz = -1.0;
+                    f.cz = side > 0 ? (l + 1) * p.H : -(l - 1) * p.H;
+                    f.zsign = -1.0;
+                } else {       // translation
+                    f.sz = 1.0;
+                    f.cz = side > 0 ? -l * p.H : l * p.H;
+                    f.zsign = 1.0;
+                }
+                f.w = side > 0 ? gpl : gml;
+                f.dwt = side > 0 ? dpt : dmt;
+                f.dwb = side > 0 ? dpb : dmb;
+                sh.fam.push_back(f);
+            }
+        }
+    }
+    if ((int)sh.fam.size() > kMaxFamilies)
+        return fail(nullptr, RBE2D_E_INVAL, "too many image orders within r_c (H too small for r_c)");
+    d.nfam = (int)sh.fam.size();
+
+    // k-sampling tables and the FP32 phase split
+    sh.cdf.assign(3, {});
+    const double Ls[3] = {p.Lx, p.Ly, Lz};
+    int nall = 0;
+    for (int ax = 0; ax < 3; ax++) {
+        axis_table(p.alpha, Ls[ax], &d.nmax[ax], sh.cdf[ax]);
+        nall = std::max(nall, d.nmax[ax]);
+    }
+    int bits = 0;
+    while ((1 << bits) <= nall) bits++;
+    d.fh_bits = std::max(1, 23 - bits);
+    d.scale_h = std::ldexp(1.0, d.fh_bits);
+    if (p.precision == RBE2D_PREC_FP32_PHASE && bits > 20)
+        return fail(nullptr, RBE2D_E_INVAL, "k-range too wide for FP32 phases (alpha L too large)");
+
+    // cell grid: cells >= r_c / reach in x, y and z (searched +-reach
+    // columns), coarsened if there would be too many cells
+    d.reach = 2;
+    int ncx = std::max(1, (int)std::floor(d.reach * p.Lx / p.r_c));
+    int ncy = std::max(1, (int)std::floor(d.reach * p.Ly / p.r_c));
+    int ncz = std::max(1, (int)std::floor(d.reach * p.H / p.r_c));
+    const int64_t cell_cap = std::max<int64_t>(2 * p.n_max, 4096);
+    while ((int64_t)ncx * ncy * ncz > cell_cap && (ncx > 5 || ncy > 5 || ncz > 1)) {
+        if (ncz > 1) ncz = (ncz + 1) / 2;
+        else { ncx = std::max(5, ncx / 2); ncy = std::max(5, ncy / 2); }
+    }
+    d.ncx = ncx; d.ncy = ncy; d.ncz = ncz;
+    d.hx = p.Lx / ncx; d.hy = p.Ly / ncy; d.hz = p.H / ncz;
+    d.inv_hy = 1.0 / d.hy; d.inv_hz = 1.0 / d.hz;
+    return RBE2D_OK;
+}
+
 template <typename T>
 hipError_t dalloc(rbe2d_ctx *h, T **ptr, size_t count) {
     void *p = nullptr;
@@ -131,157 +233,131 @@ void prof_free(rbe2d_ctx *h) {
     for (int sl = 0; sl < RBE2D_PROF_SLOTS; sl++) p.used[sl] = 0;
 }
 
-}  // namespace
+void free_graph(rbe2d_ctx *h) {
+    if (h->md_exec) (void)hipGraphExecDestroy(h->md_exec);
+    if (h->md_graph) (void)hipGraphDestroy(h->md_graph);
+    h->md_exec = nullptr;
+    h->md_graph = nullptr;
+    h->md_key.clear();
+}
 
-extern "C" {
+void free_all(rbe2d_ctx *h) {
+    free_graph(h);
+    prof_free(h);
+    for (void *p : h->allocs) (void)hipFree(p);
+    h->allocs.clear();
+    if (h->kstage) (void)hipHostFree(h->kstage);
+    if (h->lay_stage) (void)hipHostFree(h->lay_stage);
+    if (h->kev) (void)hipEventDestroy(h->kev);
+    if (h->lay_ev) (void)hipEventDestroy(h->lay_ev);
+}
 
-rbe2d_status rbe2d_create(const rbe2d_params *pin, rbe2d_handle *out) {
+// A handle over n systems: every system is set up and the workspaces are
+// sized for the sum of their n_max.
+rbe2d_status create_handle(int n, const rbe2d_params *ps, bool batch, rbe2d_handle *out) {
     if (!out) return fail(nullptr, RBE2D_E_INVAL, "out is NULL");
     *out = nullptr;
-    rbe2d_status st = validate(pin, nullptr);
-    if (st) return st;
+    if (n < 1 || n > 65536) return fail(nullptr, RBE2D_E_INVAL, "n_sys must be in [1, 65536]");
+    if (!ps) return fail(nullptr, RBE2D_E_INVAL, "params is NULL");
     rbe2d_ctx *h = new (std::nothrow) rbe2d_ctx();
     if (!h) return fail(nullptr, RBE2D_E_NOMEM, "host allocation failed");
-    h->p = *pin;
-    rbe2d_params &p = h->p;
-    if (p.eps_lz <= 0.0) p.eps_lz = 1e-6;
-    if (p.coulomb_prefactor == 0.0) p.coulomb_prefactor = 1.0;
-    h->pref = p.coulomb_prefactor;
-    h->Lz = p.Lz_ext > 0.0 ? p.Lz_ext : auto_lz(&p);
-    if (h->Lz < (p.M + 1) * p.H) {
-        delete h;
-        return fail(nullptr, RBE2D_E_INVAL,
-                    "Lz_ext = %g < (M+1) H = %g: the z-replicas of the charges would overlap their images",
-                    p.Lz_ext, (p.M + 1) * p.H);
-    }
-    p.Lz_ext = h->Lz;
-    h->V = p.Lx * p.Ly * h->Lz;
-    h->S = theta_axis(p.alpha, p.Lx) * theta_axis(p.alpha, p.Ly) * theta_axis(p.alpha, h->Lz) - 1.0;
-    h->M = p.M;
-    h->P = p.P;
-    h->P_pad = (p.P + kPPad - 1) / kPPad * kPPad;
-
-    // image weights, their derivatives and the IBC image-dipole coefficients
-    ImgTable img;
-    std::memset(&img, 0, sizeof img);
-    h->gp.assign(std::max(1, p.M), 0.0);
-    h->gm.assign(std::max(1, p.M), 0.0);
-    h->g1 = 1.0; h->cgam = 0.0;
-    for (int l = 1; l <= p.M; l++) {
-        int a, b;
-        exponents(l, +1, &a, &b);
-        img.ea_p[l - 1] = a; img.eb_p[l - 1] = b;
-        const double gpl = ipow(p.gamma_top, a) * ipow(p.gamma_bot, b);
-        const double dpt = dmono(a, p.gamma_top, b, p.gamma_bot), dpb = dmono(b, p.gamma_bot, a, p.gamma_top);
-        exponents(l, -1, &a, &b);
-        img.ea_m[l - 1] = a; img.eb_m[l - 1] = b;
-        const double gml = ipow(p.gamma_top, a) * ipow(p.gamma_bot, b);
-        const double dmt = dmono(a, p.gamma_top, b, p.gamma_bot), dmb = dmono(b, p.gamma_bot, a, p.gamma_top);
-        h->gp[l - 1] = gpl; h->gm[l - 1] = gml;
-        img.gp[l - 1] = gpl; img.gm[l - 1] = gml;
-        const double sgn = (l % 2 == 0) ? 1.0 : -1.0;
-        const double shp = 2.0 * ((l + 1) / 2) * p.H, shm = -2.0 * (l / 2) * p.H;
-        h->g1 += sgn * (gpl + gml);
-        h->cgam += shp * gpl + shm * gml;
-        h->dg1[0] += sgn * (dpt + dmt); h->dg1[1] += sgn * (dpb + dmb);
-        h->dcgam[0] += shp * dpt + shm * dmt; h->dcgam[1] += shp * dpb + shm * dmb;
-        // real-space families that can come within r_c of the slab
-        if ((l - 1) * p.H < p.r_c) {
-            for (int side = 1; side >= -1; side -= 2) {
-                Family f;
-                if (l % 2) {   // reflection: target seen at sz = -1
-                    f.sz = -1.0;
-                    f.cz = side > 0 ? (l + 1) * p.H : -(l - 1) * p.H;
-                    f.zsign = -1.0;
-                } else {       // translation
-                    f.sz = 1.0;
-                    f.cz = side > 0 ? -l * p.H : l * p.H;
-                    f.zsign = 1.0;
-                }
-                f.w = side > 0 ? gpl : gml;
-                f.dwt = side > 0 ? dpt : dmt;
-                f.dwb = side > 0 ? dpb : dmb;
-                h->fam.push_back(f);
-            }
+    h->n_sys = n;
+    h->batch = batch;
+    h->sys.resize(n);
+    int64_t n_cap = 0, cap_p = 0, cap_s = 0;
+    int cells = 0;
+    size_t cdf_total = 0;
+    for (int r = 0; r < n; r++) {
+        rbe2d_status st = setup_system(&ps[r], h->sys[r]);
+        if (st) {
+            delete h;
+            if (n > 1) g_create_error = "system " + std::to_string(r) + ": " + g_create_error;
+            return st;
         }
+        const rbe2d_params &p = h->sys[r].p;
+        if (r > 0 && (p.P != h->sys[0].p.P || p.precision != h->sys[0].p.precision)) {
+            delete h;
+            return fail(nullptr, RBE2D_E_INVAL, "all systems of a batch need the same P and precision");
+        }
+        SysDesc &d = h->sys[r].d;
+        d.cbase = cells;
+        cells += d.ncx * d.ncy * d.ncz;
+        for (int ax = 0; ax < 3; ax++) {
+            d.cdf_off[ax] = (int)cdf_total;
+            cdf_total += h->sys[r].cdf[ax].size();
+        }
+        n_cap += p.n_max;
+        cap_p += (p.n_max + kTileMax - 1) / kTileMax * kTileMax;
+        cap_s += (p.n_max + kWave - 1) / kWave * kWave;
     }
-    if ((int)h->fam.size() > kMaxFamilies) {
+    if (n_cap > INT32_MAX - kTileMax || cap_p > INT32_MAX / 2 || cells > INT32_MAX / 2) {
         delete h;
-        return fail(nullptr, RBE2D_E_INVAL, "too many image orders within r_c (H too small for r_c)");
+        return fail(nullptr, RBE2D_E_INVAL, "total particle or cell capacity exceeds 2^30");
     }
-
-    // k-sampling tables and the FP32 phase split
-    h->cdf_host.resize(3);
-    const double Ls[3] = {p.Lx, p.Ly, h->Lz};
-    int nall = 0;
-    for (int d = 0; d < 3; d++) {
-        axis_table(p.alpha, Ls[d], &h->nmax[d], h->cdf_host[d]);
-        nall = std::max(nall, h->nmax[d]);
-    }
-    int bits = 0;
-    while ((1 << bits) <= nall) bits++;
-    h->fh_bits = std::max(1, 23 - bits);
-    if (p.precision == RBE2D_PREC_FP32_PHASE && bits > 20) {
-        delete h;
-        return fail(nullptr, RBE2D_E_INVAL, "k-range too wide for FP32 phases (alpha L too large)");
-    }
-
-    // cell grid: cells >= r_c / reach in x and y (searched +-reach columns),
-    // >= r_c / reach in z; coarsened if there would be too many cells
-    h->reach = 2;
-    h->ncx = std::max(1, (int)std::floor(h->reach * p.Lx / p.r_c));
-    h->ncy = std::max(1, (int)std::floor(h->reach * p.Ly / p.r_c));
-    h->ncz = std::max(1, (int)std::floor(h->reach * p.H / p.r_c));
-    const int64_t cell_cap = std::max<int64_t>(2 * p.n_max, 4096);
-    while ((int64_t)h->ncx * h->ncy * h->ncz > cell_cap && (h->ncx > 5 || h->ncy > 5 || h->ncz > 1)) {
-        if (h->ncz > 1) h->ncz = (h->ncz + 1) / 2;
-        else { h->ncx = std::max(5, h->ncx / 2); h->ncy = std::max(5, h->ncy / 2); }
-    }
-    h->ncells = h->ncx * h->ncy * h->ncz;
+    h->precision = h->sys[0].p.precision;
+    h->P = h->sys[0].p.P;
+    h->P_pad = (h->P + kPPad - 1) / kPPad * kPPad;
+    h->n_cap = n_cap;
+    h->cap_particles = std::max<int64_t>(cap_p, kTileMax);
+    h->cap_sorted = std::max<int64_t>(cap_s, kWave);
+    h->total_cells = cells;
     if (const char *env = std::getenv("RBE2D_REAL_ROUND_MIN")) h->round_min = std::max(1, std::min(64, std::atoi(env)));
-    h->hx = p.Lx / h->ncx; h->hy = p.Ly / h->ncy; h->hz = p.H / h->ncz;
-
     (void)hipGetDevice(&h->device);
-    const int64_t ncap = (std::max<int64_t>(p.n_max, 1) + kTileMax - 1) / kTileMax * kTileMax;
-    h->n_cap = ncap;
-    const int64_t nblk = ncap / kBlock;
+
+    const int64_t cap_blocks = h->cap_particles / kBlock;
     Workspace &w = h->w;
     hipError_t e = hipSuccess;
-    auto A = [&](auto **ptr, size_t n) { if (e == hipSuccess) e = dalloc(h, ptr, n); };
-    A(&w.p32, 2 * ncap);
-    A(&w.p64, ncap);
-    A(&w.bpart, 4 * nblk);
-    A(&w.scal, 16);
-    A(&w.kn32, h->P_pad);
-    A(&w.kn64, h->P_pad);
+    auto A = [&](auto **ptr, size_t cnt) { if (e == hipSuccess) e = dalloc(h, ptr, cnt); };
+    A(&w.sys, n);
+    A(&w.img, n);
+    A(&w.fam, (size_t)n * kMaxFamilies);
+    A(&w.cdf, cdf_total);
+    A(&w.lay.off, n + 1); A(&w.lay.pbase, n + 1); A(&w.lay.bbase, n + 1);
+    A(&w.lay.tbase, n + 1); A(&w.lay.sbase, n + 1);
+    A(&w.p32, 2 * h->cap_particles);
+    A(&w.p64, h->cap_particles);
+    A(&w.bpart, 4 * cap_blocks);
+    A(&w.scal, 8 * (size_t)n);
+    A(&w.kset, 3 * (size_t)n * h->P);
+    A(&w.kn32, (size_t)n * h->P_pad);
+    A(&w.kn64, (size_t)n * h->P_pad);
     double *sfp = nullptr;
-    A(&sfp, (size_t)nblk * h->P_pad * 4);
+    A(&sfp, (size_t)cap_blocks * h->P_pad * 4);
     w.sfpart = sfp;
-    A(&w.krec, (size_t)h->P * kKRec);
-    A(&w.kf32, 2 * (size_t)h->P);
-    A(&w.fpart, (size_t)std::min<int64_t>(64 * ncap, 4096 * kBlock) * 4);
-    A(&w.cell, ncap); A(&w.slot, ncap); A(&w.tmp, ncap); A(&w.sidx, ncap); A(&w.scell, ncap);
-    A(&w.count, h->ncells); A(&w.start, h->ncells + 1); A(&w.scanbuf, h->ncells / 1024 + 2);
-    A(&w.sorted, ncap); A(&w.freal, ncap); A(&w.dgreal, ncap);
-    A(&w.rpart, 3 * nblk);
-    A(&w.fam, std::max<size_t>(1, h->fam.size()));
-    A(&w.img, 1);
+    A(&w.krec, (size_t)n * h->P * kKRec);
+    A(&w.kf32, 2 * (size_t)n * h->P);
+    A(&w.fpart, (size_t)std::min<int64_t>(64 * cap_blocks * kBlock, 4096 * kBlock) * 4);
+    const int64_t nc = std::max<int64_t>(n_cap, 1);
+    A(&w.cell, nc); A(&w.slot, nc); A(&w.tmp, nc);
+    A(&w.count, cells); A(&w.start, cells + 1); A(&w.scanbuf, cells / 1024 + 2);
+    A(&w.sorted, h->cap_sorted); A(&w.sidx, h->cap_sorted); A(&w.scell, h->cap_sorted);
+    A(&w.freal, nc); A(&w.dgreal, nc);
+    A(&w.rpart, 3 * (h->cap_sorted / kWave));
     A(&w.err, 4);
-    A(&w.kset, 3 * (size_t)h->P);
-    for (int d = 0; d < 3; d++) A(&w.cdf[d], h->cdf_host[d].size());
-    if (e == hipSuccess && !h->fam.empty())
-        e = hipMemcpy(w.fam, h->fam.data(), h->fam.size() * sizeof(Family), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(w.img, &img, sizeof img, hipMemcpyHostToDevice);
-    for (int d = 0; d < 3 && e == hipSuccess; d++)
-        e = hipMemcpy(w.cdf[d], h->cdf_host[d].data(), h->cdf_host[d].size() * sizeof(double),
-                      hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipHostMalloc((void **)&h->kstage, 3 * sizeof(int32_t) * h->P, hipHostMallocDefault);
+    A(&w.step, 1);
+    std::vector<SysDesc> descs(n);
+    std::vector<ImgTable> imgs(n);
+    std::vector<Family> fams((size_t)n * kMaxFamilies);
+    std::vector<double> cdf(cdf_total);
+    for (int r = 0; r < n; r++) {
+        descs[r] = h->sys[r].d;
+        imgs[r] = h->sys[r].img;
+        std::copy(h->sys[r].fam.begin(), h->sys[r].fam.end(), fams.begin() + (size_t)r * kMaxFamilies);
+        for (int ax = 0; ax < 3; ax++)
+            std::copy(h->sys[r].cdf[ax].begin(), h->sys[r].cdf[ax].end(), cdf.begin() + descs[r].cdf_off[ax]);
+    }
+    if (e == hipSuccess) e = hipMemcpy(w.sys, descs.data(), n * sizeof(SysDesc), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(w.img, imgs.data(), n * sizeof(ImgTable), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(w.fam, fams.data(), fams.size() * sizeof(Family), hipMemcpyHostToDevice);
+    if (e == hipSuccess && cdf_total)
+        e = hipMemcpy(w.cdf, cdf.data(), cdf_total * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&h->kstage, 3 * sizeof(int32_t) * n * h->P, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&h->lay_stage, 5 * sizeof(int) * (n + 1), hipHostMallocDefault);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&h->kev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->lay_ev, hipEventDisableTiming);
     if (e != hipSuccess) {
         const bool oom = e == hipErrorOutOfMemory;
-        for (void *ptr : h->allocs) (void)hipFree(ptr);
-        if (h->kstage) (void)hipHostFree(h->kstage);
-        if (h->kev) (void)hipEventDestroy(h->kev);
+        free_all(h);
         delete h;
         return fail(nullptr, oom ? RBE2D_E_NOMEM : RBE2D_E_HIP, "workspace setup failed: %s",
                     hipGetErrorString(e));
@@ -290,25 +366,196 @@ rbe2d_status rbe2d_create(const rbe2d_params *pin, rbe2d_handle *out) {
     return RBE2D_OK;
 }
 
+// Particle layout of all systems for the given counts; uploaded (through
+// pinned staging, ordered on the stream) only when it changes.
+rbe2d_status set_layout(rbe2d_ctx *h, const int64_t *counts, hipStream_t s) {
+    const int n = h->n_sys;
+    int64_t total = 0;
+    for (int r = 0; r < n; r++) {
+        if (counts[r] < 0 || counts[r] > h->sys[r].p.n_max)
+            return fail(h, RBE2D_E_INVAL, "system %d: N = %lld outside [0, n_max = %lld]", r,
+                        (long long)counts[r], (long long)h->sys[r].p.n_max);
+        total += counts[r];
+    }
+    const bool fp32 = h->precision == RBE2D_PREC_FP32_PHASE;
+    const int nkc = h->P_pad / (fp32 ? kKChunk32 : kKChunk64);
+    // tile size: enough tiles to fill the chip, padding under ~10% of the particles
+    int per = choose_tile(total, nkc);
+    for (; per > 1; per >>= 1) {
+        int64_t padded = 0;
+        const int64_t tile = (int64_t)kBlock * per;
+        for (int r = 0; r < n; r++) padded += (counts[r] + tile - 1) / tile * tile;
+        if (padded <= total + total / 10 + tile) break;
+    }
+    const int tile = kBlock * per;
+    std::vector<int> lay(5 * (n + 1), 0);
+    int *off = lay.data(), *pb = off + (n + 1), *bb = pb + (n + 1), *tb = bb + (n + 1), *sb = tb + (n + 1);
+    for (int r = 0; r < n; r++) {
+        off[r + 1] = off[r] + (int)counts[r];
+        pb[r + 1] = pb[r] + (int)((counts[r] + tile - 1) / tile * tile);
+        sb[r + 1] = sb[r] + (int)((counts[r] + kWave - 1) / kWave * kWave);
+    }
+    for (int r = 0; r <= n; r++) { bb[r] = pb[r] / kBlock; tb[r] = pb[r] / tile; }
+    h->per = per;
+    h->n_total = total;
+    h->n_blocks = bb[n];
+    h->n_tiles = tb[n];
+    h->n_swaves = sb[n] / kWave;
+    if (h->lay_valid && lay == h->lay_host) return RBE2D_OK;
+    if (h->lay_ev_pending) RBE2D_TRY(h, hipEventSynchronize(h->lay_ev), "layout wait");
+    std::memcpy(h->lay_stage, lay.data(), lay.size() * sizeof(int));
+    int *dst[5] = {h->w.lay.off, h->w.lay.pbase, h->w.lay.bbase, h->w.lay.tbase, h->w.lay.sbase};
+    for (int k = 0; k < 5; k++)
+        RBE2D_TRY(h, hipMemcpyAsync(dst[k], h->lay_stage + k * (n + 1), (n + 1) * sizeof(int),
+                                    hipMemcpyHostToDevice, s), "layout upload");
+    RBE2D_TRY(h, hipEventRecord(h->lay_ev, s), "layout event");
+    h->lay_ev_pending = true;
+    h->lay_host = lay;
+    h->lay_valid = true;
+    return RBE2D_OK;
+}
+
+rbe2d_status layout_from_offsets(rbe2d_ctx *h, const int64_t *offsets, hipStream_t s) {
+    if (!offsets) return fail(h, RBE2D_E_INVAL, "offsets is NULL");
+    if (offsets[0] != 0) return fail(h, RBE2D_E_INVAL, "offsets[0] must be 0");
+    std::vector<int64_t> counts(h->n_sys);
+    for (int r = 0; r < h->n_sys; r++) {
+        counts[r] = offsets[r + 1] - offsets[r];
+        if (counts[r] < 0) return fail(h, RBE2D_E_INVAL, "offsets must be nondecreasing");
+    }
+    return set_layout(h, counts.data(), s);
+}
+
+rbe2d_status check_arrays(rbe2d_ctx *h, const double *pos, const double *q) {
+    if (!h->kset_valid) return fail(h, RBE2D_E_STATE, "no k-set: call rbe2d_set_kset or rbe2d_sample_kset");
+    if (h->n_total > 0 && (!pos || !q)) return fail(h, RBE2D_E_INVAL, "pos or q is NULL");
+    return RBE2D_OK;
+}
+
+// prep + structure factors + real space: everything the outputs depend on
+rbe2d_status run_common(rbe2d_ctx *h, const double *pos, const double *q, uint32_t flags, bool want_dg,
+                        hipStream_t s) {
+    if (flags & (RBE2D_KSPACE | RBE2D_IBC)) RBE2D_TRY(h, launch_prep(h, pos, q, s), "prep launch");
+    if (flags & RBE2D_KSPACE) RBE2D_TRY(h, launch_kcoef_sf(h, s), "structure-factor launch");
+    if (flags & RBE2D_REAL) RBE2D_TRY(h, launch_real(h, pos, q, want_dg, s), "real-space launch");
+    return RBE2D_OK;
+}
+
+rbe2d_status run_forces(rbe2d_ctx *h, const double *pos, const double *q, double *F, double *energy,
+                        uint32_t flags, hipStream_t s) {
+    if (flags & ~(uint32_t)(RBE2D_ALL | RBE2D_ACCUMULATE)) return fail(h, RBE2D_E_INVAL, "unknown flags");
+    rbe2d_status st = check_arrays(h, pos, q);
+    if (st) return st;
+    if (h->n_total > 0 && !F) return fail(h, RBE2D_E_INVAL, "F is NULL");
+    const uint32_t parts = flags & RBE2D_ALL;
+    st = run_common(h, pos, q, parts, false, s);
+    if (st) return st;
+    RBE2D_TRY(h, launch_kforce(h, pos, q, F, nullptr, parts, (flags & RBE2D_ACCUMULATE) != 0, false,
+                               (parts & RBE2D_REAL) != 0, nullptr, s), "force launch");
+    if (energy) RBE2D_TRY(h, launch_energy(h, energy, parts, nullptr, nullptr, s), "energy launch");
+    return RBE2D_OK;
+}
+
+// one velocity-Verlet step; the k-set is drawn with the device step counter
+// when dev_step is set (graph replays), else with stream id `step`
+rbe2d_status md_step(rbe2d_ctx *h, double *pos, double *vel, const double *q, double *F, double dt,
+                     double zlo, double zhi_from_top, uint64_t seed, int64_t step, bool dev_step,
+                     hipStream_t s) {
+    RBE2D_TRY(h, launch_md_kick_drift(h, pos, vel, F, dt, zlo, zhi_from_top, s), "md drift");
+    RBE2D_TRY(h, launch_sample(h, seed, (uint64_t)step * (uint64_t)h->n_sys, dev_step ? h->w.step : nullptr, s),
+              "md sample");
+    rbe2d_status st = run_common(h, pos, q, RBE2D_ALL, false, s);
+    if (st) return st;
+    RBE2D_TRY(h, launch_kforce(h, pos, q, F, nullptr, RBE2D_ALL, false, false, true, nullptr, s), "md force");
+    RBE2D_TRY(h, launch_md_kick(h, vel, F, dt, s), "md kick");
+    if (dev_step) RBE2D_TRY(h, launch_step_inc(h, s), "md step counter");
+    return RBE2D_OK;
+}
+
+// n_steps MD steps, eager or as replays of one captured step
+rbe2d_status md_run(rbe2d_ctx *h, double *pos, double *vel, const double *q, double *F, double dt, double zlo,
+                    double zhi_from_top, uint64_t seed, int64_t step0, int32_t n_steps, bool use_graph,
+                    hipStream_t s) {
+    if (n_steps <= 0) return RBE2D_OK;
+    h->kset_valid = true;
+    if (!use_graph) {
+        for (int32_t it = 0; it < n_steps; it++) {
+            rbe2d_status st = md_step(h, pos, vel, q, F, dt, zlo, zhi_from_top, seed, step0 + it, false, s);
+            if (st) return st;
+        }
+        return RBE2D_OK;
+    }
+    // a captured step is valid for these arguments and this layout only
+    auto bits = [](double x) { uint64_t u; std::memcpy(&u, &x, 8); return u; };
+    std::vector<uint64_t> key = {(uint64_t)(uintptr_t)pos, (uint64_t)(uintptr_t)vel, (uint64_t)(uintptr_t)q,
+                                 (uint64_t)(uintptr_t)F, bits(dt), bits(zlo), bits(zhi_from_top), seed,
+                                 (uint64_t)h->per};
+    key.insert(key.end(), h->lay_host.begin(), h->lay_host.end());
+    if (!h->md_exec || key != h->md_key) {
+        free_graph(h);
+        hipStream_t cs;
+        RBE2D_TRY(h, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "capture stream");
+        const int prof_n = h->prof.n;
+        h->prof.n = 0;   // no profiling events inside the graph
+        hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        rbe2d_status st = RBE2D_OK;
+        if (e == hipSuccess) {
+            st = md_step(h, pos, vel, q, F, dt, zlo, zhi_from_top, seed, 0, true, cs);
+            hipGraph_t g = nullptr;
+            const hipError_t e2 = hipStreamEndCapture(cs, &g);
+            if (st == RBE2D_OK && e2 != hipSuccess) st = hipfail(h, e2, "end capture");
+            if (st == RBE2D_OK) {
+                h->md_graph = g;
+                const hipError_t e3 = hipGraphInstantiate(&h->md_exec, g, nullptr, nullptr, 0);
+                if (e3 != hipSuccess) st = hipfail(h, e3, "graph instantiate");
+            } else if (g) {
+                (void)hipGraphDestroy(g);
+            }
+        } else {
+            st = hipfail(h, e, "begin capture");
+        }
+        h->prof.n = prof_n;
+        (void)hipStreamDestroy(cs);
+        if (st) { free_graph(h); return st; }
+        h->md_key = key;
+    }
+    RBE2D_TRY(h, launch_set_step(h, step0, s), "md step counter");
+    for (int32_t it = 0; it < n_steps; it++) RBE2D_TRY(h, hipGraphLaunch(h->md_exec, s), "graph launch");
+    return RBE2D_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rbe2d_status rbe2d_create(const rbe2d_params *p, rbe2d_handle *out) { return create_handle(1, p, false, out); }
+
+rbe2d_status rbe2d_batch_create(int32_t n_sys, const rbe2d_params *params, rbe2d_handle *out) {
+    return create_handle(n_sys, params, true, out);
+}
+
 void rbe2d_destroy(rbe2d_handle h) {
     if (!h) return;
     int cur = 0;
     (void)hipGetDevice(&cur);
     (void)hipSetDevice(h->device);
     (void)hipDeviceSynchronize();
-    prof_free(h);
-    for (void *p : h->allocs) (void)hipFree(p);
-    if (h->kstage) (void)hipHostFree(h->kstage);
-    if (h->kev) (void)hipEventDestroy(h->kev);
+    free_all(h);
     (void)hipSetDevice(cur);
     delete h;
 }
 
 rbe2d_status rbe2d_query(rbe2d_handle h, double *Lz_ext, double *V, double *S) {
+    return rbe2d_query_system(h, 0, Lz_ext, V, S);
+}
+
+rbe2d_status rbe2d_query_system(rbe2d_handle h, int32_t sys, double *Lz_ext, double *V, double *S) {
     if (!h) return fail(nullptr, RBE2D_E_INVAL, "handle is NULL");
-    if (Lz_ext) *Lz_ext = h->Lz;
-    if (V) *V = h->V;
-    if (S) *S = h->S;
+    if (sys < 0 || sys >= h->n_sys) return fail(h, RBE2D_E_INVAL, "system index out of range");
+    const SysDesc &d = h->sys[sys].d;
+    if (Lz_ext) *Lz_ext = d.Lz;
+    if (V) *V = d.V;
+    if (S) *S = d.S;
     return RBE2D_OK;
 }
 
@@ -342,24 +589,31 @@ rbe2d_status rbe2d_set_kset(rbe2d_handle h, const int32_t *n, int n_is_device, v
     if (!h) return fail(nullptr, RBE2D_E_INVAL, "handle is NULL");
     if (!n) return fail(h, RBE2D_E_INVAL, "n is NULL");
     hipStream_t s = (hipStream_t)stream;
+    const size_t cnt = 3 * (size_t)h->n_sys * h->P;
     if (n_is_device) {
-        RBE2D_TRY(h, hipMemcpyAsync(h->w.kset, n, 3 * sizeof(int32_t) * h->P, hipMemcpyDeviceToDevice, s),
+        RBE2D_TRY(h, hipMemcpyAsync(h->w.kset, n, cnt * sizeof(int32_t), hipMemcpyDeviceToDevice, s),
                   "set_kset copy");
         h->kset_valid = true;
         return RBE2D_OK;
     }
-    const int64_t lim = h->p.precision == RBE2D_PREC_FP32_PHASE ? ((int64_t)1 << (24 - h->fh_bits)) : ((int64_t)1 << 20);
-    for (int l = 0; l < h->P; l++) {
-        if (!(n[3 * l] | n[3 * l + 1] | n[3 * l + 2]))
-            return fail(h, RBE2D_E_INVAL, "k-set entry %d is the zero vector", l);
-        for (int d = 0; d < 3; d++)
-            if (std::llabs((long long)n[3 * l + d]) >= lim)
-                return fail(h, RBE2D_E_INVAL, "k-set entry %d exceeds |n| < %lld", l, (long long)lim);
+    for (int r = 0; r < h->n_sys; r++) {
+        const SysDesc &d = h->sys[r].d;
+        const int64_t lim = h->precision == RBE2D_PREC_FP32_PHASE ? ((int64_t)1 << (24 - d.fh_bits))
+                                                                  : ((int64_t)1 << 20);
+        for (int l = 0; l < h->P; l++) {
+            const int32_t *v = n + 3 * ((size_t)r * h->P + l);
+            if (!(v[0] | v[1] | v[2]))
+                return fail(h, RBE2D_E_INVAL, "k-set entry %d of system %d is the zero vector", l, r);
+            for (int c = 0; c < 3; c++)
+                if (std::llabs((long long)v[c]) >= lim)
+                    return fail(h, RBE2D_E_INVAL, "k-set entry %d of system %d exceeds |n| < %lld", l, r,
+                                (long long)lim);
+        }
     }
     // the pinned staging buffer may still feed the previous upload
     if (h->kev_pending) RBE2D_TRY(h, hipEventSynchronize(h->kev), "set_kset wait");
-    std::memcpy(h->kstage, n, 3 * sizeof(int32_t) * h->P);
-    RBE2D_TRY(h, hipMemcpyAsync(h->w.kset, h->kstage, 3 * sizeof(int32_t) * h->P, hipMemcpyHostToDevice, s),
+    std::memcpy(h->kstage, n, cnt * sizeof(int32_t));
+    RBE2D_TRY(h, hipMemcpyAsync(h->w.kset, h->kstage, cnt * sizeof(int32_t), hipMemcpyHostToDevice, s),
               "set_kset copy");
     RBE2D_TRY(h, hipEventRecord(h->kev, s), "set_kset event");
     h->kev_pending = true;
@@ -369,7 +623,7 @@ rbe2d_status rbe2d_set_kset(rbe2d_handle h, const int32_t *n, int n_is_device, v
 
 rbe2d_status rbe2d_sample_kset(rbe2d_handle h, uint64_t seed, uint64_t stream_id, void *stream) {
     if (!h) return fail(nullptr, RBE2D_E_INVAL, "handle is NULL");
-    RBE2D_TRY(h, launch_sample(h, seed, stream_id, (hipStream_t)stream), "sample_kset launch");
+    RBE2D_TRY(h, launch_sample(h, seed, stream_id, nullptr, (hipStream_t)stream), "sample_kset launch");
     h->kset_valid = true;
     return RBE2D_OK;
 }
@@ -379,99 +633,92 @@ rbe2d_status rbe2d_get_kset(rbe2d_handle h, int32_t *n_host, void *stream) {
     if (!n_host) return fail(h, RBE2D_E_INVAL, "n_host is NULL");
     if (!h->kset_valid) return fail(h, RBE2D_E_STATE, "no k-set");
     hipStream_t s = (hipStream_t)stream;
-    RBE2D_TRY(h, hipMemcpyAsync(n_host, h->w.kset, 3 * sizeof(int32_t) * h->P, hipMemcpyDeviceToHost, s),
+    RBE2D_TRY(h, hipMemcpyAsync(n_host, h->w.kset, 3 * sizeof(int32_t) * h->n_sys * h->P, hipMemcpyDeviceToHost, s),
               "get_kset copy");
     RBE2D_TRY(h, hipStreamSynchronize(s), "get_kset sync");
     return RBE2D_OK;
 }
 
-static rbe2d_status check_call(rbe2d_ctx *h, int64_t N, const double *pos, const double *q) {
+static rbe2d_status single_layout(rbe2d_ctx *h, int64_t N, hipStream_t s) {
     if (!h) return fail(nullptr, RBE2D_E_INVAL, "handle is NULL");
-    if (N < 0 || N > h->p.n_max) return fail(h, RBE2D_E_INVAL, "N = %lld outside [0, n_max = %lld]",
-                                             (long long)N, (long long)h->p.n_max);
-    if (N > 0 && (!pos || !q)) return fail(h, RBE2D_E_INVAL, "pos or q is NULL");
-    if (!h->kset_valid) return fail(h, RBE2D_E_STATE, "no k-set: call rbe2d_set_kset or rbe2d_sample_kset");
-    return RBE2D_OK;
-}
-
-// prep + structure factors + real space: everything the outputs depend on
-static rbe2d_status run_common(rbe2d_ctx *h, int64_t N, const double *pos, const double *q,
-                               uint32_t flags, bool want_dg, hipStream_t s) {
-    const bool fp32 = h->p.precision == RBE2D_PREC_FP32_PHASE;
-    const int nkc = h->P_pad / (fp32 ? kKChunk32 : kKChunk64);
-    const int per = choose_tile(N, nkc);
-    const int64_t tile = (int64_t)kBlock * per;
-    const int64_t N_pad = (N + tile - 1) / tile * tile;
-    if (flags & (RBE2D_KSPACE | RBE2D_IBC))
-        RBE2D_TRY(h, launch_prep(h, N, N_pad, pos, q, s), "prep launch");
-    if (flags & RBE2D_KSPACE) RBE2D_TRY(h, launch_kcoef_sf(h, N_pad, per, s), "structure-factor launch");
-    if (flags & RBE2D_REAL) RBE2D_TRY(h, launch_real(h, N, pos, q, want_dg, s), "real-space launch");
-    return RBE2D_OK;
+    if (h->batch) return fail(h, RBE2D_E_STATE, "batched handle: use the rbe2d_batch_* calls");
+    return set_layout(h, &N, s);
 }
 
 rbe2d_status rbe2d_forces(rbe2d_handle h, int64_t N, const double *pos, const double *q, double *F,
                           double *energy, uint32_t flags, void *stream) {
-    rbe2d_status st = check_call(h, N, pos, q);
-    if (st) return st;
-    if (flags & ~(uint32_t)(RBE2D_ALL | RBE2D_ACCUMULATE)) return fail(h, RBE2D_E_INVAL, "unknown flags");
-    if (N > 0 && !F) return fail(h, RBE2D_E_INVAL, "F is NULL");
     hipStream_t s = (hipStream_t)stream;
-    const uint32_t parts = flags & RBE2D_ALL;
-    st = run_common(h, N, pos, q, parts, false, s);
+    rbe2d_status st = single_layout(h, N, s);
     if (st) return st;
-    RBE2D_TRY(h, launch_kforce(h, N, pos, q, F, nullptr, parts, (flags & RBE2D_ACCUMULATE) != 0, false,
-                               (parts & RBE2D_REAL) != 0, nullptr, s), "force launch");
-    if (energy) RBE2D_TRY(h, launch_energy(h, N, energy, parts, nullptr, nullptr, s), "energy launch");
-    return RBE2D_OK;
+    return run_forces(h, pos, q, F, energy, flags, s);
+}
+
+rbe2d_status rbe2d_batch_forces(rbe2d_handle h, const int64_t *offsets, const double *pos, const double *q,
+                                double *F, double *energy, uint32_t flags, void *stream) {
+    if (!h) return fail(nullptr, RBE2D_E_INVAL, "handle is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    rbe2d_status st = layout_from_offsets(h, offsets, s);
+    if (st) return st;
+    return run_forces(h, pos, q, F, energy, flags, s);
 }
 
 rbe2d_status rbe2d_energy(rbe2d_handle h, int64_t N, const double *pos, const double *q, double *energy,
                           void *stream) {
-    rbe2d_status st = check_call(h, N, pos, q);
+    hipStream_t s = (hipStream_t)stream;
+    rbe2d_status st = single_layout(h, N, s);
     if (st) return st;
     if (!energy) return fail(h, RBE2D_E_INVAL, "energy is NULL");
-    hipStream_t s = (hipStream_t)stream;
-    st = run_common(h, N, pos, q, RBE2D_ALL, false, s);
+    st = check_arrays(h, pos, q);
     if (st) return st;
-    RBE2D_TRY(h, launch_energy(h, N, energy, RBE2D_ALL, nullptr, nullptr, s), "energy launch");
+    st = run_common(h, pos, q, RBE2D_ALL, false, s);
+    if (st) return st;
+    RBE2D_TRY(h, launch_energy(h, energy, RBE2D_ALL, nullptr, nullptr, s), "energy launch");
     return RBE2D_OK;
 }
 
 rbe2d_status rbe2d_energy_backward(rbe2d_handle h, int64_t N, const double *pos, const double *q,
                                    const double *gE, double *dEdr, double *dEdq, double *dEdgamma,
                                    void *stream) {
-    rbe2d_status st = check_call(h, N, pos, q);
+    hipStream_t s = (hipStream_t)stream;
+    rbe2d_status st = single_layout(h, N, s);
     if (st) return st;
     if (!gE) return fail(h, RBE2D_E_INVAL, "gE is NULL");
-    hipStream_t s = (hipStream_t)stream;
-    st = run_common(h, N, pos, q, RBE2D_ALL, dEdgamma != nullptr, s);
+    st = check_arrays(h, pos, q);
+    if (st) return st;
+    st = run_common(h, pos, q, RBE2D_ALL, dEdgamma != nullptr, s);
     if (st) return st;
     if (dEdr || dEdq)
-        RBE2D_TRY(h, launch_kforce(h, N, pos, q, dEdr, dEdq, RBE2D_ALL, false, true, true, gE, s),
-                  "adjoint launch");
-    if (dEdgamma) RBE2D_TRY(h, launch_energy(h, N, nullptr, RBE2D_ALL, gE, dEdgamma, s), "dgamma launch");
+        RBE2D_TRY(h, launch_kforce(h, pos, q, dEdr, dEdq, RBE2D_ALL, false, true, true, gE, s), "adjoint launch");
+    if (dEdgamma) RBE2D_TRY(h, launch_energy(h, nullptr, RBE2D_ALL, gE, dEdgamma, s), "dgamma launch");
     return RBE2D_OK;
 }
 
 rbe2d_status rbe2d_md_run(rbe2d_handle h, int64_t N, double *pos, double *vel, const double *q, double *F,
-                          double dt, double z_lo, double z_hi, uint64_t seed, int64_t step0,
-                          int32_t n_steps, void *stream) {
-    if (!h) return fail(nullptr, RBE2D_E_INVAL, "handle is NULL");
-    if (N < 0 || N > h->p.n_max) return fail(h, RBE2D_E_INVAL, "N outside [0, n_max]");
-    if (N > 0 && (!pos || !vel || !q || !F)) return fail(h, RBE2D_E_INVAL, "NULL array");
-    if (!(dt > 0.0) || !(z_lo > 0.0 && z_lo < z_hi && z_hi < h->p.H) || n_steps < 0)
-        return fail(h, RBE2D_E_INVAL, "need dt > 0, 0 < z_lo < z_hi < H, n_steps >= 0");
+                          double dt, double z_lo, double z_hi, uint64_t seed, int64_t step0, int32_t n_steps,
+                          int32_t use_graph, void *stream) {
     hipStream_t s = (hipStream_t)stream;
-    for (int32_t it = 0; it < n_steps; it++) {
-        RBE2D_TRY(h, launch_md_kick_drift(h, N, pos, vel, F, dt, z_lo, z_hi, s), "md drift");
-        RBE2D_TRY(h, launch_sample(h, seed, (uint64_t)(step0 + it), s), "md sample");
-        h->kset_valid = true;
-        rbe2d_status st = run_common(h, N, pos, q, RBE2D_ALL, false, s);
-        if (st) return st;
-        RBE2D_TRY(h, launch_kforce(h, N, pos, q, F, nullptr, RBE2D_ALL, false, false, true, nullptr, s), "md force");
-        RBE2D_TRY(h, launch_md_kick(h, N, vel, F, dt, s), "md kick");
-    }
-    return RBE2D_OK;
+    rbe2d_status st = single_layout(h, N, s);
+    if (st) return st;
+    const SysHost &sh = h->sys[0];
+    if (N > 0 && (!pos || !vel || !q || !F)) return fail(h, RBE2D_E_INVAL, "NULL array");
+    if (!(dt > 0.0) || !(z_lo > 0.0 && z_lo < z_hi && z_hi < sh.p.H) || n_steps < 0)
+        return fail(h, RBE2D_E_INVAL, "need dt > 0, 0 < z_lo < z_hi < H, n_steps >= 0");
+    return md_run(h, pos, vel, q, F, dt, z_lo, sh.p.H - z_hi, seed, step0, n_steps, use_graph != 0, s);
+}
+
+rbe2d_status rbe2d_batch_md_run(rbe2d_handle h, const int64_t *offsets, double *pos, double *vel, const double *q,
+                                double *F, double dt, double wall_margin, uint64_t seed, int64_t step0,
+                                int32_t n_steps, int32_t use_graph, void *stream) {
+    if (!h) return fail(nullptr, RBE2D_E_INVAL, "handle is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    rbe2d_status st = layout_from_offsets(h, offsets, s);
+    if (st) return st;
+    if (h->n_total > 0 && (!pos || !vel || !q || !F)) return fail(h, RBE2D_E_INVAL, "NULL array");
+    double hmin = h->sys[0].p.H;
+    for (const SysHost &sh : h->sys) hmin = std::min(hmin, sh.p.H);
+    if (!(dt > 0.0) || !(wall_margin > 0.0 && 2 * wall_margin < hmin) || n_steps < 0)
+        return fail(h, RBE2D_E_INVAL, "need dt > 0, 0 < wall_margin < H/2, n_steps >= 0");
+    return md_run(h, pos, vel, q, F, dt, wall_margin, wall_margin, seed, step0, n_steps, use_graph != 0, s);
 }
 
 rbe2d_status rbe2d_profile_enable(rbe2d_handle h, int32_t n_events) {

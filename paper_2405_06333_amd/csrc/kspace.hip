@@ -1,6 +1,8 @@
 // k-space half of RBE2D on gfx950: particle preparation, the N x P
 // structure-factor pass, the FP64 reduction/recalibration per k, the force
-// scatter and the energy reduction.
+// scatter.  Every launch covers all systems of a handle; a block finds its
+// system in the layout tables (particles are padded per system to whole
+// tiles, so blocks never straddle systems and k-data stay wave-uniform).
 //
 // Phases are carried in revolutions: k.r / 2pi = nx fx + ny fy + nz fz with
 // fx = x/Lx wrapped into [0,1), fy = y/Ly, fz = z/Lz_ext.
@@ -20,8 +22,9 @@ namespace rbe2d {
 
 struct PrepArgs {
     const double *pos, *q;
-    int64_t N, N_pad;
-    double Lx, Ly, Lz, H, scale_h;   // scale_h = 2^fh_bits
+    const SysDesc *sys;
+    Layout lay;
+    int n_sys;
     float4 *p32;
     double4 *p64;
     double *bpart;
@@ -31,89 +34,92 @@ struct PrepArgs {
 template <bool FP32>
 __global__ __launch_bounds__(kBlock) void k_prep(PrepArgs a) {
     __shared__ double sh[kBlock / 64];
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int b = blockIdx.x;
+    const int r = find_sys(a.lay.bbase, a.n_sys, b);
+    const SysDesc &d = a.sys[r];
+    const int iloc = (b - a.lay.bbase[r]) * kBlock + threadIdx.x;
+    const int Nr = a.lay.off[r + 1] - a.lay.off[r];
+    const int64_t ii = (int64_t)a.lay.pbase[r] + iloc;      // internal (padded) index
     double sqz = 0.0, sq = 0.0, sq2 = 0.0;
-    if (i < a.N_pad) {
-        double fx = 0, fy = 0, fz = 0, qi = 0;
-        if (i < a.N) {
-            const double x = a.pos[3 * i], y = a.pos[3 * i + 1], z = a.pos[3 * i + 2];
-            qi = a.q[i];
-            if (!(z > 0.0 && z < a.H)) atomicOr(a.err, 1);
-            fx = x / a.Lx; fx -= floor(fx);
-            fy = y / a.Ly; fy -= floor(fy);
-            fz = z / a.Lz;
-            sqz = qi * z; sq = qi; sq2 = qi * qi;
-        }
-        if (FP32) {
-            const double hx = rint(fx * a.scale_h) / a.scale_h;
-            const double hy = rint(fy * a.scale_h) / a.scale_h;
-            const double hz = rint(fz * a.scale_h) / a.scale_h;
-            a.p32[2 * i] = make_float4((float)hx, (float)(fx - hx), (float)hy, (float)(fy - hy));
-            a.p32[2 * i + 1] = make_float4((float)hz, (float)(fz - hz), (float)qi, 0.0f);
-        } else {
-            a.p64[i] = make_double4(fx, fy, fz, qi);
-        }
+    double fx = 0, fy = 0, fz = 0, qi = 0;
+    if (iloc < Nr) {
+        const int64_t g = (int64_t)a.lay.off[r] + iloc;      // caller index
+        const double x = a.pos[3 * g], y = a.pos[3 * g + 1], z = a.pos[3 * g + 2];
+        qi = a.q[g];
+        if (!(z > 0.0 && z < d.H)) atomicOr(a.err, 1);
+        fx = x / d.Lx; fx -= floor(fx);
+        fy = y / d.Ly; fy -= floor(fy);
+        fz = z / d.Lz;
+        sqz = qi * z; sq = qi; sq2 = qi * qi;
     }
-    double t0 = block_sum(sqz, sh);
-    double t1 = block_sum(sq, sh);
-    double t2 = block_sum(sq2, sh);
+    if (FP32) {
+        const double hx = rint(fx * d.scale_h) / d.scale_h;
+        const double hy = rint(fy * d.scale_h) / d.scale_h;
+        const double hz = rint(fz * d.scale_h) / d.scale_h;
+        a.p32[2 * ii] = make_float4((float)hx, (float)(fx - hx), (float)hy, (float)(fy - hy));
+        a.p32[2 * ii + 1] = make_float4((float)hz, (float)(fz - hz), (float)qi, 0.0f);
+    } else {
+        a.p64[ii] = make_double4(fx, fy, fz, qi);
+    }
+    const double t0 = block_sum(sqz, sh);
+    const double t1 = block_sum(sq, sh);
+    const double t2 = block_sum(sq2, sh);
     if (threadIdx.x == 0) {
-        a.bpart[4 * blockIdx.x] = t0;
-        a.bpart[4 * blockIdx.x + 1] = t1;
-        a.bpart[4 * blockIdx.x + 2] = t2;
-        a.bpart[4 * blockIdx.x + 3] = 0.0;
+        a.bpart[4 * b] = t0;
+        a.bpart[4 * b + 1] = t1;
+        a.bpart[4 * b + 2] = t2;
+        a.bpart[4 * b + 3] = 0.0;
     }
 }
 
-// scal layout: 0 mu=sum qz, 1 Q=sum q, 2 sum q^2, 3 muM, 4 fibc, 5 pot_ibc offset,
-//              6 dmuM/dg_top, 7 dmuM/dg_bot
+// scal layout (8 per system): 0 mu = sum q z, 1 Q = sum q, 2 sum q^2,
+// 3 muM (image dipole of Theorem 3.3), 4 F_ibc,z / q_i, 5 offset of the
+// IBC potential, 6 dmuM/dgamma_top, 7 dmuM/dgamma_bot
 struct ScalArgs {
     const double *bpart;
-    int nb;
-    double g1, cgam, dg1t, dg1b, dcgt, dcgb, twopi_over_V, pref;
+    const SysDesc *sys;
+    Layout lay;
     double *scal;
 };
 
 __global__ __launch_bounds__(kBlock) void k_scalars(ScalArgs a) {
     __shared__ double sh[kBlock / 64];
+    const int r = blockIdx.x;
+    const SysDesc &d = a.sys[r];
     double v[3] = {0, 0, 0};
-    for (int b = threadIdx.x; b < a.nb; b += kBlock)
+    for (int b = a.lay.bbase[r] + threadIdx.x; b < a.lay.bbase[r + 1]; b += kBlock)
         for (int c = 0; c < 3; c++) v[c] += a.bpart[4 * b + c];
-    double s0 = block_sum(v[0], sh), s1 = block_sum(v[1], sh), s2 = block_sum(v[2], sh);
+    const double s0 = block_sum(v[0], sh), s1 = block_sum(v[1], sh), s2 = block_sum(v[2], sh);
     if (threadIdx.x == 0) {
         const double mu = s0, Q = s1;
-        const double muM = a.g1 * mu + a.cgam * Q;
-        a.scal[0] = mu;
-        a.scal[1] = Q;
-        a.scal[2] = s2;
-        a.scal[3] = muM;
-        a.scal[4] = -a.twopi_over_V * a.pref * (muM + a.g1 * mu);
-        a.scal[5] = a.twopi_over_V * a.pref * mu * a.cgam;
-        a.scal[6] = a.dg1t * mu + a.dcgt * Q;
-        a.scal[7] = a.dg1b * mu + a.dcgb * Q;
+        const double muM = d.g1 * mu + d.cgam * Q;
+        const double tv = 2.0 * kPi / d.V * d.pref;
+        double *o = a.scal + 8 * r;
+        o[0] = mu;
+        o[1] = Q;
+        o[2] = s2;
+        o[3] = muM;
+        o[4] = -tv * (muM + d.g1 * mu);
+        o[5] = tv * mu * d.cgam;
+        o[6] = d.dg1t * mu + d.dcgt * Q;
+        o[7] = d.dg1b * mu + d.dcgb * Q;
     }
 }
 
-hipError_t launch_prep(rbe2d_ctx *h, int64_t N, int64_t N_pad, const double *pos, const double *q,
-                       hipStream_t s) {
+hipError_t launch_prep(rbe2d_ctx *h, const double *pos, const double *q, hipStream_t s) {
     PrepArgs a;
-    a.pos = pos; a.q = q; a.N = N; a.N_pad = N_pad;
-    a.Lx = h->p.Lx; a.Ly = h->p.Ly; a.Lz = h->Lz; a.H = h->p.H;
-    a.scale_h = ldexp(1.0, h->fh_bits);
+    a.pos = pos; a.q = q; a.sys = h->w.sys; a.lay = h->w.lay; a.n_sys = h->n_sys;
     a.p32 = h->w.p32; a.p64 = h->w.p64; a.bpart = h->w.bpart; a.err = h->w.err;
-    const int nb = (int)((N_pad + kBlock - 1) / kBlock);
     prof_begin(h, 0, s);
-    if (nb > 0) {
-        if (h->p.precision == RBE2D_PREC_FP32_PHASE)
-            hipLaunchKernelGGL(k_prep<true>, dim3(nb), dim3(kBlock), 0, s, a);
+    if (h->n_blocks > 0) {
+        if (h->precision == RBE2D_PREC_FP32_PHASE)
+            hipLaunchKernelGGL(k_prep<true>, dim3(h->n_blocks), dim3(kBlock), 0, s, a);
         else
-            hipLaunchKernelGGL(k_prep<false>, dim3(nb), dim3(kBlock), 0, s, a);
+            hipLaunchKernelGGL(k_prep<false>, dim3(h->n_blocks), dim3(kBlock), 0, s, a);
     }
     ScalArgs b;
-    b.bpart = h->w.bpart; b.nb = nb; b.g1 = h->g1; b.cgam = h->cgam;
-    b.dg1t = h->dg1[0]; b.dg1b = h->dg1[1]; b.dcgt = h->dcgam[0]; b.dcgb = h->dcgam[1];
-    b.twopi_over_V = 2.0 * kPi / h->V; b.pref = h->pref; b.scal = h->w.scal;
-    hipLaunchKernelGGL(k_scalars, dim3(1), dim3(kBlock), 0, s, b);
+    b.bpart = h->w.bpart; b.sys = h->w.sys; b.lay = h->w.lay; b.scal = h->w.scal;
+    hipLaunchKernelGGL(k_scalars, dim3(h->n_sys), dim3(kBlock), 0, s, b);
     prof_end(h, 0, s);
     return hipGetLastError();
 }
@@ -122,13 +128,17 @@ hipError_t launch_prep(rbe2d_ctx *h, int64_t N, int64_t N_pad, const double *pos
 // 2. k-vector table (nx, ny, nz as floats / doubles, padded with zeros)
 // ---------------------------------------------------------------------------
 
-__global__ void k_ktable(const int32_t *kset, int P, int P_pad, float4 *kn32, double4 *kn64) {
-    const int l = blockIdx.x * blockDim.x + threadIdx.x;
-    if (l >= P_pad) return;
+__global__ void k_ktable(const int32_t *kset, int n_sys, int P, int P_pad, float4 *kn32, double4 *kn64) {
+    const int kg = blockIdx.x * blockDim.x + threadIdx.x;
+    if (kg >= n_sys * P_pad) return;
+    const int r = kg / P_pad, l = kg - r * P_pad;
     int nx = 0, ny = 0, nz = 0;
-    if (l < P) { nx = kset[3 * l]; ny = kset[3 * l + 1]; nz = kset[3 * l + 2]; }
-    kn32[l] = make_float4((float)nx, (float)ny, (float)nz, 0.0f);
-    kn64[l] = make_double4((double)nx, (double)ny, (double)nz, 0.0);
+    if (l < P) {
+        const int32_t *n = kset + 3 * ((int64_t)r * P + l);
+        nx = n[0]; ny = n[1]; nz = n[2];
+    }
+    kn32[kg] = make_float4((float)nx, (float)ny, (float)nz, 0.0f);
+    kn64[kg] = make_double4((double)nx, (double)ny, (double)nz, 0.0);
 }
 
 // ---------------------------------------------------------------------------
@@ -140,10 +150,12 @@ __global__ void k_ktable(const int32_t *kset, int P, int P_pad, float4 *kn32, do
 
 template <int KC>
 __global__ __launch_bounds__(kBlock) void k_sf32(const float4 *__restrict__ p32,
-                                                 const float4 *__restrict__ kn, int per_thread,
-                                                 int P_pad, float *__restrict__ part) {
+                                                 const float4 *__restrict__ kn, const int *tbase,
+                                                 int n_sys, int per_thread, int P_pad,
+                                                 float *__restrict__ part) {
     __shared__ float sh[kBlock / 64][64];
-    const int kc0 = blockIdx.y * KC;
+    const int r = find_sys(tbase, n_sys, (int)blockIdx.x);
+    const float4 *knr = kn + (int64_t)r * P_pad + blockIdx.y * KC;
     float acc[4 * KC];
 #pragma unroll
     for (int v = 0; v < 4 * KC; v++) acc[v] = 0.0f;
@@ -154,7 +166,7 @@ __global__ __launch_bounds__(kBlock) void k_sf32(const float4 *__restrict__ p32,
         const float4 b = p32[2 * i + 1];
 #pragma unroll
         for (int kk = 0; kk < KC; kk++) {
-            const float4 n = kn[kc0 + kk];
+            const float4 n = knr[kk];
             float pxy = fractf(n.x * a.x) + fractf(n.y * a.z);
             pxy = fmaf(n.x, a.y, pxy);
             pxy = fmaf(n.y, a.w, pxy);
@@ -174,16 +186,18 @@ __global__ __launch_bounds__(kBlock) void k_sf32(const float4 *__restrict__ p32,
         float t = 0.0f;
 #pragma unroll
         for (int w = 0; w < kBlock / 64; w++) t += sh[w][threadIdx.x];
-        part[((int64_t)blockIdx.x * P_pad + kc0) * 4 + threadIdx.x] = t;
+        part[((int64_t)blockIdx.x * P_pad + blockIdx.y * KC) * 4 + threadIdx.x] = t;
     }
 }
 
 template <int KC>
 __global__ __launch_bounds__(kBlock) void k_sf64(const double4 *__restrict__ p64,
-                                                 const double4 *__restrict__ kn, int per_thread,
-                                                 int P_pad, double *__restrict__ part) {
+                                                 const double4 *__restrict__ kn, const int *tbase,
+                                                 int n_sys, int per_thread, int P_pad,
+                                                 double *__restrict__ part) {
     __shared__ double sh[kBlock / 64][4 * KC];
-    const int kc0 = blockIdx.y * KC;
+    const int r = find_sys(tbase, n_sys, (int)blockIdx.x);
+    const double4 *knr = kn + (int64_t)r * P_pad + blockIdx.y * KC;
     double acc[4 * KC];
 #pragma unroll
     for (int v = 0; v < 4 * KC; v++) acc[v] = 0.0;
@@ -193,7 +207,7 @@ __global__ __launch_bounds__(kBlock) void k_sf64(const double4 *__restrict__ p64
         const double4 a = p64[i];
 #pragma unroll
         for (int kk = 0; kk < KC; kk++) {
-            const double4 n = kn[kc0 + kk];
+            const double4 n = knr[kk];
             const double pxy = fma(n.y, a.y, n.x * a.x);
             const double pz = n.z * a.z;
             double c1, s1, c2, s2;
@@ -213,7 +227,7 @@ __global__ __launch_bounds__(kBlock) void k_sf64(const double4 *__restrict__ p64
         double t = 0.0;
 #pragma unroll
         for (int w = 0; w < kBlock / 64; w++) t += sh[w][threadIdx.x];
-        part[((int64_t)blockIdx.x * P_pad + kc0) * 4 + threadIdx.x] = t;
+        part[((int64_t)blockIdx.x * P_pad + blockIdx.y * KC) * 4 + threadIdx.x] = t;
     }
 }
 
@@ -221,18 +235,18 @@ __global__ __launch_bounds__(kBlock) void k_sf64(const double4 *__restrict__ p64
 // 4. reduce over tiles (FP64, fixed order) and recalibrate (Sec. 3.4):
 //    rho^M = (1 + Y_even) rho + Y_odd rhohat,
 //    A = rho^M + (1 + conj Y_even) rho,  B = conj(Y_odd) rho,
-//    c = 2 pi S pref / (V P |k|^2),  e = c Re(rho conj rho^M).
-//    One wave per k; lanes split the tiles and the image orders.
+//    c = 2 pi S pref / (V P |k|^2),  e = c Re(rho conj(rho^M)).
+//    One wave per (system, k); lanes split the tiles and the image orders.
 // ---------------------------------------------------------------------------
 
 struct AssembleArgs {
     const void *part;
     int fp32_part;
-    int n_tiles, P, P_pad, M;
+    int P, P_pad;
+    const int *tbase;
     const int32_t *kset;
-    const ImgTable *img;      // image weights and exponents (index l-1)
-    double g_top, g_bot;
-    double Lx, Ly, Lz, H, cfac;   // cfac = 2 pi S pref / (V P)
+    const SysDesc *sys;
+    const ImgTable *img;
     double *krec;
     float4 *kf32;
 };
@@ -247,10 +261,12 @@ __device__ __forceinline__ double dmono(int e_self, double g_self, int e_other, 
 }
 
 __global__ __launch_bounds__(64) void k_assemble(AssembleArgs a) {
-    const int l = blockIdx.x;
+    const int r = blockIdx.x / a.P, l = blockIdx.x - r * a.P;
+    const SysDesc &d = a.sys[r];
+    const ImgTable &it = a.img[r];
     const int lane = threadIdx.x;
     double s[4] = {0, 0, 0, 0};
-    for (int t = lane; t < a.n_tiles; t += 64) {
+    for (int t = a.tbase[r] + lane; t < a.tbase[r + 1]; t += 64) {
         const int64_t o = ((int64_t)t * a.P_pad + l) * 4;
         if (a.fp32_part) {
             const float *p = (const float *)a.part;
@@ -262,11 +278,12 @@ __global__ __launch_bounds__(64) void k_assemble(AssembleArgs a) {
     }
     for (int c = 0; c < 4; c++) s[c] = wave_sum(s[c]);
     // Y_odd, Y_even and their gamma derivatives; lane handles order o = lane+1, lane+65, ...
-    const int nx = a.kset[3 * l], ny = a.kset[3 * l + 1], nz = a.kset[3 * l + 2];
-    const double rev_per_H = (double)nz * a.H / a.Lz;   // kz H / (2 pi)
+    const int64_t kg = (int64_t)r * a.P + l;
+    const int nx = a.kset[3 * kg], ny = a.kset[3 * kg + 1], nz = a.kset[3 * kg + 2];
+    const double rev_per_H = (double)nz * d.H / d.Lz;   // kz H / (2 pi)
     double y[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};  // Yo, Ye, dYo/dt, dYe/dt, dYo/db, dYe/db
-    for (int o = lane + 1; o <= a.M; o += 64) {
-        const double gpl = a.img->gp[o - 1], gml = a.img->gm[o - 1];
+    for (int o = lane + 1; o <= d.M; o += 64) {
+        const double gpl = it.gp[o - 1], gml = it.gm[o - 1];
         double mp, mm;   // multiples of kz H in the exponents of the + and - terms
         int slot;
         if (o & 1) { mp = (double)(o + 1); mm = -(double)(o - 1); slot = 0; }
@@ -276,11 +293,10 @@ __global__ __launch_bounds__(64) void k_assemble(AssembleArgs a) {
         sincos_rev64(mm * rev_per_H, &sm, &cm);
         y[slot] += gpl * cp + gml * cm;
         y[slot + 1] += gpl * sp + gml * sm;
-        const ImgTable &it = *a.img;
-        const double dpt = dmono(it.ea_p[o - 1], a.g_top, it.eb_p[o - 1], a.g_bot);
-        const double dmt = dmono(it.ea_m[o - 1], a.g_top, it.eb_m[o - 1], a.g_bot);
-        const double dpb = dmono(it.eb_p[o - 1], a.g_bot, it.ea_p[o - 1], a.g_top);
-        const double dmb = dmono(it.eb_m[o - 1], a.g_bot, it.ea_m[o - 1], a.g_top);
+        const double dpt = dmono(it.ea_p[o - 1], d.g_top, it.eb_p[o - 1], d.g_bot);
+        const double dmt = dmono(it.ea_m[o - 1], d.g_top, it.eb_m[o - 1], d.g_bot);
+        const double dpb = dmono(it.eb_p[o - 1], d.g_bot, it.ea_p[o - 1], d.g_top);
+        const double dmb = dmono(it.eb_m[o - 1], d.g_bot, it.ea_m[o - 1], d.g_top);
         y[4 + slot] += dpt * cp + dmt * cm;
         y[5 + slot] += dpt * sp + dmt * sm;
         y[8 + slot] += dpb * cp + dmb * cm;
@@ -289,9 +305,9 @@ __global__ __launch_bounds__(64) void k_assemble(AssembleArgs a) {
     for (int c = 0; c < 12; c++) y[c] = wave_sum(y[c]);
     if (lane != 0) return;
     const double rr = s[0], ri = s[1], hr = s[2], hi = s[3];
-    const double kx = 2.0 * kPi * nx / a.Lx, ky = 2.0 * kPi * ny / a.Ly, kz = 2.0 * kPi * nz / a.Lz;
+    const double kx = 2.0 * kPi * nx / d.Lx, ky = 2.0 * kPi * ny / d.Ly, kz = 2.0 * kPi * nz / d.Lz;
     const double k2 = kx * kx + ky * ky + kz * kz;
-    const double c = a.cfac / k2;
+    const double c = d.cfac / k2;
     // rho^M = (1 + Ye) rho + Yo rhohat
     const double er = 1.0 + y[2], ei = y[3];
     const double mr = er * rr - ei * ri + y[0] * hr - y[1] * hi;
@@ -305,19 +321,19 @@ __global__ __launch_bounds__(64) void k_assemble(AssembleArgs a) {
     // d e / d gamma = c Re(rho conj(dYe rho + dYo rhohat))
     double de[2];
     for (int w = 0; w < 2; w++) {
-        const double *d = y + 4 + 4 * w;
-        const double tr = d[2] * rr - d[3] * ri + d[0] * hr - d[1] * hi;
-        const double ti = d[2] * ri + d[3] * rr + d[0] * hi + d[1] * hr;
+        const double *dy = y + 4 + 4 * w;
+        const double tr = dy[2] * rr - dy[3] * ri + dy[0] * hr - dy[1] * hi;
+        const double ti = dy[2] * ri + dy[3] * rr + dy[0] * hi + dy[1] * hr;
         de[w] = c * (rr * tr + ri * ti);
     }
-    double *rec = a.krec + (int64_t)l * kKRec;
+    double *rec = a.krec + kg * kKRec;
     rec[0] = kx; rec[1] = ky; rec[2] = kz;
     rec[3] = c * Ar; rec[4] = c * Ai; rec[5] = c * Br; rec[6] = c * Bi;
     rec[7] = e; rec[8] = de[0]; rec[9] = de[1];
     rec[10] = nx; rec[11] = ny; rec[12] = nz;
     rec[13] = rr; rec[14] = ri; rec[15] = 0.0;
-    a.kf32[2 * l] = make_float4((float)kx, (float)ky, (float)kz, 0.0f);
-    a.kf32[2 * l + 1] = make_float4((float)(c * Ar), (float)(c * Ai), (float)(c * Br), (float)(c * Bi));
+    a.kf32[2 * kg] = make_float4((float)kx, (float)ky, (float)kz, 0.0f);
+    a.kf32[2 * kg + 1] = make_float4((float)(c * Ar), (float)(c * Ai), (float)(c * Br), (float)(c * Bi));
 }
 
 int choose_tile(int64_t N, int n_kchunks) {
@@ -332,35 +348,30 @@ int choose_tile(int64_t N, int n_kchunks) {
     return per;
 }
 
-hipError_t launch_kcoef_sf(rbe2d_ctx *h, int64_t N_pad, int per, hipStream_t s) {
-    const bool fp32 = h->p.precision == RBE2D_PREC_FP32_PHASE;
-    hipLaunchKernelGGL(k_ktable, dim3((h->P_pad + 63) / 64), dim3(64), 0, s, h->w.kset, h->P,
+hipError_t launch_kcoef_sf(rbe2d_ctx *h, hipStream_t s) {
+    const bool fp32 = h->precision == RBE2D_PREC_FP32_PHASE;
+    const int nk = h->n_sys * h->P_pad;
+    hipLaunchKernelGGL(k_ktable, dim3((nk + 63) / 64), dim3(64), 0, s, h->w.kset, h->n_sys, h->P,
                        h->P_pad, h->w.kn32, h->w.kn64);
-    const int tile = kBlock * per;
-    const int n_tiles = (int)((N_pad + tile - 1) / tile);
     prof_begin(h, 1, s);
-    if (n_tiles > 0) {
+    if (h->n_tiles > 0) {
         if (fp32) {
-            dim3 g(n_tiles, h->P_pad / kKChunk32);
-            hipLaunchKernelGGL(k_sf32<kKChunk32>, g, dim3(kBlock), 0, s, h->w.p32, h->w.kn32, per,
-                               h->P_pad, (float *)h->w.sfpart);
+            dim3 g(h->n_tiles, h->P_pad / kKChunk32);
+            hipLaunchKernelGGL(k_sf32<kKChunk32>, g, dim3(kBlock), 0, s, h->w.p32, h->w.kn32,
+                               h->w.lay.tbase, h->n_sys, h->per, h->P_pad, (float *)h->w.sfpart);
         } else {
-            dim3 g(n_tiles, h->P_pad / kKChunk64);
-            hipLaunchKernelGGL(k_sf64<kKChunk64>, g, dim3(kBlock), 0, s, h->w.p64, h->w.kn64, per,
-                               h->P_pad, (double *)h->w.sfpart);
+            dim3 g(h->n_tiles, h->P_pad / kKChunk64);
+            hipLaunchKernelGGL(k_sf64<kKChunk64>, g, dim3(kBlock), 0, s, h->w.p64, h->w.kn64,
+                               h->w.lay.tbase, h->n_sys, h->per, h->P_pad, (double *)h->w.sfpart);
         }
     }
     prof_end(h, 1, s);
     AssembleArgs a;
-    a.part = h->w.sfpart; a.fp32_part = fp32; a.n_tiles = n_tiles; a.P = h->P; a.P_pad = h->P_pad;
-    a.M = h->M; a.kset = h->w.kset;
-    a.img = h->w.img;
-    a.g_top = h->p.gamma_top; a.g_bot = h->p.gamma_bot;
-    a.Lx = h->p.Lx; a.Ly = h->p.Ly; a.Lz = h->Lz; a.H = h->p.H;
-    a.cfac = 2.0 * kPi * h->S * h->pref / (h->V * h->P);
+    a.part = h->w.sfpart; a.fp32_part = fp32; a.P = h->P; a.P_pad = h->P_pad;
+    a.tbase = h->w.lay.tbase; a.kset = h->w.kset; a.sys = h->w.sys; a.img = h->w.img;
     a.krec = h->w.krec; a.kf32 = h->w.kf32;
     prof_begin(h, 2, s);
-    hipLaunchKernelGGL(k_assemble, dim3(h->P), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(k_assemble, dim3(h->n_sys * h->P), dim3(64), 0, s, a);
     prof_end(h, 2, s);
     return hipGetLastError();
 }
@@ -378,58 +389,66 @@ struct ForceArgs {
     const double4 *kn64;
     const float4 *kf32;
     const double *krec;
-    int64_t N;
-    int P, k_per_split;
+    Layout lay;
+    const SysDesc *sys;
+    int n_sys, P, P_pad, k_per_split, n_threads;   // n_threads = particle blocks * kBlock
     const double *pos;       // for the IBC potential (z_i)
     const double *q;
     const double *scal;
     const double4 *freal;    // added when add_real
-    double *fpart;           // [split][N][4] when splitting
-    double *F;               // final output (N x 3) when not splitting
-    double *dEdq;            // final dE/dq (N) when want_pot and not splitting
+    double *fpart;           // [split][n_threads][4] when splitting
+    double *F;               // final output (caller order, N x 3)
+    double *dEdq;            // final dE/dq when want_pot
     const double *gE;        // scale of the backward outputs (device scalar) or null
-    double alpha_self;       // -2 alpha pref / sqrt(pi): d E_self / d q_i = alpha_self q_i
     int accumulate, add_real, want_pot, do_kspace, do_ibc, split;
 };
 
-__device__ __forceinline__ void finish_particle(const ForceArgs &a, int64_t i, double fx,
+__device__ __forceinline__ void finish_particle(const ForceArgs &a, int r, int64_t g, double fx,
                                                 double fy, double fz, double pot) {
-    const double qi = a.q[i];
+    const SysDesc &d = a.sys[r];
+    const double *sc = a.scal + 8 * r;
+    const double qi = a.q[g];
     double Fx = 0, Fy = 0, Fz = 0, ph = 0;
     if (a.do_kspace) {
         Fx = -qi * fx; Fy = -qi * fy; Fz = -qi * fz;
-        ph = pot + a.alpha_self * qi;
+        ph = pot - 2.0 * d.alpha * d.pref / sqrt(kPi) * qi;   // + dE_self/dq_i
     }
     if (a.do_ibc) {
-        Fz += qi * a.scal[4];
-        ph += -a.scal[4] * a.pos[3 * i + 2] + a.scal[5];
+        Fz += qi * sc[4];
+        ph += -sc[4] * a.pos[3 * g + 2] + sc[5];
     }
     if (a.add_real) {
-        const double4 r = a.freal[i];
-        Fx += r.x; Fy += r.y; Fz += r.z; ph += r.w;
+        const double4 rr = a.freal[g];
+        Fx += rr.x; Fy += rr.y; Fz += rr.z; ph += rr.w;
     }
     if (a.want_pot) {
         // backward: dL/dr = -gE F, dL/dq = gE phi
-        const double g = a.gE ? *a.gE : 1.0;
+        const double gs = a.gE ? *a.gE : 1.0;
         if (a.F) {
-            a.F[3 * i] = -g * Fx; a.F[3 * i + 1] = -g * Fy; a.F[3 * i + 2] = -g * Fz;
+            a.F[3 * g] = -gs * Fx; a.F[3 * g + 1] = -gs * Fy; a.F[3 * g + 2] = -gs * Fz;
         }
-        if (a.dEdq) a.dEdq[i] = g * ph;
+        if (a.dEdq) a.dEdq[g] = gs * ph;
         return;
     }
     if (a.accumulate) {
-        a.F[3 * i] += Fx; a.F[3 * i + 1] += Fy; a.F[3 * i + 2] += Fz;
+        a.F[3 * g] += Fx; a.F[3 * g + 1] += Fy; a.F[3 * g + 2] += Fz;
     } else {
-        a.F[3 * i] = Fx; a.F[3 * i + 1] = Fy; a.F[3 * i + 2] = Fz;
+        a.F[3 * g] = Fx; a.F[3 * g + 1] = Fy; a.F[3 * g + 2] = Fz;
     }
 }
 
 template <bool WANT_POT>
 __global__ __launch_bounds__(kBlock) void k_force32(ForceArgs a) {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= a.N) return;
-    const float4 pa = a.p32[2 * i];
-    const float4 pb = a.p32[2 * i + 1];
+    const int b = blockIdx.x;
+    const int r = find_sys(a.lay.bbase, a.n_sys, b);
+    const int iloc = (b - a.lay.bbase[r]) * kBlock + threadIdx.x;
+    if (iloc >= a.lay.off[r + 1] - a.lay.off[r]) return;
+    const int64_t ii = (int64_t)a.lay.pbase[r] + iloc;
+    const int64_t g = (int64_t)a.lay.off[r] + iloc;
+    const float4 pa = a.p32[2 * ii];
+    const float4 pb = a.p32[2 * ii + 1];
+    const float4 *kn = a.kn32 + (int64_t)r * a.P_pad;
+    const float4 *kf = a.kf32 + 2 * (int64_t)r * a.P;
     const int l0 = blockIdx.y * a.k_per_split;
     const int l1 = min(a.P, l0 + a.k_per_split);
     double Fx = 0, Fy = 0, Fz = 0, Pt = 0;
@@ -438,9 +457,9 @@ __global__ __launch_bounds__(kBlock) void k_force32(ForceArgs a) {
             const int c1 = min(l1, c0 + 64);
             float fx = 0, fy = 0, fz = 0, pt = 0;
             for (int l = c0; l < c1; l++) {
-                const float4 n = a.kn32[l];
-                const float4 kv = a.kf32[2 * l];
-                const float4 ab = a.kf32[2 * l + 1];
+                const float4 n = kn[l];
+                const float4 kv = kf[2 * l];
+                const float4 ab = kf[2 * l + 1];
                 float pxy = fractf(n.x * pa.x) + fractf(n.y * pa.z);
                 pxy = fmaf(n.x, pa.y, pxy);
                 pxy = fmaf(n.y, pa.w, pxy);
@@ -463,25 +482,31 @@ __global__ __launch_bounds__(kBlock) void k_force32(ForceArgs a) {
         }
     }
     if (a.split) {
-        double *o = a.fpart + ((int64_t)blockIdx.y * a.N + i) * 4;
+        double *o = a.fpart + ((int64_t)blockIdx.y * a.n_threads + (int64_t)b * kBlock + threadIdx.x) * 4;
         o[0] = Fx; o[1] = Fy; o[2] = Fz; o[3] = Pt;
     } else {
-        finish_particle(a, i, Fx, Fy, Fz, Pt);
+        finish_particle(a, r, g, Fx, Fy, Fz, Pt);
     }
 }
 
 template <bool WANT_POT>
 __global__ __launch_bounds__(kBlock) void k_force64(ForceArgs a) {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= a.N) return;
-    const double4 p = a.p64[i];
+    const int b = blockIdx.x;
+    const int r = find_sys(a.lay.bbase, a.n_sys, b);
+    const int iloc = (b - a.lay.bbase[r]) * kBlock + threadIdx.x;
+    if (iloc >= a.lay.off[r + 1] - a.lay.off[r]) return;
+    const int64_t ii = (int64_t)a.lay.pbase[r] + iloc;
+    const int64_t g = (int64_t)a.lay.off[r] + iloc;
+    const double4 p = a.p64[ii];
+    const double4 *kn = a.kn64 + (int64_t)r * a.P_pad;
+    const double *kr = a.krec + (int64_t)r * a.P * kKRec;
     const int l0 = blockIdx.y * a.k_per_split;
     const int l1 = min(a.P, l0 + a.k_per_split);
     double fx = 0, fy = 0, fz = 0, pt = 0;
     if (a.do_kspace) {
         for (int l = l0; l < l1; l++) {
-            const double4 n = a.kn64[l];
-            const double *rec = a.krec + (int64_t)l * kKRec;
+            const double4 n = kn[l];
+            const double *rec = kr + (int64_t)l * kKRec;
             const double pxy = fma(n.y, p.y, n.x * p.x);
             const double pz = n.z * p.z;
             double c1, s1, c2, s2;
@@ -500,50 +525,51 @@ __global__ __launch_bounds__(kBlock) void k_force64(ForceArgs a) {
         }
     }
     if (a.split) {
-        double *o = a.fpart + ((int64_t)blockIdx.y * a.N + i) * 4;
+        double *o = a.fpart + ((int64_t)blockIdx.y * a.n_threads + (int64_t)b * kBlock + threadIdx.x) * 4;
         o[0] = fx; o[1] = fy; o[2] = fz; o[3] = pt;
     } else {
-        finish_particle(a, i, fx, fy, fz, pt);
+        finish_particle(a, r, g, fx, fy, fz, pt);
     }
 }
 
 __global__ __launch_bounds__(kBlock) void k_force_combine(ForceArgs a, int nsplit) {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= a.N) return;
+    const int b = blockIdx.x;
+    const int r = find_sys(a.lay.bbase, a.n_sys, b);
+    const int iloc = (b - a.lay.bbase[r]) * kBlock + threadIdx.x;
+    if (iloc >= a.lay.off[r + 1] - a.lay.off[r]) return;
+    const int64_t g = (int64_t)a.lay.off[r] + iloc;
     double fx = 0, fy = 0, fz = 0, pt = 0;
     for (int sidx = 0; sidx < nsplit; sidx++) {
-        const double *o = a.fpart + ((int64_t)sidx * a.N + i) * 4;
+        const double *o = a.fpart + ((int64_t)sidx * a.n_threads + (int64_t)b * kBlock + threadIdx.x) * 4;
         fx += o[0]; fy += o[1]; fz += o[2]; pt += o[3];
     }
-    finish_particle(a, i, fx, fy, fz, pt);
+    finish_particle(a, r, g, fx, fy, fz, pt);
 }
 
-int choose_ksplit(int64_t N, int P) {
+int choose_ksplit(int64_t nb, int P) {
     // split the k-loop across blocks when there are too few particles to fill the chip
-    const int64_t nb = (N + kBlock - 1) / kBlock;
     int split = 1;
     while (nb * split < 2048 && split * 2 <= 64 && (P + split * 2 - 1) / (split * 2) >= 8) split *= 2;
     return split;
 }
 
-hipError_t launch_kforce(rbe2d_ctx *h, int64_t N, const double *pos, const double *q, double *F,
-                         double *dEdq, uint32_t flags, bool accumulate, bool want_pot,
-                         bool add_real, const double *gE, hipStream_t s) {
-    if (N == 0) return hipSuccess;
+hipError_t launch_kforce(rbe2d_ctx *h, const double *pos, const double *q, double *F, double *dEdq,
+                         uint32_t flags, bool accumulate, bool want_pot, bool add_real, const double *gE,
+                         hipStream_t s) {
+    if (h->n_total == 0) return hipSuccess;
     ForceArgs a;
     a.p32 = h->w.p32; a.p64 = h->w.p64; a.kn32 = h->w.kn32; a.kn64 = h->w.kn64;
-    a.kf32 = h->w.kf32; a.krec = h->w.krec; a.N = N; a.P = h->P;
+    a.kf32 = h->w.kf32; a.krec = h->w.krec; a.lay = h->w.lay; a.sys = h->w.sys;
+    a.n_sys = h->n_sys; a.P = h->P; a.P_pad = h->P_pad; a.n_threads = h->n_blocks * kBlock;
     a.pos = pos; a.q = q; a.scal = h->w.scal; a.freal = h->w.freal;
     a.fpart = h->w.fpart; a.F = F; a.dEdq = dEdq; a.gE = gE;
-    a.alpha_self = -2.0 * h->p.alpha * h->pref / sqrt(kPi);
     a.accumulate = accumulate; a.add_real = add_real; a.want_pot = want_pot;
     a.do_kspace = (flags & RBE2D_KSPACE) != 0; a.do_ibc = (flags & RBE2D_IBC) != 0;
-    const int split = a.do_kspace ? choose_ksplit(N, h->P) : 1;
+    const int split = a.do_kspace ? choose_ksplit(h->n_blocks, h->P) : 1;
     a.k_per_split = (h->P + split - 1) / split;
     a.split = split > 1;
-    const int nb = (int)((N + kBlock - 1) / kBlock);
-    const bool fp32 = h->p.precision == RBE2D_PREC_FP32_PHASE;
-    dim3 g(nb, split);
+    const bool fp32 = h->precision == RBE2D_PREC_FP32_PHASE;
+    dim3 g(h->n_blocks, split);
     prof_begin(h, 5, s);
     if (fp32) {
         if (want_pot) hipLaunchKernelGGL(k_force32<true>, g, dim3(kBlock), 0, s, a);
@@ -552,7 +578,7 @@ hipError_t launch_kforce(rbe2d_ctx *h, int64_t N, const double *pos, const doubl
         if (want_pot) hipLaunchKernelGGL(k_force64<true>, g, dim3(kBlock), 0, s, a);
         else hipLaunchKernelGGL(k_force64<false>, g, dim3(kBlock), 0, s, a);
     }
-    if (a.split) hipLaunchKernelGGL(k_force_combine, dim3(nb), dim3(kBlock), 0, s, a, split);
+    if (a.split) hipLaunchKernelGGL(k_force_combine, dim3(h->n_blocks), dim3(kBlock), 0, s, a, split);
     prof_end(h, 5, s);
     return hipGetLastError();
 }

@@ -1,38 +1,45 @@
-// Energies, the on-device k-sampler and the velocity-Verlet integrator.
+// Energies, the on-device k-sampler and the velocity-Verlet integrator, for
+// all systems of a handle at once.
 #include "devmath.h"
 #include "rbe2d_internal.h"
 
 namespace rbe2d {
 
 // ---------------------------------------------------------------------------
-// energy components {total, real, kspace, self, ibc} and, in backward mode,
-// gE * dE/dgamma_{top,bot}.  One block, fixed summation order.
+// energy components {total, real, kspace, self, ibc} per system and, in
+// backward mode, gE * dE/dgamma_{top,bot}.  One block per system, fixed
+// summation order.
 // ---------------------------------------------------------------------------
 
 struct EnergyArgs {
     const double *krec, *rpart, *scal;
-    int P, n_rblocks;
-    double twopi_over_V, pref, self_coef;   // self_coef = -alpha pref / sqrt(pi)
+    const SysDesc *sys;
+    Layout lay;
+    int P;
     int do_real, do_k, do_ibc, want_dg;
-    double *energy;
+    double *energy;          // 5 per system
     const double *gE;
-    double *dEdgamma;
+    double *dEdgamma;        // 2 per system
 };
 
 __global__ __launch_bounds__(kBlock) void k_energy(EnergyArgs a) {
     __shared__ double sh[kBlock / 64];
+    const int r = blockIdx.x;
+    const SysDesc &d = a.sys[r];
     double ek = 0.0, dkt = 0.0, dkb = 0.0, er = 0.0, drt = 0.0, drb = 0.0;
     if (a.do_k)
         for (int l = threadIdx.x; l < a.P; l += kBlock) {
-            ek += a.krec[(int64_t)l * kKRec + 7];
-            dkt += a.krec[(int64_t)l * kKRec + 8];
-            dkb += a.krec[(int64_t)l * kKRec + 9];
+            const double *rec = a.krec + ((int64_t)r * a.P + l) * kKRec;
+            ek += rec[7];
+            dkt += rec[8];
+            dkb += rec[9];
         }
-    if (a.do_real)
-        for (int b = threadIdx.x; b < a.n_rblocks; b += kBlock) {
-            er += a.rpart[3 * b];
-            drt += a.rpart[3 * b + 1];
-            drb += a.rpart[3 * b + 2];
+    const bool has_real = a.do_real && a.lay.off[r + 1] > a.lay.off[r];
+    if (has_real)
+        for (int wv = a.lay.sbase[r] / kWave + threadIdx.x; wv < a.lay.sbase[r + 1] / kWave; wv += kBlock) {
+            er += a.rpart[3 * wv];
+            drt += a.rpart[3 * wv + 1];
+            drb += a.rpart[3 * wv + 2];
         }
     ek = block_sum(ek, sh);
     er = block_sum(er, sh);
@@ -41,102 +48,128 @@ __global__ __launch_bounds__(kBlock) void k_energy(EnergyArgs a) {
         drt = block_sum(drt, sh); drb = block_sum(drb, sh);
     }
     if (threadIdx.x != 0) return;
-    const double Er = a.do_real ? 0.5 * er : 0.0;
+    const double *sc = a.scal + 8 * r;
+    const double tv = 2.0 * kPi / d.V * d.pref;
+    const double Er = has_real ? 0.5 * er : 0.0;
     const double Ek = a.do_k ? ek : 0.0;
-    const double Es = a.do_k ? a.self_coef * a.scal[2] : 0.0;
-    const double Ei = a.do_ibc ? a.twopi_over_V * a.pref * a.scal[0] * a.scal[3] : 0.0;
+    const double Es = a.do_k ? -d.alpha * d.pref / sqrt(kPi) * sc[2] : 0.0;
+    const double Ei = a.do_ibc ? tv * sc[0] * sc[3] : 0.0;
     if (a.energy) {
-        a.energy[0] = Er + Ek + Es + Ei;
-        a.energy[1] = Er;
-        a.energy[2] = Ek;
-        a.energy[3] = Es;
-        a.energy[4] = Ei;
+        double *o = a.energy + 5 * r;
+        o[0] = Er + Ek + Es + Ei;
+        o[1] = Er;
+        o[2] = Ek;
+        o[3] = Es;
+        o[4] = Ei;
     }
     if (a.want_dg && a.dEdgamma) {
-        const double g = a.gE ? *a.gE : 1.0;
-        const double ibt = a.do_ibc ? a.twopi_over_V * a.pref * a.scal[0] * a.scal[6] : 0.0;
-        const double ibb = a.do_ibc ? a.twopi_over_V * a.pref * a.scal[0] * a.scal[7] : 0.0;
-        a.dEdgamma[0] = g * ((a.do_real ? 0.5 * drt : 0.0) + (a.do_k ? dkt : 0.0) + ibt);
-        a.dEdgamma[1] = g * ((a.do_real ? 0.5 * drb : 0.0) + (a.do_k ? dkb : 0.0) + ibb);
+        const double g = a.gE ? a.gE[r] : 1.0;
+        const double ibt = a.do_ibc ? tv * sc[0] * sc[6] : 0.0;
+        const double ibb = a.do_ibc ? tv * sc[0] * sc[7] : 0.0;
+        a.dEdgamma[2 * r] = g * ((has_real ? 0.5 * drt : 0.0) + (a.do_k ? dkt : 0.0) + ibt);
+        a.dEdgamma[2 * r + 1] = g * ((has_real ? 0.5 * drb : 0.0) + (a.do_k ? dkb : 0.0) + ibb);
     }
 }
 
-hipError_t launch_energy(rbe2d_ctx *h, int64_t N, double *energy, uint32_t flags,
-                         const double *gE, double *dEdgamma, hipStream_t s) {
+hipError_t launch_energy(rbe2d_ctx *h, double *energy, uint32_t flags, const double *gE, double *dEdgamma,
+                         hipStream_t s) {
     EnergyArgs a;
-    a.krec = h->w.krec; a.rpart = h->w.rpart; a.scal = h->w.scal; a.P = h->P;
-    a.n_rblocks = (int)((N + kBlock - 1) / kBlock);
-    a.twopi_over_V = 2.0 * kPi / h->V; a.pref = h->pref;
-    a.self_coef = -h->p.alpha * h->pref / sqrt(kPi);
-    a.do_real = (flags & RBE2D_REAL) && N > 0;
+    a.krec = h->w.krec; a.rpart = h->w.rpart; a.scal = h->w.scal; a.sys = h->w.sys; a.lay = h->w.lay;
+    a.P = h->P;
+    a.do_real = (flags & RBE2D_REAL) != 0;
     a.do_k = (flags & RBE2D_KSPACE) != 0;
     a.do_ibc = (flags & RBE2D_IBC) != 0;
     a.want_dg = dEdgamma != nullptr;
     a.energy = energy; a.gE = gE; a.dEdgamma = dEdgamma;
     prof_begin(h, 6, s);
-    hipLaunchKernelGGL(k_energy, dim3(1), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_energy, dim3(h->n_sys), dim3(kBlock), 0, s, a);
     prof_end(h, 6, s);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// on-device k-sampler: the same draws as the host sampler in api.hip
+// on-device k-sampler: the same draws as the host sampler in api.hip; the
+// k-set of system r uses stream id (stream_base + r), where stream_base is
+// the argument or, for graph replays, n_sys times a device step counter
 // ---------------------------------------------------------------------------
 
 struct SampleArgs {
-    const double *cdf0, *cdf1, *cdf2;
-    int nm0, nm1, nm2, P;
-    uint64_t key;
+    const double *cdf;
+    const SysDesc *sys;
+    int n_sys, P;
+    uint64_t seed, stream_base;
+    const long long *dev_step;   // if set: stream_base = n_sys * (*dev_step)
     int32_t *kset;
     int *err;
 };
 
 __global__ void k_sample(SampleArgs a) {
-    const int l = blockIdx.x * blockDim.x + threadIdx.x;
-    if (l >= a.P) return;
+    const int kg = blockIdx.x * blockDim.x + threadIdx.x;
+    if (kg >= a.n_sys * a.P) return;
+    const int r = kg / a.P, l = kg - r * a.P;
+    const SysDesc &d = a.sys[r];
+    const uint64_t base = a.dev_step ? (uint64_t)(*a.dev_step) * (uint64_t)a.n_sys : a.stream_base;
+    const uint64_t key = stream_key(a.seed, base + (uint64_t)r);
     for (int att = 0; att < 64; att++) {
         const uint64_t c = ((uint64_t)l * 64 + att) * 3;
-        const int nx = draw_axis(a.cdf0, a.nm0, uniform01(a.key, c));
-        const int ny = draw_axis(a.cdf1, a.nm1, uniform01(a.key, c + 1));
-        const int nz = draw_axis(a.cdf2, a.nm2, uniform01(a.key, c + 2));
+        const int nx = draw_axis(a.cdf + d.cdf_off[0], d.nmax[0], uniform01(key, c));
+        const int ny = draw_axis(a.cdf + d.cdf_off[1], d.nmax[1], uniform01(key, c + 1));
+        const int nz = draw_axis(a.cdf + d.cdf_off[2], d.nmax[2], uniform01(key, c + 2));
         if (nx | ny | nz) {
-            a.kset[3 * l] = nx; a.kset[3 * l + 1] = ny; a.kset[3 * l + 2] = nz;
+            a.kset[3 * kg] = nx; a.kset[3 * kg + 1] = ny; a.kset[3 * kg + 2] = nz;
             return;
         }
     }
-    a.kset[3 * l] = 1; a.kset[3 * l + 1] = 0; a.kset[3 * l + 2] = 0;
+    a.kset[3 * kg] = 1; a.kset[3 * kg + 1] = 0; a.kset[3 * kg + 2] = 0;
     atomicOr(a.err, 2);
 }
 
-hipError_t launch_sample(rbe2d_ctx *h, uint64_t seed, uint64_t stream_id, hipStream_t s) {
+hipError_t launch_sample(rbe2d_ctx *h, uint64_t seed, uint64_t stream_id, const long long *dev_step,
+                         hipStream_t s) {
     SampleArgs a;
-    a.cdf0 = h->w.cdf[0]; a.cdf1 = h->w.cdf[1]; a.cdf2 = h->w.cdf[2];
-    a.nm0 = h->nmax[0]; a.nm1 = h->nmax[1]; a.nm2 = h->nmax[2]; a.P = h->P;
-    a.key = stream_key(seed, stream_id);
+    a.cdf = h->w.cdf; a.sys = h->w.sys; a.n_sys = h->n_sys; a.P = h->P;
+    a.seed = seed; a.stream_base = stream_id; a.dev_step = dev_step;
     a.kset = h->w.kset; a.err = h->w.err;
+    const int n = h->n_sys * h->P;
     prof_begin(h, 8, s);
-    hipLaunchKernelGGL(k_sample, dim3((h->P + 63) / 64), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(k_sample, dim3((n + 63) / 64), dim3(64), 0, s, a);
     prof_end(h, 8, s);
     return hipGetLastError();
 }
 
+__global__ void k_set_step(long long *step, long long v) { *step = v; }
+__global__ void k_step_inc(long long *step) { *step += 1; }
+
+hipError_t launch_set_step(rbe2d_ctx *h, long long value, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_step, dim3(1), dim3(1), 0, s, h->w.step, value);
+    return hipGetLastError();
+}
+hipError_t launch_step_inc(rbe2d_ctx *h, hipStream_t s) {
+    hipLaunchKernelGGL(k_step_inc, dim3(1), dim3(1), 0, s, h->w.step);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
-// velocity Verlet with unit masses; x, y periodic, z reflected at zlo, zhi
+// velocity Verlet with unit masses; x, y periodic, z reflected at the walls
+// zlo and H - zhi_from_top of each system
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(kBlock) void k_kick_drift(int64_t N, double *pos, double *vel,
-                                                       const double *F, double dt, double Lx,
-                                                       double Ly, double zlo, double zhi) {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= N) return;
+__global__ __launch_bounds__(kBlock) void k_kick_drift(const SysDesc *sys, Layout lay, int n_sys, int n_total,
+                                                       double *pos, double *vel, const double *F, double dt,
+                                                       double zlo, double zhi_from_top) {
+    const int g = blockIdx.x * kBlock + threadIdx.x;
+    if (g >= n_total) return;
+    const SysDesc &d = sys[find_sys(lay.off, n_sys, g)];
+    const int64_t i = g;
     double v[3], r[3];
-    for (int d = 0; d < 3; d++) {
-        v[d] = fma(0.5 * dt, F[3 * i + d], vel[3 * i + d]);
-        r[d] = fma(dt, v[d], pos[3 * i + d]);
+    for (int c = 0; c < 3; c++) {
+        v[c] = fma(0.5 * dt, F[3 * i + c], vel[3 * i + c]);
+        r[c] = fma(dt, v[c], pos[3 * i + c]);
     }
-    r[0] -= Lx * floor(r[0] / Lx);
-    r[1] -= Ly * floor(r[1] / Ly);
+    r[0] -= d.Lx * floor(r[0] / d.Lx);
+    r[1] -= d.Ly * floor(r[1] / d.Ly);
     // fold z into [zlo, zhi]: every crossing of a wall is a specular reflection
+    const double zhi = d.H - zhi_from_top;
     const double W = zhi - zlo;
     const double u = r[2] - zlo;
     const double m = floor(u / W);
@@ -145,36 +178,33 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(int64_t N, double *pos, d
     r[2] = odd ? zhi - rem : zlo + rem;
     if (odd) v[2] = -v[2];
     r[2] = fmin(fmax(r[2], zlo), zhi);
-    for (int d = 0; d < 3; d++) {
-        vel[3 * i + d] = v[d];
-        pos[3 * i + d] = r[d];
+    for (int c = 0; c < 3; c++) {
+        vel[3 * i + c] = v[c];
+        pos[3 * i + c] = r[c];
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_kick(int64_t N, double *vel, const double *F,
-                                                 double dt) {
+__global__ __launch_bounds__(kBlock) void k_kick(int64_t n3, double *vel, const double *F, double dt) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= 3 * N) return;
+    if (i >= n3) return;
     vel[i] = fma(0.5 * dt, F[i], vel[i]);
 }
 
-hipError_t launch_md_kick_drift(rbe2d_ctx *h, int64_t N, double *pos, double *vel,
-                                const double *F, double dt, double zlo, double zhi,
-                                hipStream_t s) {
-    if (N == 0) return hipSuccess;
+hipError_t launch_md_kick_drift(rbe2d_ctx *h, double *pos, double *vel, const double *F, double dt,
+                                double zlo, double zhi_from_top, hipStream_t s) {
+    if (h->n_total == 0) return hipSuccess;
     prof_begin(h, 7, s);
-    hipLaunchKernelGGL(k_kick_drift, dim3((unsigned)((N + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
-                       N, pos, vel, F, dt, h->p.Lx, h->p.Ly, zlo, zhi);
+    hipLaunchKernelGGL(k_kick_drift, dim3((unsigned)((h->n_total + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                       h->w.sys, h->w.lay, h->n_sys, (int)h->n_total, pos, vel, F, dt, zlo, zhi_from_top);
     prof_end(h, 7, s);
     return hipGetLastError();
 }
 
-hipError_t launch_md_kick(rbe2d_ctx *h, int64_t N, double *vel, const double *F, double dt,
-                          hipStream_t s) {
-    if (N == 0) return hipSuccess;
+hipError_t launch_md_kick(rbe2d_ctx *h, double *vel, const double *F, double dt, hipStream_t s) {
+    if (h->n_total == 0) return hipSuccess;
+    const int64_t n3 = 3 * h->n_total;
     prof_begin(h, 7, s);
-    hipLaunchKernelGGL(k_kick, dim3((unsigned)((3 * N + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
-                       N, vel, F, dt);
+    hipLaunchKernelGGL(k_kick, dim3((unsigned)((n3 + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, n3, vel, F, dt);
     prof_end(h, 7, s);
     return hipGetLastError();
 }

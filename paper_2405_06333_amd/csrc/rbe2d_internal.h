@@ -1,5 +1,11 @@
-// Internal declarations of librbe2d: the handle, device helpers and the
-// kernel launchers shared by the translation units of the library.
+// Internal declarations of librbe2d: the handle, the per-system descriptor
+// tables, device helpers and the kernel launchers shared by the translation
+// units of the library.
+//
+// A handle holds n_sys >= 1 independent slabs ("systems").  A single-system
+// handle is a batch of one.  Every kernel finds the system of its block (or
+// wave) in small layout tables, so one launch of each kernel covers all
+// systems of a batch.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -18,7 +24,8 @@ constexpr int kTileMax = kBlock * kMaxTileThreads;
 constexpr int kKChunk32 = 16;        // k-vectors per structure-factor block, FP32 phases
 constexpr int kKChunk64 = 8;         // k-vectors per structure-factor block, FP64
 constexpr int kPPad = 16;            // P is padded to a multiple of this
-constexpr int kMaxFamilies = 128;    // real-space image families (order, side)
+constexpr int kMaxFamilies = 128;    // real-space image families (order, side) per system
+constexpr int kWave = 64;
 constexpr double kPi = 3.14159265358979323846;
 
 // One family of image sources for the real-space sum, seen from the target:
@@ -38,11 +45,34 @@ struct ImgTable {
     int ea_p[64], eb_p[64], ea_m[64], eb_m[64];
 };
 
+// Parameters and derived constants of one system (device copy).
+struct SysDesc {
+    double Lx, Ly, H, Lz, V, S, alpha, rc, rc2, pref;
+    double g_top, g_bot;
+    double g1, cgam, dg1t, dg1b, dcgt, dcgb;   // IBC image-dipole coefficients
+    double cfac;                               // 2 pi S pref / (V P)
+    double scale_h;                            // 2^fh_bits (FP32 phase split)
+    double hx, hy, hz, inv_hy, inv_hz;         // cell sizes
+    int ncx, ncy, ncz, reach, nfam, M, fh_bits, cbase;
+    int nmax[3], cdf_off[3];                   // sampler tables in the shared CDF array
+};
+
 // Per-k record written by the reduce/assemble kernel (FP64):
 //   [0..2] kx, ky, kz      [3..6] c*A (re, im), c*B (re, im)
 //   [7] e_l = c Re(rho conj(rho^M))   [8..9] d e_l / d gamma_{top,bot}
-//   [10..12] nx, ny, nz (as doubles)  [13..15] unused
+//   [10..12] nx, ny, nz (as doubles)  [13..14] rho (re, im)
 constexpr int kKRec = 16;
+
+// Layout of the particles of all systems in the internal arrays (device
+// copies, n_sys + 1 entries each, prefix form: entry r is the start of
+// system r, entry n_sys the total).
+struct Layout {
+    int *off = nullptr;     // caller particle offsets
+    int *pbase = nullptr;   // padded k-space particle offsets (multiples of the tile)
+    int *bbase = nullptr;   // pbase / kBlock: particle blocks
+    int *tbase = nullptr;   // pbase / tile: structure-factor tiles
+    int *sbase = nullptr;   // padded real-space offsets (multiples of a wave)
+};
 
 // HIP-event timing of kernel classes (rbe2d_profile_enable / _read)
 struct Profiler {
@@ -52,93 +82,125 @@ struct Profiler {
 };
 
 struct Workspace {
-    // particles (padded to a multiple of kTileMax)
+    SysDesc *sys = nullptr;
+    ImgTable *img = nullptr;
+    Family *fam = nullptr;      // kMaxFamilies per system
+    double *cdf = nullptr;      // sampler tables of all systems
+    Layout lay;
+    // particles (k-space arrays padded per system to whole tiles)
     float4 *p32 = nullptr;      // 2 per particle: (fxh, fxl, fyh, fyl), (fzh, fzl, q, 0)
     double4 *p64 = nullptr;     // 1 per particle: (fx, fy, fz, q)
-    double *bpart = nullptr;    // per prep block: sum q z, sum q, sum q^2, 0
-    double *scal = nullptr;     // scalars, see kspace.hip
-    // k-space
+    double *bpart = nullptr;    // per particle block: sum q z, sum q, sum q^2, 0
+    double *scal = nullptr;     // 8 scalars per system, see kspace.hip
+    // k-space (P_pad k-vectors per system)
+    int32_t *kset = nullptr;    // n_sys x P x 3
     float4 *kn32 = nullptr;     // per k: (nx, ny, nz, 0) as floats
     double4 *kn64 = nullptr;    // per k: (nx, ny, nz, 0) as doubles
     void *sfpart = nullptr;     // structure-factor partials [tile][P_pad][4] (float or double)
-    double *krec = nullptr;     // per-k records, kKRec doubles each
+    double *krec = nullptr;     // per-k records, kKRec doubles each (n_sys x P)
     float4 *kf32 = nullptr;     // per k: (kx, ky, kz, 0), (cAr, cAi, cBr, cBi)
-    double *fpart = nullptr;    // force-pass partials [ksplit][N][4]
+    double *fpart = nullptr;    // force-pass partials [ksplit][blocks * kBlock][4]
     // real space
     int *cell = nullptr, *slot = nullptr, *count = nullptr, *start = nullptr, *tmp = nullptr;
     int *scanbuf = nullptr;     // per-scan-block totals of the cell counts
-    double4 *sorted = nullptr;  // (x, y, z, q) in cell order, x relative to the cell's x edge
-    int *sidx = nullptr;        // original index of sorted particle
-    int *scell = nullptr;       // cell of sorted particle
-    double4 *freal = nullptr;   // per original particle: F_real (x, y, z), phi_real
-    double2 *dgreal = nullptr;  // per original particle: d phi_real / d gamma_{top,bot}
-    double *rpart = nullptr;    // per real-space block: sum q phi, sum q dphi/dg_top, .../dg_bot
-    Family *fam = nullptr;      // image families (device copy)
-    ImgTable *img = nullptr;    // image weights (device copy)
+    double4 *sorted = nullptr;  // (x - x0(cell), y, z, q) in cell order, padded per system
+    int *sidx = nullptr;        // caller index of sorted particle
+    int *scell = nullptr;       // local cell of sorted particle
+    double4 *freal = nullptr;   // per caller particle: F_real (x, y, z), phi_real
+    double2 *dgreal = nullptr;  // per caller particle: d phi_real / d gamma_{top,bot}
+    double *rpart = nullptr;    // per real-space wave: sum q phi, sum q dphi/dg_top, .../dg_bot
     int *err = nullptr;         // device error word
-    int32_t *kset = nullptr;    // P x 3
-    double *cdf[3] = {nullptr, nullptr, nullptr};
+    long long *step = nullptr;  // device MD step counter (graph replays)
+};
+
+// Host copy of one system's setup.
+struct SysHost {
+    rbe2d_params p{};
+    SysDesc d{};
+    ImgTable img{};
+    std::vector<Family> fam;
+    std::vector<std::vector<double>> cdf;   // per axis
 };
 
 }  // namespace rbe2d
 
 struct rbe2d_ctx {
-    rbe2d_params p{};
-    double Lz = 0, V = 0, S = 0, pref = 1;
+    int n_sys = 1;
+    bool batch = false;
+    int precision = RBE2D_PREC_FP64;
+    int P = 0, P_pad = 0;
     int device = 0;
-    int M = 0, P = 0, P_pad = 0;
-    std::vector<double> gp, gm;      // image weights, index l-1
-    double g1 = 1.0;                 // dw/dz = 1 + sum_l (-1)^l (g+ + g-)
-    double cgam = 0.0;               // sum_l (2 ceil(l/2) H g+ - 2 floor(l/2) H g-)
-    double dg1[2] = {0, 0}, dcgam[2] = {0, 0};   // their gamma derivatives
-    int nmax[3] = {0, 0, 0};
-    int fh_bits = 12;                // fraction bits of the FP32 phase split
-    std::vector<std::vector<double>> cdf_host;
-    bool kset_valid = false;
-    int64_t n_cap = 0;               // padded particle capacity
-    int n_tiles_cap = 0;
-    // cell grid
-    int ncx = 1, ncy = 1, ncz = 1, ncells = 1;
-    int reach = 2;                   // neighbour columns on each side; cells >= r_c / reach
+    std::vector<rbe2d::SysHost> sys;
+    int64_t n_cap = 0;               // caller particles (sum of n_max)
+    int64_t cap_particles = 0;       // padded k-space capacity (all systems)
+    int64_t cap_sorted = 0;          // padded real-space capacity
+    int total_cells = 0;
     int round_min = 40;              // real space: drain pair queues while >= this many lanes hold work
-    double hx = 0, hy = 0, hz = 0;
-    std::vector<rbe2d::Family> fam;
+    bool kset_valid = false;
+    // current layout (host mirror); a layout is uploaded when it changes
+    std::vector<int> lay_host;       // 5 x (n_sys + 1): off, pbase, bbase, tbase, sbase
+    bool lay_valid = false;
+    int per = 0;                     // particles per thread of the structure-factor tiles
+    int64_t n_total = 0;
+    int n_blocks = 0, n_tiles = 0, n_swaves = 0;
+    int *lay_stage = nullptr;        // pinned staging of layout uploads
+    hipEvent_t lay_ev = nullptr;
+    bool lay_ev_pending = false;
     rbe2d::Workspace w;
     std::vector<void *> allocs;
     int32_t *kstage = nullptr;       // pinned staging of host k-set uploads
     hipEvent_t kev = nullptr;        // completion of the last upload from kstage
     bool kev_pending = false;
+    // cached graph of one MD step
+    hipGraphExec_t md_exec = nullptr;
+    hipGraph_t md_graph = nullptr;
+    std::vector<uint64_t> md_key;    // arguments and layout the graph was captured for
     rbe2d::Profiler prof;
     std::string err;
 };
 
 namespace rbe2d {
 
-// kernel launchers (return hipSuccess or the launch error)
-hipError_t launch_prep(rbe2d_ctx *h, int64_t N, int64_t N_pad, const double *pos, const double *q,
-                       hipStream_t s);
-hipError_t launch_kcoef_sf(rbe2d_ctx *h, int64_t N_pad, int tile, hipStream_t s);
-hipError_t launch_kforce(rbe2d_ctx *h, int64_t N, const double *pos, const double *q, double *F,
-                         double *dEdq, uint32_t flags, bool accumulate, bool want_pot,
-                         bool add_real, const double *gE, hipStream_t s);
-hipError_t launch_real(rbe2d_ctx *h, int64_t N, const double *pos, const double *q, bool want_dg,
-                       hipStream_t s);
-hipError_t launch_energy(rbe2d_ctx *h, int64_t N, double *energy, uint32_t flags,
-                         const double *gE, double *dEdgamma, hipStream_t s);
-hipError_t launch_sample(rbe2d_ctx *h, uint64_t seed, uint64_t stream_id, hipStream_t s);
-hipError_t launch_md_kick_drift(rbe2d_ctx *h, int64_t N, double *pos, double *vel,
-                                const double *F, double dt, double zlo, double zhi,
-                                hipStream_t s);
-hipError_t launch_md_kick(rbe2d_ctx *h, int64_t N, double *vel, const double *F, double dt,
-                          hipStream_t s);
+// kernel launchers (return hipSuccess or the launch error); all systems at once
+hipError_t launch_prep(rbe2d_ctx *h, const double *pos, const double *q, hipStream_t s);
+hipError_t launch_kcoef_sf(rbe2d_ctx *h, hipStream_t s);
+hipError_t launch_kforce(rbe2d_ctx *h, const double *pos, const double *q, double *F, double *dEdq,
+                         uint32_t flags, bool accumulate, bool want_pot, bool add_real, const double *gE,
+                         hipStream_t s);
+hipError_t launch_real(rbe2d_ctx *h, const double *pos, const double *q, bool want_dg, hipStream_t s);
+hipError_t launch_energy(rbe2d_ctx *h, double *energy, uint32_t flags, const double *gE, double *dEdgamma,
+                         hipStream_t s);
+hipError_t launch_sample(rbe2d_ctx *h, uint64_t seed, uint64_t stream_id, const long long *dev_step,
+                         hipStream_t s);
+hipError_t launch_md_kick_drift(rbe2d_ctx *h, double *pos, double *vel, const double *F, double dt,
+                                double zlo, double zhi_from_top, hipStream_t s);
+hipError_t launch_md_kick(rbe2d_ctx *h, double *vel, const double *F, double dt, hipStream_t s);
+hipError_t launch_set_step(rbe2d_ctx *h, long long value, hipStream_t s);
+hipError_t launch_step_inc(rbe2d_ctx *h, hipStream_t s);
 hipError_t launch_fill(void *p, int64_t nbytes_multiple_of_4, hipStream_t s);
 
-// bracket a launch of kernel class `slot` with profiling events (no-op when off)
-inline void prof_begin(rbe2d_ctx *h, int slot, hipStream_t s);
-inline void prof_end(rbe2d_ctx *h, int slot, hipStream_t s);
+int choose_tile(int64_t N_total, int n_kchunks);
+int choose_ksplit(int64_t n_blocks, int P);
 
-int choose_tile(int64_t N, int n_kchunks);
-int choose_ksplit(int64_t N, int P);
+// bracket a launch of kernel class `slot` with profiling events (no-op when off)
+inline void prof_begin(rbe2d_ctx *h, int slot, hipStream_t s) {
+    Profiler &p = h->prof;
+    if (p.n > 0 && p.used[slot] < p.n) (void)hipEventRecord(p.ev[slot][0][p.used[slot]], s);
+}
+inline void prof_end(rbe2d_ctx *h, int slot, hipStream_t s) {
+    Profiler &p = h->prof;
+    if (p.n > 0 && p.used[slot] < p.n) (void)hipEventRecord(p.ev[slot][1][p.used[slot]++], s);
+}
+
+// Largest r in [0, n) with a[r] <= x, for a nondecreasing prefix array a[0..n].
+__host__ __device__ inline int find_sys(const int *a, int n, int x) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (a[mid] <= x) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
 
 // SplitMix64 stream used by the host and device k-samplers.
 __host__ __device__ inline uint64_t mix64(uint64_t z) {
@@ -161,15 +223,6 @@ __host__ __device__ inline int draw_axis(const double *cdf, int nmax, double u) 
         if (u < cdf[mid]) hi = mid; else lo = mid + 1;
     }
     return lo - nmax;
-}
-
-inline void prof_begin(rbe2d_ctx *h, int slot, hipStream_t s) {
-    Profiler &p = h->prof;
-    if (p.n > 0 && p.used[slot] < p.n) (void)hipEventRecord(p.ev[slot][0][p.used[slot]], s);
-}
-inline void prof_end(rbe2d_ctx *h, int slot, hipStream_t s) {
-    Profiler &p = h->prof;
-    if (p.n > 0 && p.used[slot] < p.n) (void)hipEventRecord(p.ev[slot][1][p.used[slot]++], s);
 }
 
 }  // namespace rbe2d

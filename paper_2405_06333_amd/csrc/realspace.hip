@@ -1,11 +1,13 @@
-// Real-space half of RBE2D on gfx950 (Eq. (3.12)): a cell list over the
+// Real-space half of RBE2D on gfx950 (Eq. (3.12)): a cell list over each
 // slab built by counting sort with a deterministic in-cell order, and the
 // erfc pair sum over real charges and truncated image charges within r_c.
+// All systems of a handle share one sort (their cells are numbered
+// consecutively) and one launch of the pair kernel.
 //
 // Images are never materialised: the order-l image of source j is at the
 // same distance from target i as the real source j is from a transformed
 // target (x_i, y_i, sz z_i + cz) -- a reflection for odd l, a shift for even
-// l -- so every image family is a second cell search around the transformed
+// l -- so every image family is another cell search around the transformed
 // target, done only when that point lies within r_c of the slab.
 #include "devmath.h"
 #include "erfcx_fit.h"
@@ -26,32 +28,36 @@ hipError_t launch_fill(void *p, int64_t nbytes, hipStream_t s) {
 
 struct CellArgs {
     const double *pos, *q;
-    int64_t N;
-    double Lx, Ly, hx, hy, hz;
-    int ncx, ncy, ncz, ncells;
+    const SysDesc *sys;
+    Layout lay;
+    int n_sys, n_total, ncells;
     int *cell, *slot, *count, *start, *tmp, *sidx, *scell;
     double4 *sorted;
 };
 
-__device__ __forceinline__ int cell_of(double x, double y, double z, const CellArgs &a, double *xw,
+// local cell of a particle: z-layer slowest, then x, then y (rows along y are contiguous)
+__device__ __forceinline__ int cell_of(double x, double y, double z, const SysDesc &d, double *xw,
                                        double *yw) {
-    double fx = x / a.Lx; fx -= floor(fx);
-    double fy = y / a.Ly; fy -= floor(fy);
-    *xw = fx * a.Lx;
-    *yw = fy * a.Ly;
-    int cx = min(a.ncx - 1, max(0, (int)(*xw / a.hx)));
-    int cy = min(a.ncy - 1, max(0, (int)(*yw / a.hy)));
-    int cz = min(a.ncz - 1, max(0, (int)(z / a.hz)));   // z outside (0,H) is flagged by prep
-    return (cz * a.ncx + cx) * a.ncy + cy;             // rows along y are contiguous
+    double fx = x / d.Lx; fx -= floor(fx);
+    double fy = y / d.Ly; fy -= floor(fy);
+    *xw = fx * d.Lx;
+    *yw = fy * d.Ly;
+    const int cx = min(d.ncx - 1, max(0, (int)(*xw / d.hx)));
+    const int cy = min(d.ncy - 1, max(0, (int)(*yw / d.hy)));
+    const int cz = min(d.ncz - 1, max(0, (int)(z / d.hz)));   // z outside (0,H) is flagged by prep
+    return (cz * d.ncx + cx) * d.ncy + cy;
 }
 
 __global__ __launch_bounds__(kBlock) void k_cell_assign(CellArgs a) {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= a.N) return;
+    const int g = blockIdx.x * kBlock + threadIdx.x;
+    if (g >= a.n_total) return;
+    const int r = find_sys(a.lay.off, a.n_sys, g);
+    const SysDesc &d = a.sys[r];
     double xw, yw;
-    const int c = cell_of(a.pos[3 * i], a.pos[3 * i + 1], a.pos[3 * i + 2], a, &xw, &yw);
-    a.cell[i] = c;
-    a.slot[i] = atomicAdd(&a.count[c], 1);
+    const int c = d.cbase + cell_of(a.pos[3 * (int64_t)g], a.pos[3 * (int64_t)g + 1], a.pos[3 * (int64_t)g + 2], d,
+                                    &xw, &yw);
+    a.cell[g] = c;
+    a.slot[g] = atomicAdd(&a.count[c], 1);
 }
 
 // exclusive scan of count[0..ncells) into start[0..ncells] in three phases:
@@ -114,42 +120,44 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_apply(const int *count, int
 }
 
 __global__ __launch_bounds__(kBlock) void k_cell_scatter(CellArgs a) {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= a.N) return;
-    a.tmp[a.start[a.cell[i]] + a.slot[i]] = (int)i;
+    const int g = blockIdx.x * kBlock + threadIdx.x;
+    if (g >= a.n_total) return;
+    a.tmp[a.start[a.cell[g]] + a.slot[g]] = g;
 }
 
-// position within the cell = number of members with a smaller original index
+// position within the cell = number of members with a smaller caller index;
+// sorted positions are padded per system to whole waves
 __global__ __launch_bounds__(kBlock) void k_cell_rank(CellArgs a) {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= a.N) return;
-    const int c = a.cell[i];
+    const int g = blockIdx.x * kBlock + threadIdx.x;
+    if (g >= a.n_total) return;
+    const int r = find_sys(a.lay.off, a.n_sys, g);
+    const SysDesc &d = a.sys[r];
+    const int c = a.cell[g];
     const int b = a.start[c], e = a.start[c + 1];
-    int r = 0;
-    for (int j = b; j < e; j++) r += a.tmp[j] < (int)i;
+    int rank = 0;
+    for (int j = b; j < e; j++) rank += a.tmp[j] < g;
+    const int s = b + rank + (a.lay.sbase[r] - a.lay.off[r]);
     double xw, yw;
-    cell_of(a.pos[3 * i], a.pos[3 * i + 1], a.pos[3 * i + 2], a, &xw, &yw);
+    const int cl = cell_of(a.pos[3 * (int64_t)g], a.pos[3 * (int64_t)g + 1], a.pos[3 * (int64_t)g + 2], d, &xw, &yw);
     // x relative to the cell's lower x edge (a row along y shares it), y wrapped, z as given
-    const int cx = (c / a.ncy) % a.ncx;
-    const double xr = xw - cx * a.hx;
-    a.sorted[b + r] = make_double4(xr, yw, a.pos[3 * i + 2], a.q[i]);
-    a.sidx[b + r] = (int)i;
-    a.scell[b + r] = c;
+    const int cx = (cl / d.ncy) % d.ncx;
+    a.sorted[s] = make_double4(xw - cx * d.hx, yw, a.pos[3 * (int64_t)g + 2], a.q[g]);
+    a.sidx[s] = g;
+    a.scell[s] = cl;
 }
 
 struct RealArgs {
-    const void *src;            // sorted sources: (x - x0(cell), y, z, q) as double4
+    const double4 *src;         // sorted sources: (x - x0(cell), y, z, q)
     const int *sidx, *scell, *start;
-    const Family *fam;
-    int nfam;
-    int64_t N;
-    double Lx, Ly, H, hx, hy, hz, inv_hy, inv_hz, rc, rc2, alpha, pref;
-    int ncx, ncy, ncz, reach;   // reach: neighbour columns on each side (cells are >= r_c / reach)
+    const SysDesc *sys;
+    const Family *fam;          // kMaxFamilies per system
+    Layout lay;
+    int n_sys, n_waves;         // n_waves: padded real-space waves of all systems
     int nblocks;                // logical blocks (the grid is rounded up to a multiple of 8)
     int round_min;              // keep draining the pair queues while this many lanes hold work
     double4 *freal;
     double2 *dgreal;
-    double *rpart;
+    double *rpart;              // per wave
 };
 
 template <bool FP32> struct RealTypes;
@@ -191,57 +199,62 @@ __device__ __forceinline__ int wave_min(int v) {
 
 // One thread per target, targets in cell order (z-layer slowest, then x,
 // then y), so the lanes of a wave share a z-layer and see neighbour rows of
-// similar length.  For each image family, each z-layer within r_c and each
-// x-column, the sources lie in one contiguous run of cells along y (two
-// runs where the range wraps around the periodic y boundary), culled to the
-// y-extent the sphere of radius r_c allows in that layer and column.  Pairs
-// within r_c go to a per-lane queue in LDS; the queue is drained (erfc/exp)
-// whenever some lane's queue is full, with all lanes taking part, so the
-// transcendental work is spent on accepted pairs only.  Pair geometry is
-// FP64 in both variants (the closest pairs dominate the force); the FP32
-// variant evaluates erfc/exp and the per-drain partial sums in FP32 and
-// accumulates the drains in FP64.
+// similar length; every wave belongs to one system.  For each image family,
+// each z-layer within r_c and each x-column, the sources lie in one
+// contiguous run of cells along y (two runs where the range wraps around the
+// periodic y boundary), culled to the y-extent the sphere of radius r_c
+// allows in that layer and column.  Pairs within r_c go to a per-lane ring
+// buffer in LDS, drained in rounds in which every lane holding a pair
+// evaluates erfc/exp for it, so the transcendental work is spent on accepted
+// pairs only.  Pair geometry is FP64 in both variants (the closest pairs
+// dominate the force); the FP32 variant evaluates erfc/exp and the
+// per-drain partial sums in FP32 and accumulates the drains in FP64.
 template <bool FP32, bool WANT_DG>
 __global__ __launch_bounds__(kBlock) void k_real(RealArgs a) {
     using T = typename RealTypes<FP32>::T;
     using V4 = typename RealTypes<FP32>::V4;
     constexpr int Q = RealTypes<FP32>::Q;
     __shared__ V4 queue[Q][kBlock];
-    __shared__ double sh[kBlock / 64];
-    const double4 *src = (const double4 *)a.src;
+    const double4 *src = a.src;
     const int tid = threadIdx.x;
     // Blocks are dealt round-robin to the 8 XCDs: give each XCD a contiguous
     // range of targets, so neighbouring cells share that XCD's L2.
     const int per_xcd = (int)(gridDim.x >> 3);
     const int lb = (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
     if (lb >= a.nblocks) return;
-    const int64_t t = (int64_t)lb * kBlock + tid;
-    const bool active = t < a.N;
+    const int t = lb * kBlock + tid;
+    // the system of this wave (system ranges are padded to whole waves)
+    const int r = __builtin_amdgcn_readfirstlane(find_sys(a.lay.sbase, a.n_sys, t & ~(kWave - 1)));
+    const SysDesc &d = a.sys[r];
+    const int shift = a.lay.sbase[r] - a.lay.off[r];    // unpadded -> padded sorted position
+    const bool active = t - a.lay.sbase[r] < a.lay.off[r + 1] - a.lay.off[r];
+    const Family *fams = a.fam + (int64_t)r * kMaxFamilies;
+    const int *start = a.start + d.cbase;
     double4 me = make_double4(0.0, 0.0, 0.0, 0.0);
     int cid = 0;
     if (active) { me = src[t]; cid = a.scell[t]; }
-    const int cy = cid % a.ncy;
-    const int cx = (cid / a.ncy) % a.ncx;
-    const bool allx = a.ncx < 2 * a.reach + 1, ally = a.ncy < 2 * a.reach + 1;
-    const double yrel = me.y - cy * a.hy;           // y within the target's cell
-    const double rcm2 = a.rc2 * (1.0 + 2e-9);       // culling bounds get a 1e-9 margin:
-    const double rmarg = 1e-9 * a.rc;               // cells were assigned by division
-    const T alpha = (T)a.alpha;
-    const T c2a = (T)(1.1283791670955126 * a.alpha);
+    const int cy = cid % d.ncy;
+    const int cx = (cid / d.ncy) % d.ncx;
+    const bool allx = d.ncx < 2 * d.reach + 1, ally = d.ncy < 2 * d.reach + 1;
+    const double yrel = me.y - cy * d.hy;           // y within the target's cell
+    const double rcm2 = d.rc2 * (1.0 + 2e-9);       // culling bounds get a 1e-9 margin:
+    const double rmarg = 1e-9 * d.rc;               // cells were assigned by division
+    const T alpha = (T)d.alpha;
+    const T c2a = (T)(1.1283791670955126 * d.alpha);
     double fx = 0, fy = 0, fz = 0, phi = 0, dpt = 0, dpb = 0;
-    for (int f = 0; f <= a.nfam; f++) {
+    for (int f = 0; f <= d.nfam; f++) {
         double sz = 1.0, czs = 0.0, w = 1.0, zsign = 1.0, dwt = 0.0, dwb = 0.0;
         if (f > 0) {
-            const Family fm = a.fam[f - 1];
+            const Family fm = fams[f - 1];
             sz = fm.sz; czs = fm.cz; w = fm.w; zsign = fm.zsign; dwt = fm.dwt; dwb = fm.dwb;
         }
         const double tz = sz * me.z + czs;
-        const bool fam_on = active && tz > -a.rc && tz < a.H + a.rc;
+        const bool fam_on = active && tz > -d.rc && tz < d.H + d.rc;
         if (__ballot(fam_on) == 0) continue;
-        int lzlo = a.ncz, lzhi = -1;
+        int lzlo = d.ncz, lzhi = -1;
         if (fam_on) {
-            lzlo = max(0, (int)floor((tz - a.rc - rmarg) * a.inv_hz));
-            lzhi = min(a.ncz - 1, (int)floor((tz + a.rc + rmarg) * a.inv_hz));
+            lzlo = max(0, (int)floor((tz - d.rc - rmarg) * d.inv_hz));
+            lzhi = min(d.ncz - 1, (int)floor((tz + d.rc + rmarg) * d.inv_hz));
         }
         const int wzlo = wave_min(lzlo), wzhi = wave_max(lzhi);
         double gfx = 0, gfy = 0, gfz = 0, gph = 0;
@@ -284,11 +297,11 @@ __global__ __launch_bounds__(kBlock) void k_real(RealArgs a) {
                     const double4 s = p[m];
                     double dx = xt - s.x;
                     double dy = yt - s.y;
-                    if (allx) dx -= a.Lx * rint(dx / a.Lx);
-                    if (ally) dy -= a.Ly * rint(dy / a.Ly);
+                    if (allx) dx -= d.Lx * rint(dx / d.Lx);
+                    if (ally) dy -= d.Ly * rint(dy / d.Ly);
                     const double dz = tz - s.z;
                     const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-                    if (r2 < a.rc2 && m != self) {
+                    if (r2 < d.rc2 && m != self) {
                         V4 e;
                         e.x = (T)dx; e.y = (T)dy; e.z = (T)dz; e.w = (T)s.w;
                         queue[(head + cnt) & (Q - 1)][tid] = e;
@@ -298,48 +311,50 @@ __global__ __launch_bounds__(kBlock) void k_real(RealArgs a) {
                 if (__ballot(cnt == Q) != 0) drain();
             }
         };
-        const int xlo = allx ? 0 : -a.reach, xhi = allx ? a.ncx - 1 : a.reach;
+        const int xlo = allx ? 0 : -d.reach, xhi = allx ? d.ncx - 1 : d.reach;
         for (int lz = wzlo; lz <= wzhi; lz++) {
             const bool lay_on = lz >= lzlo && lz <= lzhi;
-            const double dzmin = fmax(0.0, fmax(lz * a.hz - tz, tz - (lz + 1) * a.hz));
+            const double dzmin = fmax(0.0, fmax(lz * d.hz - tz, tz - (lz + 1) * d.hz));
             for (int ox = xlo; ox <= xhi; ox++) {
                 const int dxc = allx ? ox - cx : ox;       // column offset in cells
                 int cxx = allx ? ox : cx + ox;
-                if (!allx) cxx += cxx < 0 ? a.ncx : (cxx >= a.ncx ? -a.ncx : 0);
+                if (!allx) cxx += cxx < 0 ? d.ncx : (cxx >= d.ncx ? -d.ncx : 0);
                 double dxmin = 0;
-                if (!allx) dxmin = dxc > 0 ? dxc * a.hx - me.x : (dxc < 0 ? me.x - (dxc + 1) * a.hx : 0.0);
-                const double xt = me.x - dxc * a.hx;
+                if (!allx) dxmin = dxc > 0 ? dxc * d.hx - me.x : (dxc < 0 ? me.x - (dxc + 1) * d.hx : 0.0);
+                const double xt = me.x - dxc * d.hx;
                 const double ye2 = rcm2 - dxmin * dxmin - dzmin * dzmin;
                 // up to two runs of cells along y: [ya, yb] unshifted, the wrapped one shifted by sy2
                 int jb1 = 0, len1 = 0, jb2 = 0, len2 = 0;
                 double sy2 = 0.0;
                 if (lay_on && ye2 > 0.0) {
-                    const int row = (lz * a.ncx + cxx) * a.ncy;
+                    const int row = (lz * d.ncx + cxx) * d.ncy;
                     if (ally) {
-                        jb1 = a.start[row];
-                        len1 = a.start[row + a.ncy] - jb1;
+                        jb1 = start[row];
+                        len1 = start[row + d.ncy] - jb1;
                     } else {
                         const double ye = sqrt(ye2) + rmarg;
-                        int cylo = cy + (int)floor((yrel - ye) * a.inv_hy);
-                        int cyhi = cy + (int)floor((yrel + ye) * a.inv_hy);
-                        cylo = max(cylo, cy - a.reach);
-                        cyhi = min(cyhi, cy + a.reach);
-                        const int ya = max(cylo, 0), yb = min(cyhi, a.ncy - 1);
-                        if (ya <= yb) { jb1 = a.start[row + ya]; len1 = a.start[row + yb + 1] - jb1; }
+                        int cylo = cy + (int)floor((yrel - ye) * d.inv_hy);
+                        int cyhi = cy + (int)floor((yrel + ye) * d.inv_hy);
+                        cylo = max(cylo, cy - d.reach);
+                        cyhi = min(cyhi, cy + d.reach);
+                        const int ya = max(cylo, 0), yb = min(cyhi, d.ncy - 1);
+                        if (ya <= yb) { jb1 = start[row + ya]; len1 = start[row + yb + 1] - jb1; }
                         if (cylo < 0) {
-                            jb2 = a.start[row + cylo + a.ncy];
-                            len2 = a.start[row + a.ncy] - jb2;
-                            sy2 = -a.Ly;
-                        } else if (cyhi >= a.ncy) {
-                            jb2 = a.start[row];
-                            len2 = a.start[row + cyhi - a.ncy + 1] - jb2;
-                            sy2 = a.Ly;
+                            jb2 = start[row + cylo + d.ncy];
+                            len2 = start[row + d.ncy] - jb2;
+                            sy2 = -d.Ly;
+                        } else if (cyhi >= d.ncy) {
+                            jb2 = start[row];
+                            len2 = start[row + cyhi - d.ncy + 1] - jb2;
+                            sy2 = d.Ly;
                         }
                     }
                 }
+                jb1 += shift;
+                jb2 += shift;
                 // the target itself is excluded from the direct family only
-                const int self1 = f == 0 ? (int)(t - jb1) : -1;
-                const int self2 = f == 0 ? (int)(t - jb2) : -1;
+                const int self1 = f == 0 ? t - jb1 : -1;
+                const int self2 = f == 0 ? t - jb2 : -1;
                 scan(src + jb1, len1, xt, me.y, self1);
                 if (__ballot(len2 > 0) != 0) scan(src + jb2, len2, xt, me.y - sy2, self2);
             }
@@ -355,56 +370,54 @@ __global__ __launch_bounds__(kBlock) void k_real(RealArgs a) {
     double qphi = 0.0, qdt = 0.0, qdb = 0.0;
     if (active) {
         const int i = a.sidx[t];
-        const double qi = me.w * a.pref;
-        a.freal[i] = make_double4(qi * fx, qi * fy, qi * fz, a.pref * phi);
+        const double qi = me.w * d.pref;
+        a.freal[i] = make_double4(qi * fx, qi * fy, qi * fz, d.pref * phi);
         qphi = qi * phi;
         if (WANT_DG) {
-            a.dgreal[i] = make_double2(a.pref * dpt, a.pref * dpb);
+            a.dgreal[i] = make_double2(d.pref * dpt, d.pref * dpb);
             qdt = qi * dpt;
             qdb = qi * dpb;
         }
     }
-    const double s0 = block_sum_r(qphi, sh);
-    double s1 = 0.0, s2 = 0.0;
-    if (WANT_DG) { s1 = block_sum_r(qdt, sh); s2 = block_sum_r(qdb, sh); }
-    if (threadIdx.x == 0) {
-        a.rpart[3 * lb] = s0;
-        a.rpart[3 * lb + 1] = s1;
-        a.rpart[3 * lb + 2] = s2;
+    // per-wave partial sums (a wave never straddles two systems)
+    qphi = wave_sum(qphi);
+    if (WANT_DG) { qdt = wave_sum(qdt); qdb = wave_sum(qdb); }
+    if ((tid & (kWave - 1)) == 0 && t / kWave < a.n_waves) {
+        const int wv = t / kWave;
+        a.rpart[3 * wv] = qphi;
+        a.rpart[3 * wv + 1] = qdt;
+        a.rpart[3 * wv + 2] = qdb;
     }
 }
 
-hipError_t launch_real(rbe2d_ctx *h, int64_t N, const double *pos, const double *q, bool want_dg,
-                       hipStream_t s) {
-    if (N == 0) return hipSuccess;
+hipError_t launch_real(rbe2d_ctx *h, const double *pos, const double *q, bool want_dg, hipStream_t s) {
+    if (h->n_total == 0) return hipSuccess;
     CellArgs c;
-    c.pos = pos; c.q = q; c.N = N;
-    c.Lx = h->p.Lx; c.Ly = h->p.Ly; c.hx = h->hx; c.hy = h->hy; c.hz = h->hz;
-    c.ncx = h->ncx; c.ncy = h->ncy; c.ncz = h->ncz; c.ncells = h->ncells;
+    c.pos = pos; c.q = q; c.sys = h->w.sys; c.lay = h->w.lay; c.n_sys = h->n_sys;
+    c.n_total = (int)h->n_total; c.ncells = h->total_cells;
     c.cell = h->w.cell; c.slot = h->w.slot; c.count = h->w.count; c.start = h->w.start;
-    const bool fp32 = h->p.precision == RBE2D_PREC_FP32_PHASE;
     c.tmp = h->w.tmp; c.sidx = h->w.sidx; c.scell = h->w.scell; c.sorted = h->w.sorted;
-    const int nb = (int)((N + kBlock - 1) / kBlock);
+    const int nb = (int)((h->n_total + kBlock - 1) / kBlock);
     prof_begin(h, 3, s);
-    (void)launch_fill(h->w.count, (int64_t)h->ncells * 4, s);
+    (void)launch_fill(h->w.count, (int64_t)h->total_cells * 4, s);
     hipLaunchKernelGGL(k_cell_assign, dim3(nb), dim3(kBlock), 0, s, c);
-    const int nsb = (h->ncells + kScanBlock - 1) / kScanBlock;
-    hipLaunchKernelGGL(k_scan_totals, dim3(nsb), dim3(kScanBlock), 0, s, h->w.count, h->ncells, h->w.scanbuf);
+    const int nsb = (h->total_cells + kScanBlock - 1) / kScanBlock;
+    hipLaunchKernelGGL(k_scan_totals, dim3(nsb), dim3(kScanBlock), 0, s, h->w.count, h->total_cells, h->w.scanbuf);
     hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kScanBlock), 0, s, h->w.scanbuf, nsb);
-    hipLaunchKernelGGL(k_scan_apply, dim3(nsb), dim3(kScanBlock), 0, s, h->w.count, h->ncells, h->w.scanbuf,
+    hipLaunchKernelGGL(k_scan_apply, dim3(nsb), dim3(kScanBlock), 0, s, h->w.count, h->total_cells, h->w.scanbuf,
                        h->w.start);
     hipLaunchKernelGGL(k_cell_scatter, dim3(nb), dim3(kBlock), 0, s, c);
     hipLaunchKernelGGL(k_cell_rank, dim3(nb), dim3(kBlock), 0, s, c);
     prof_end(h, 3, s);
     RealArgs r;
-    r.src = h->w.sorted; r.sidx = h->w.sidx; r.scell = h->w.scell; r.start = h->w.start; r.fam = h->w.fam;
-    r.nfam = (int)h->fam.size(); r.N = N;
-    r.Lx = h->p.Lx; r.Ly = h->p.Ly; r.H = h->p.H; r.hx = h->hx; r.hy = h->hy; r.hz = h->hz;
-    r.rc = h->p.r_c; r.rc2 = h->p.r_c * h->p.r_c; r.alpha = h->p.alpha; r.pref = h->pref;
-    r.inv_hy = 1.0 / h->hy; r.inv_hz = 1.0 / h->hz; r.nblocks = nb; r.round_min = h->round_min;
-    const int nb8 = (nb + 7) / 8 * 8;
-    r.ncx = h->ncx; r.ncy = h->ncy; r.ncz = h->ncz; r.reach = h->reach;
+    r.src = h->w.sorted; r.sidx = h->w.sidx; r.scell = h->w.scell; r.start = h->w.start;
+    r.sys = h->w.sys; r.fam = h->w.fam; r.lay = h->w.lay; r.n_sys = h->n_sys; r.n_waves = h->n_swaves;
+    r.round_min = h->round_min;
     r.freal = h->w.freal; r.dgreal = h->w.dgreal; r.rpart = h->w.rpart;
+    const int nbs = (h->n_swaves * kWave + kBlock - 1) / kBlock;
+    r.nblocks = nbs;
+    const int nb8 = (nbs + 7) / 8 * 8;
+    const bool fp32 = h->precision == RBE2D_PREC_FP32_PHASE;
     prof_begin(h, 4, s);
     if (fp32) {
         if (want_dg) hipLaunchKernelGGL((k_real<true, true>), dim3(nb8), dim3(kBlock), 0, s, r);

@@ -23,7 +23,8 @@ KSPACE, REAL, IBC, ALL, ACCUMULATE = 1, 2, 4, 7, 16
 EXPORTS = ("rbe2d_create", "rbe2d_destroy", "rbe2d_query", "rbe2d_draw_kset", "rbe2d_set_kset",
            "rbe2d_sample_kset", "rbe2d_get_kset", "rbe2d_forces", "rbe2d_energy",
            "rbe2d_energy_backward", "rbe2d_md_run", "rbe2d_profile_enable", "rbe2d_profile_read",
-           "rbe2d_check", "rbe2d_last_error")
+           "rbe2d_check", "rbe2d_last_error", "rbe2d_batch_create", "rbe2d_query_system",
+           "rbe2d_batch_forces", "rbe2d_batch_md_run")
 PROF_SLOTS = ("prep", "sf_pass", "assemble", "cell_build", "real_pairs", "force_scatter", "energy",
               "integrator", "ksample")
 
@@ -67,7 +68,13 @@ def lib():
         L.rbe2d_energy.argtypes = [_vp, ctypes.c_int64, _vp, _vp, _vp, _vp]
         L.rbe2d_energy_backward.argtypes = [_vp, ctypes.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
         L.rbe2d_md_run.argtypes = [_vp, ctypes.c_int64, _vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_double,
-                                   ctypes.c_double, ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32, _vp]
+                                   ctypes.c_double, ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32,
+                                   ctypes.c_int32, _vp]
+        L.rbe2d_batch_create.argtypes = [ctypes.c_int32, _vp, ctypes.POINTER(_vp)]
+        L.rbe2d_query_system.argtypes = [_vp, ctypes.c_int32, _vp, _vp, _vp]
+        L.rbe2d_batch_forces.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_uint32, _vp]
+        L.rbe2d_batch_md_run.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _vp]
         L.rbe2d_profile_enable.argtypes = [_vp, ctypes.c_int32]
         L.rbe2d_profile_read.argtypes = [_vp, _vp, _vp, ctypes.c_int32]
         L.rbe2d_check.argtypes = [_vp, _vp]
@@ -209,13 +216,14 @@ class Slab:
             _dptr(dq, torch.float64, (N,), "dEdq"), _dptr(dg, torch.float64, (2,), "dEdgamma"), _stream()))
         return dr, dq, dg
 
-    def md_run(self, pos, vel, q, F, dt, z_lo, z_hi, seed, step0, n_steps):
+    def md_run(self, pos, vel, q, F, dt, z_lo, z_hi, seed, step0, n_steps, use_graph=False):
         import torch
         N = int(q.shape[0])
         self._ok(lib().rbe2d_md_run(
             self._h, N, _dptr(pos, torch.float64, (N, 3), "pos"), _dptr(vel, torch.float64, (N, 3), "vel"),
             _dptr(q, torch.float64, (N,), "q"), _dptr(F, torch.float64, (N, 3), "F"), float(dt),
-            float(z_lo), float(z_hi), ctypes.c_uint64(seed), int(step0), int(n_steps), _stream()))
+            float(z_lo), float(z_hi), ctypes.c_uint64(seed), int(step0), int(n_steps), int(bool(use_graph)),
+            _stream()))
 
     def profile_enable(self, n_events):
         self._ok(lib().rbe2d_profile_enable(self._h, int(n_events)))
@@ -231,6 +239,95 @@ class Slab:
 
     def check(self):
         self._ok(lib().rbe2d_check(self._h, _stream()))
+
+
+class BatchedSlab(Slab):
+    """n_sys independent slabs (replicas) evaluated together: one handle,
+    one launch of each kernel for all of them.  `params_list` holds one
+    dict of Slab keyword arguments per system (same P and precision)."""
+
+    def __init__(self, params_list):
+        n = len(params_list)
+        arr = (Params * n)()
+        for i, kw in enumerate(params_list):
+            arr[i] = make_params(**kw)
+        self._params_arr = arr
+        self.params = arr[0]
+        self._h = ctypes.c_void_p()
+        st = lib().rbe2d_batch_create(n, ctypes.cast(arr, ctypes.c_void_p), ctypes.byref(self._h))
+        if st != RBE2D_OK:
+            raise RBE2DError(st, lib().rbe2d_last_error(None).decode())
+        self.n_sys = n
+        self.P = int(arr[0].P)
+        self.n_max = [int(a.n_max) for a in arr]
+        self.Lz_ext, self.V, self.S = [], [], []
+        for r in range(n):
+            Lz, V, S = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+            self._ok(lib().rbe2d_query_system(self._h, r, ctypes.byref(Lz), ctypes.byref(V), ctypes.byref(S)))
+            self.Lz_ext.append(Lz.value)
+            self.V.append(V.value)
+            self.S.append(S.value)
+
+    @staticmethod
+    def offsets(counts):
+        off = np.zeros(len(counts) + 1, dtype=np.int64)
+        off[1:] = np.cumsum(np.asarray(counts, dtype=np.int64))
+        return off
+
+    def _off(self, offsets):
+        off = np.ascontiguousarray(offsets, dtype=np.int64)
+        if off.shape != (self.n_sys + 1,):
+            raise ValueError(f"offsets must have {self.n_sys + 1} entries")
+        return off
+
+    def draw_kset(self, seed, stream_id=0):
+        """Host draw of the batch k-set: system r from stream id stream_id + r."""
+        return np.stack([draw_kset(self._params_arr[r], seed, stream_id + r) for r in range(self.n_sys)])
+
+    def set_kset(self, n):
+        import torch
+        if isinstance(n, torch.Tensor) and n.is_cuda:
+            self._ok(lib().rbe2d_set_kset(self._h, _dptr(n, torch.int32, (self.n_sys, self.P, 3), "n"), 1,
+                                          _stream()))
+        else:
+            a = np.ascontiguousarray(n, dtype=np.int32).reshape(self.n_sys, self.P, 3)
+            self._ok(lib().rbe2d_set_kset(self._h, ctypes.c_void_p(a.ctypes.data), 0, _stream()))
+
+    def get_kset(self):
+        out = np.zeros((self.n_sys, self.P, 3), dtype=np.int32)
+        self._ok(lib().rbe2d_get_kset(self._h, ctypes.c_void_p(out.ctypes.data), _stream()))
+        return out
+
+    def forces(self, offsets, pos, q, flags=ALL, want_energy=False, out=None, energy_out=None):
+        import torch
+        off = self._off(offsets)
+        N = int(off[-1])
+        F = torch.empty((N, 3), dtype=torch.float64, device=pos.device) if out is None else out
+        E = None
+        if want_energy:
+            E = (torch.empty((self.n_sys, 5), dtype=torch.float64, device=pos.device)
+                 if energy_out is None else energy_out)
+        self._ok(lib().rbe2d_batch_forces(
+            self._h, ctypes.c_void_p(off.ctypes.data), _dptr(pos, torch.float64, (N, 3), "pos"),
+            _dptr(q, torch.float64, (N,), "q"), _dptr(F, torch.float64, (N, 3), "F"),
+            _dptr(E, torch.float64, (self.n_sys, 5), "energy"), flags, _stream()))
+        return (F, E) if want_energy else F
+
+    def md_run(self, offsets, pos, vel, q, F, dt, wall_margin, seed, step0, n_steps, use_graph=False):
+        import torch
+        off = self._off(offsets)
+        N = int(off[-1])
+        self._ok(lib().rbe2d_batch_md_run(
+            self._h, ctypes.c_void_p(off.ctypes.data), _dptr(pos, torch.float64, (N, 3), "pos"),
+            _dptr(vel, torch.float64, (N, 3), "vel"), _dptr(q, torch.float64, (N,), "q"),
+            _dptr(F, torch.float64, (N, 3), "F"), float(dt), float(wall_margin), ctypes.c_uint64(seed),
+            int(step0), int(n_steps), int(bool(use_graph)), _stream()))
+
+    def energy(self, *a, **k):
+        raise NotImplementedError("use forces(..., want_energy=True) on a batch")
+
+    def energy_backward(self, *a, **k):
+        raise NotImplementedError("the adjoint is provided for single systems")
 
 
 def energy_function():
