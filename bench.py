@@ -8,7 +8,11 @@ on the device, real space (cell list + erfc pairs with images), k-space
 
 Prints one JSON line: particle-steps/s, the live roofline of the dominant
 kernel (HIP events around its launches in the timed region) and the CPU
-oracle timed on a bounded sample of the same workload.
+oracle timed on a bounded sample of the same workload.  Side measurements
+in the same line: the same MD step replayed from a captured HIP graph, the
+64-replica batch (one graph-captured launch sequence per MD step for all
+replicas) and the differentiable energy (forward + adjoint), each next to
+the plain single-system FP64 path on the same GPU.
 """
 import argparse
 import json
@@ -45,6 +49,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=20000, help="particles in the oracle's rho sample")
     ap.add_argument("--cpu-targets", type=int, default=32, help="oracle force targets")
+    ap.add_argument("--side-steps", type=int, default=10, help="steps of each side measurement (0 = skip)")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (HBM counter calibration)")
     return ap.parse_args()
 
 
@@ -68,7 +75,7 @@ def expected_real_pairs(w, nz=4000):
     return float(rho * w.N * np.mean(direct + img))
 
 
-def run_md(R, torch, w, precision, steps, warmup, profile):
+def run_md(R, torch, w, precision, steps, warmup, profile, use_graph=False):
     from paper_2405_06333_amd import inputs
     pos, q = inputs.sample(w)
     dev = "cuda"
@@ -81,7 +88,7 @@ def run_md(R, torch, w, precision, steps, warmup, profile):
     slab.forces(P_, Q_, out=F_)
     zlo, zhi = w.margin, w.H - w.margin
     step = 1
-    slab.md_run(P_, V_, Q_, F_, w.dt, zlo, zhi, w.seed, step, warmup)
+    slab.md_run(P_, V_, Q_, F_, w.dt, zlo, zhi, w.seed, step, warmup, use_graph=use_graph)
     step += warmup
     torch.cuda.synchronize()
     slab.check()
@@ -90,13 +97,125 @@ def run_md(R, torch, w, precision, steps, warmup, profile):
         slab.profile_read()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    slab.md_run(P_, V_, Q_, F_, w.dt, zlo, zhi, w.seed, step, steps)
+    slab.md_run(P_, V_, Q_, F_, w.dt, zlo, zhi, w.seed, step, steps, use_graph=use_graph)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = slab.profile_read() if profile else None
     slab.check()
     finite = bool(torch.isfinite(F_).all().item() and torch.isfinite(P_).all().item())
     return (t1 - t0), prof, finite
+
+
+def timed(torch, fn, steps):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def run_batch(R, torch, steps):
+    """64 replicas of uneven N and different contrasts: batched MD steps
+    (graph replays) in FP32 phases and in FP64, against the plain path --
+    one single-system FP64 handle per replica, stepped one after another."""
+    from paper_2405_06333_amd import inputs
+    ws = inputs.replicas()
+    pos = np.concatenate([inputs.sample(w)[0] for w in ws])
+    q = np.concatenate([inputs.sample(w)[1] for w in ws])
+    counts = [w.N for w in ws]
+    ntot = int(sum(counts))
+    margin = min(w.margin for w in ws)
+    out = {"workload": f"replicas: {len(ws)} slabs, N in [{min(counts)}, {max(counts)}], total {ntot}, "
+                       f"2:1 ions, P={ws[0].P}, M={ws[0].M}", "particles": ntot}
+    for prec in ("fp32", "fp64"):
+        b = R.BatchedSlab([dict(w.slab_kwargs(), precision=prec, n_max=w.N) for w in ws])
+        off = b.offsets(counts)
+        P_ = torch.as_tensor(pos, device="cuda")
+        Q_ = torch.as_tensor(q, device="cuda")
+        V_ = torch.zeros_like(P_)
+        b.sample_kset(ws[0].seed, 0)
+        F_ = b.forces(off, P_, Q_)
+        b.md_run(off, P_, V_, Q_, F_, ws[0].dt, margin, ws[0].seed, 1, 2, use_graph=True)
+        t = timed(torch, lambda: b.md_run(off, P_, V_, Q_, F_, ws[0].dt, margin, ws[0].seed, 3, steps,
+                                          use_graph=True), 1)
+        b.check()
+        out[f"batch_{prec}_graph"] = ntot * steps / t
+        del b
+    slabs = [R.Slab(**w.slab_kwargs(), precision="fp64", n_max=w.N) for w in ws]
+    offs = np.concatenate([[0], np.cumsum(counts)])
+    P_ = torch.as_tensor(pos, device="cuda")
+    Q_ = torch.as_tensor(q, device="cuda")
+    V_ = torch.zeros_like(P_)
+    F_ = torch.zeros_like(P_)
+    views = [(P_[offs[r]:offs[r + 1]], V_[offs[r]:offs[r + 1]], Q_[offs[r]:offs[r + 1]], F_[offs[r]:offs[r + 1]])
+             for r in range(len(ws))]
+    for r, s in enumerate(slabs):
+        s.sample_kset(ws[r].seed, 0)
+        s.forces(views[r][0], views[r][2], out=views[r][3])
+
+    def plain_steps(step0, n):
+        for it in range(n):
+            for r, s in enumerate(slabs):
+                pv, vv, qv, fv = views[r]
+                s.md_run(pv, vv, qv, fv, ws[r].dt, margin, ws[r].H - margin, ws[r].seed, step0 + it, 1)
+    plain_steps(1, 1)
+    n_plain = max(1, steps // 2)
+    t = timed(torch, lambda: plain_steps(2, n_plain), 1)
+    out["plain_fp64_per_replica"] = ntot * n_plain / t
+    out["batch_fp32_vs_plain_fp64"] = out["batch_fp32_graph"] / out["plain_fp64_per_replica"]
+    out["batch_fp64_vs_plain_fp64"] = out["batch_fp64_graph"] / out["plain_fp64_per_replica"]
+    out["unit"] = "particle-steps/s"
+    return out
+
+
+def run_grad(R, torch, steps):
+    """Differentiable energy: forward energy + hand-written adjoint (dE/dr,
+    dE/dq, dE/dgamma, rho(k) recomputed) per step, against plain FP64 forces
+    on the same system and k-set."""
+    from paper_2405_06333_amd import inputs
+    w = inputs.GRADIENT
+    pos, q = inputs.sample(w)
+    P_ = torch.as_tensor(pos, device="cuda")
+    Q_ = torch.as_tensor(q, device="cuda")
+    out = {"workload": f"gradient: N={w.N}, {w.Lx:g}x{w.Ly:g}x{w.H:g}, P={w.P}, M={w.M}", "unit": "particle-steps/s"}
+    s = R.Slab(**w.slab_kwargs(), precision="fp64", n_max=w.N)
+    s.set_kset(s.draw_kset(w.seed, 0))
+    gE = torch.ones((), dtype=torch.float64, device="cuda")
+    E = torch.empty(5, dtype=torch.float64, device="cuda")
+    F = torch.empty_like(P_)
+
+    def fwd_bwd():
+        s.energy(P_, Q_, out=E)
+        s.energy_backward(P_, Q_, gE)
+    fwd_bwd()
+    out["energy_fwd_bwd_fp64"] = w.N * steps / timed(torch, fwd_bwd, steps)
+    fn = R.energy_function()
+    gamma = torch.tensor([w.gamma_top, w.gamma_bot], dtype=torch.float64, device="cuda", requires_grad=True)
+    Pg = P_.clone().requires_grad_(True)
+    Qg = Q_.clone().requires_grad_(True)
+
+    def autograd_step():
+        e = fn.apply(Pg, Qg, gamma, s)
+        e.backward()
+    autograd_step()
+    out["autograd_fp64"] = w.N * steps / timed(torch, autograd_step, steps)
+    s.forces(P_, Q_, out=F)
+    out["plain_fp64_forces"] = w.N * steps / timed(torch, lambda: s.forces(P_, Q_, out=F), steps)
+    out["fwd_bwd_vs_plain_fp64"] = out["energy_fwd_bwd_fp64"] / out["plain_fp64_forces"]
+    return out
+
+
+def copy_probe(torch, mib):
+    """A plain device copy of `mib` MiB, three times: the reference reading
+    for the HBM byte counters."""
+    n = mib * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "launches": 3}), flush=True)
 
 
 def cpu_baseline(w, n_sample, n_targets):
@@ -141,6 +260,9 @@ def main():
         print(f"bench.py: this build runs on one GPU only; --gpus {a.gpus} is not supported", file=sys.stderr)
         return 2
     import torch
+    if a.copy_mib:
+        copy_probe(torch, a.copy_mib)
+        return 0
     from paper_2405_06333_amd import inputs, rbe2d as R
     R.lib()
     w = inputs.LARGE_MD
@@ -182,6 +304,12 @@ def main():
         s64, _, _ = run_md(R, torch, w, "fp64", a.fp64_steps, 1, profile=False)
         fp64 = {"value": w.N * a.fp64_steps / s64, "unit": "particle-steps/s", "steps": a.fp64_steps}
 
+    graph = batch = grad = None
+    if a.side_steps > 0:
+        sg, _, _ = run_md(R, torch, w, a.precision, a.side_steps, 1, profile=False, use_graph=True)
+        graph = {"value": w.N * a.side_steps / sg, "unit": "particle-steps/s", "steps": a.side_steps}
+        batch = run_batch(R, torch, a.side_steps)
+        grad = run_grad(R, torch, a.side_steps)
     cpu = None if a.no_cpu_baseline else cpu_baseline(w, a.cpu_sample, a.cpu_targets)
     out = {
         "metric": METRIC,
@@ -204,6 +332,9 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "plain_fp64_gpu": fp64,
+        "md_graph": graph,
+        "batched_replicas": batch,
+        "differentiable": grad,
         "kernels": kern,
         "finite": finite,
     }

@@ -208,6 +208,19 @@ rbe2d_status setup_system(const rbe2d_params *pin, SysHost &sh) {
     d.ncx = ncx; d.ncy = ncy; d.ncz = ncz;
     d.hx = p.Lx / ncx; d.hy = p.Ly / ncy; d.hz = p.H / ncz;
     d.inv_hy = 1.0 / d.hy; d.inv_hz = 1.0 / d.hz;
+    // fixed-point frame of the FP32 pair kernel.  z (and every transformed
+    // target height within r_c of the slab) lies in [-zoff, zspan - zoff);
+    // the span exceeds twice any candidate |dz| <= r_c + hz <= r_c + H.
+    const double two32 = 4294967296.0;
+    const double zspan = 2.0 * p.H + 4.0 * p.r_c;
+    d.zoff = 0.5 * p.H + 2.0 * p.r_c;
+    d.fxs = two32 / p.Lx; d.fys = two32 / p.Ly; d.fzs = two32 / zspan;
+    d.ux = (float)(p.Lx / two32); d.uy = (float)(p.Ly / two32); d.uz = (float)(zspan / two32);
+    d.rc2f = (float)(p.r_c * p.r_c);
+    // below `near` the quantisation of the positions (one unit) would exceed
+    // ~2^-22 of the distance: such pairs take exact FP64 displacements
+    const double near = std::max(std::max(p.Lx, p.Ly), zspan) / two32 * 4194304.0;
+    d.near2f = (float)(near * near);
     return RBE2D_OK;
 }
 
@@ -331,6 +344,7 @@ rbe2d_status create_handle(int n, const rbe2d_params *ps, bool batch, rbe2d_hand
     A(&w.cell, nc); A(&w.slot, nc); A(&w.tmp, nc);
     A(&w.count, cells); A(&w.start, cells + 1); A(&w.scanbuf, cells / 1024 + 2);
     A(&w.sorted, h->cap_sorted); A(&w.sidx, h->cap_sorted); A(&w.scell, h->cap_sorted);
+    if (h->precision == RBE2D_PREC_FP32_PHASE) A(&w.src16, h->cap_sorted);
     A(&w.freal, nc); A(&w.dgreal, nc);
     A(&w.rpart, 3 * (h->cap_sorted / kWave));
     A(&w.err, 4);

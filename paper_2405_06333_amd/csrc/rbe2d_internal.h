@@ -55,6 +55,11 @@ struct SysDesc {
     double hx, hy, hz, inv_hy, inv_hz;         // cell sizes
     int ncx, ncy, ncz, reach, nfam, M, fh_bits, cbase;
     int nmax[3], cdf_off[3];                   // sampler tables in the shared CDF array
+    // fixed-point source records of the FP32 pair kernel: x and y in units
+    // of period / 2^32 (so an int32 difference is the minimum image), z + zoff
+    // in units of zspan / 2^32; pairs closer than `near` use FP64 geometry
+    double fxs, fys, fzs, zoff;                // scale factors 2^32 / (Lx, Ly, zspan)
+    float ux, uy, uz, rc2f, near2f;            // units as floats, r_c^2, near^2
 };
 
 // Per-k record written by the reduce/assemble kernel (FP64):
@@ -104,6 +109,7 @@ struct Workspace {
     int *cell = nullptr, *slot = nullptr, *count = nullptr, *start = nullptr, *tmp = nullptr;
     int *scanbuf = nullptr;     // per-scan-block totals of the cell counts
     double4 *sorted = nullptr;  // (x - x0(cell), y, z, q) in cell order, padded per system
+    uint4 *src16 = nullptr;     // the same particles as fixed-point (x, y, z) and FP32 q (FP32 kernel)
     int *sidx = nullptr;        // caller index of sorted particle
     int *scell = nullptr;       // local cell of sorted particle
     double4 *freal = nullptr;   // per caller particle: F_real (x, y, z), phi_real

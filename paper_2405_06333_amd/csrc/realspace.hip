@@ -33,7 +33,13 @@ struct CellArgs {
     int n_sys, n_total, ncells;
     int *cell, *slot, *count, *start, *tmp, *sidx, *scell;
     double4 *sorted;
+    uint4 *src16;   // written when set (FP32 pair kernel)
 };
+
+// position -> 32-bit fixed point; the wrap of 2^32 is the period (x, y)
+__device__ __forceinline__ uint32_t to_fixed(double v, double scale) {
+    return (uint32_t)(unsigned long long)llrint(v * scale);
+}
 
 // local cell of a particle: z-layer slowest, then x, then y (rows along y are contiguous)
 __device__ __forceinline__ int cell_of(double x, double y, double z, const SysDesc &d, double *xw,
@@ -141,13 +147,21 @@ __global__ __launch_bounds__(kBlock) void k_cell_rank(CellArgs a) {
     const int cl = cell_of(a.pos[3 * (int64_t)g], a.pos[3 * (int64_t)g + 1], a.pos[3 * (int64_t)g + 2], d, &xw, &yw);
     // x relative to the cell's lower x edge (a row along y shares it), y wrapped, z as given
     const int cx = (cl / d.ncy) % d.ncx;
-    a.sorted[s] = make_double4(xw - cx * d.hx, yw, a.pos[3 * (int64_t)g + 2], a.q[g]);
+    const double z = a.pos[3 * (int64_t)g + 2];
+    a.sorted[s] = make_double4(xw - cx * d.hx, yw, z, a.q[g]);
     a.sidx[s] = g;
     a.scell[s] = cl;
+    if (a.src16) {
+        // z clamped into the frame (z outside (0, H) is flagged by prep)
+        const double zc = fmin(fmax(z, -d.rc), d.H + d.rc);
+        a.src16[s] = make_uint4(to_fixed(xw, d.fxs), to_fixed(yw, d.fys), to_fixed(zc + d.zoff, d.fzs),
+                                __float_as_uint((float)a.q[g]));
+    }
 }
 
 struct RealArgs {
     const double4 *src;         // sorted sources: (x - x0(cell), y, z, q)
+    const uint4 *src16;         // the same in fixed point (FP32 kernel)
     const int *sidx, *scell, *start;
     const SysDesc *sys;
     const Family *fam;          // kMaxFamilies per system
@@ -161,9 +175,9 @@ struct RealArgs {
 };
 
 template <bool FP32> struct RealTypes;
-template <> struct RealTypes<true> { using T = float; using V4 = float4; static constexpr int Q = 8; };
-template <> struct RealTypes<false> { using T = double; using V4 = double4; static constexpr int Q = 4; };
-// (Q must be a power of two: the queues are rings)
+// Q: ring capacity per lane (a power of two); U: source loads in flight per lane
+template <> struct RealTypes<true> { using T = float; using V4 = float4; static constexpr int Q = 8, U = 4; };
+template <> struct RealTypes<false> { using T = double; using V4 = double4; static constexpr int Q = 4, U = 2; };
 
 // erfc(alpha d)/d (ec) and the radial force factor fs = [erfc(a d)/d + 2a/sqrt(pi) e^{-a^2 d^2}]/d^2
 __device__ __forceinline__ void pair_terms(float r2, float alpha, float c2a, float *ec, float *fs) {
@@ -206,14 +220,19 @@ __device__ __forceinline__ int wave_min(int v) {
 // allows in that layer and column.  Pairs within r_c go to a per-lane ring
 // buffer in LDS, drained in rounds in which every lane holding a pair
 // evaluates erfc/exp for it, so the transcendental work is spent on accepted
-// pairs only.  Pair geometry is FP64 in both variants (the closest pairs
-// dominate the force); the FP32 variant evaluates erfc/exp and the
-// per-drain partial sums in FP32 and accumulates the drains in FP64.
+// pairs only.  The FP64 variant reads 32-byte FP64 source records.  The FP32
+// variant reads 16-byte fixed-point records: a displacement is an exact
+// integer difference rounded once to FP32, so its error is one position
+// quantum (period / 2^32); pairs so close that this would matter (the closest
+// pairs dominate the force) are recomputed from the FP64 records.  It
+// evaluates erfc/exp and the per-drain partial sums in FP32 and accumulates
+// the drains in FP64.
 template <bool FP32, bool WANT_DG>
 __global__ __launch_bounds__(kBlock) void k_real(RealArgs a) {
     using T = typename RealTypes<FP32>::T;
     using V4 = typename RealTypes<FP32>::V4;
     constexpr int Q = RealTypes<FP32>::Q;
+    constexpr int U = RealTypes<FP32>::U;
     __shared__ V4 queue[Q][kBlock];
     const double4 *src = a.src;
     const int tid = threadIdx.x;
@@ -232,7 +251,12 @@ __global__ __launch_bounds__(kBlock) void k_real(RealArgs a) {
     const int *start = a.start + d.cbase;
     double4 me = make_double4(0.0, 0.0, 0.0, 0.0);
     int cid = 0;
-    if (active) { me = src[t]; cid = a.scell[t]; }
+    uint32_t xtf = 0, ytf = 0;   // target in fixed point (FP32 kernel)
+    if (active) {
+        me = src[t];
+        cid = a.scell[t];
+        if (FP32) { const uint4 m16 = a.src16[t]; xtf = m16.x; ytf = m16.y; }
+    }
     const int cy = cid % d.ncy;
     const int cx = (cid / d.ncy) % d.ncx;
     const bool allx = d.ncx < 2 * d.reach + 1, ally = d.ncy < 2 * d.reach + 1;
@@ -251,6 +275,7 @@ __global__ __launch_bounds__(kBlock) void k_real(RealArgs a) {
         const double tz = sz * me.z + czs;
         const bool fam_on = active && tz > -d.rc && tz < d.H + d.rc;
         if (__ballot(fam_on) == 0) continue;
+        const uint32_t tzf = fam_on ? to_fixed(tz + d.zoff, d.fzs) : 0u;
         int lzlo = d.ncz, lzhi = -1;
         if (fam_on) {
             lzlo = max(0, (int)floor((tz - d.rc - rmarg) * d.inv_hz));
@@ -280,35 +305,77 @@ __global__ __launch_bounds__(kBlock) void k_real(RealArgs a) {
             gfx += (double)sx; gfy += (double)sy; gfz += (double)szz; gph += (double)sp;
             sx = sy = szz = sp = 0;
         };
-        // when some lane's ring is full: rounds while enough lanes still hold work
-        // (a lane evaluates at most Q pairs per drain before the FP64 fold)
+        // make room for U more pairs in every lane's ring: rounds while a lane
+        // holds more than Q - U pairs or enough lanes still hold work (a lane
+        // evaluates at most Q pairs per drain before the FP64 fold)
         auto drain = [&]() {
             do {
                 round();
-            } while (__popcll(__ballot(cnt > 0)) >= a.round_min);
+            } while (__ballot(cnt > Q - U) != 0 || __popcll(__ballot(cnt > 0)) >= a.round_min);
             fold();
         };
-        // scan one run of sources p[0..len) for pairs within r_c; the trip
-        // count is the wave maximum, so drains always run with every lane
-        auto scan = [&](const double4 *p, int len, double xt, double yt, int self) {
+        auto push = [&](T dx, T dy, T dz, T qs) {
+            V4 e;
+            e.x = dx; e.y = dy; e.z = dz; e.w = qs;
+            queue[(head + cnt) & (Q - 1)][tid] = e;
+            cnt++;
+        };
+        // scan one run of sources [jb, jb + len) for pairs within r_c.  The
+        // trip count is the wave maximum, so drains always run with every
+        // lane.  Loads are issued U at a time ahead of their use: the loop is
+        // bound by the latency of these gathers, not by their arithmetic.
+        auto scan = [&](int jb, int len, double xt, double yt, int self) {
             const int maxlen = wave_max(len);
-            for (int m = 0; m < maxlen; m++) {
-                if (m < len) {
-                    const double4 s = p[m];
-                    double dx = xt - s.x;
-                    double dy = yt - s.y;
-                    if (allx) dx -= d.Lx * rint(dx / d.Lx);
-                    if (ally) dy -= d.Ly * rint(dy / d.Ly);
-                    const double dz = tz - s.z;
-                    const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-                    if (r2 < d.rc2 && m != self) {
-                        V4 e;
-                        e.x = (T)dx; e.y = (T)dy; e.z = (T)dz; e.w = (T)s.w;
-                        queue[(head + cnt) & (Q - 1)][tid] = e;
-                        cnt++;
+            const double4 *p = src + jb;
+            if constexpr (FP32) {
+                // fixed-point displacements: exact integer differences (the
+                // int32 wrap is the minimum image in x and y), one rounding
+                // each to FP32; exact FP64 geometry for pairs within `near`
+                const uint4 *p16 = a.src16 + jb;
+                for (int m0 = 0; m0 < maxlen; m0 += U) {
+                    if (__ballot(cnt > Q - U) != 0) drain();
+                    uint4 sv[U];
+#pragma unroll
+                    for (int k = 0; k < U; k++) sv[k] = m0 + k < len ? p16[m0 + k] : make_uint4(0, 0, 0, 0);
+#pragma unroll
+                    for (int k = 0; k < U; k++) {
+                        const int m = m0 + k;
+                        if (m >= len) continue;
+                        float dx = (float)(int)(xtf - sv[k].x) * d.ux;
+                        float dy = (float)(int)(ytf - sv[k].y) * d.uy;
+                        float dz = (float)(int)(tzf - sv[k].z) * d.uz;
+                        const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                        if (r2 < d.rc2f && m != self) {
+                            if (r2 < d.near2f) {
+                                const double4 s64 = p[m];
+                                double ex = xt - s64.x, ey = yt - s64.y;
+                                ex -= d.Lx * rint(ex / d.Lx);
+                                ey -= d.Ly * rint(ey / d.Ly);
+                                dx = (float)ex; dy = (float)ey; dz = (float)(tz - s64.z);
+                            }
+                            push(dx, dy, dz, __uint_as_float(sv[k].w));
+                        }
                     }
                 }
-                if (__ballot(cnt == Q) != 0) drain();
+                return;
+            }
+            for (int m0 = 0; m0 < maxlen; m0 += U) {
+                if (__ballot(cnt > Q - U) != 0) drain();
+                double4 sv[U];
+#pragma unroll
+                for (int k = 0; k < U; k++) sv[k] = m0 + k < len ? p[m0 + k] : make_double4(0, 0, 0, 0);
+#pragma unroll
+                for (int k = 0; k < U; k++) {
+                    const int m = m0 + k;
+                    if (m >= len) continue;
+                    double dx = xt - sv[k].x;
+                    double dy = yt - sv[k].y;
+                    if (allx) dx -= d.Lx * rint(dx / d.Lx);
+                    if (ally) dy -= d.Ly * rint(dy / d.Ly);
+                    const double dz = tz - sv[k].z;
+                    const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+                    if (r2 < d.rc2 && m != self) push((T)dx, (T)dy, (T)dz, (T)sv[k].w);
+                }
             }
         };
         const int xlo = allx ? 0 : -d.reach, xhi = allx ? d.ncx - 1 : d.reach;
@@ -355,8 +422,8 @@ __global__ __launch_bounds__(kBlock) void k_real(RealArgs a) {
                 // the target itself is excluded from the direct family only
                 const int self1 = f == 0 ? t - jb1 : -1;
                 const int self2 = f == 0 ? t - jb2 : -1;
-                scan(src + jb1, len1, xt, me.y, self1);
-                if (__ballot(len2 > 0) != 0) scan(src + jb2, len2, xt, me.y - sy2, self2);
+                scan(jb1, len1, xt, me.y, self1);
+                if (__ballot(len2 > 0) != 0) scan(jb2, len2, xt, me.y - sy2, self2);
             }
         }
         while (__ballot(cnt > 0) != 0) round();
@@ -396,7 +463,7 @@ hipError_t launch_real(rbe2d_ctx *h, const double *pos, const double *q, bool wa
     c.pos = pos; c.q = q; c.sys = h->w.sys; c.lay = h->w.lay; c.n_sys = h->n_sys;
     c.n_total = (int)h->n_total; c.ncells = h->total_cells;
     c.cell = h->w.cell; c.slot = h->w.slot; c.count = h->w.count; c.start = h->w.start;
-    c.tmp = h->w.tmp; c.sidx = h->w.sidx; c.scell = h->w.scell; c.sorted = h->w.sorted;
+    c.tmp = h->w.tmp; c.sidx = h->w.sidx; c.scell = h->w.scell; c.sorted = h->w.sorted; c.src16 = h->w.src16;
     const int nb = (int)((h->n_total + kBlock - 1) / kBlock);
     prof_begin(h, 3, s);
     (void)launch_fill(h->w.count, (int64_t)h->total_cells * 4, s);
@@ -410,7 +477,7 @@ hipError_t launch_real(rbe2d_ctx *h, const double *pos, const double *q, bool wa
     hipLaunchKernelGGL(k_cell_rank, dim3(nb), dim3(kBlock), 0, s, c);
     prof_end(h, 3, s);
     RealArgs r;
-    r.src = h->w.sorted; r.sidx = h->w.sidx; r.scell = h->w.scell; r.start = h->w.start;
+    r.src = h->w.sorted; r.src16 = h->w.src16; r.sidx = h->w.sidx; r.scell = h->w.scell; r.start = h->w.start;
     r.sys = h->w.sys; r.fam = h->w.fam; r.lay = h->w.lay; r.n_sys = h->n_sys; r.n_waves = h->n_swaves;
     r.round_min = h->round_min;
     r.freal = h->w.freal; r.dgreal = h->w.dgreal; r.rpart = h->w.rpart;
