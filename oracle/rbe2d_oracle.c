@@ -14,7 +14,7 @@
  * on the extended periodic box Lx*Ly*Lz with Lz >= (M+1)H (Theorem 3.3).
  * Coulomb constant 1 and eps_c = 1 as in Eq. (2.1).
  *
- * Readings taken where the paper is garbled (each also listed in the design doc):
+ * Readings taken where the paper is garbled, ambiguous or silent:
  *  R1  image weights: the image of order l above the slab carries
  *      gamma_top^ceil(l/2) * gamma_bot^floor(l/2), the one below carries
  *      gamma_bot^ceil(l/2) * gamma_top^floor(l/2).  This is the physical

@@ -314,7 +314,6 @@ rbe2d_status create_handle(int n, const rbe2d_params *ps, bool batch, rbe2d_hand
     h->cap_particles = std::max<int64_t>(cap_p, kTileMax);
     h->cap_sorted = std::max<int64_t>(cap_s, kWave);
     h->total_cells = cells;
-    if (const char *env = std::getenv("RBE2D_REAL_ROUND_MIN")) h->round_min = std::max(1, std::min(64, std::atoi(env)));
     (void)hipGetDevice(&h->device);
 
     const int64_t cap_blocks = h->cap_particles / kBlock;

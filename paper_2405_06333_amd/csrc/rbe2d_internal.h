@@ -141,7 +141,6 @@ struct rbe2d_ctx {
     int64_t cap_particles = 0;       // padded k-space capacity (all systems)
     int64_t cap_sorted = 0;          // padded real-space capacity
     int total_cells = 0;
-    int round_min = 40;              // real space: drain pair queues while >= this many lanes hold work
     bool kset_valid = false;
     // current layout (host mirror); a layout is uploaded when it changes
     std::vector<int> lay_host;       // 5 x (n_sys + 1): off, pbase, bbase, tbase, sbase

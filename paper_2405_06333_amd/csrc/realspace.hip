@@ -9,6 +9,8 @@
 // target (x_i, y_i, sz z_i + cz) -- a reflection for odd l, a shift for even
 // l -- so every image family is another cell search around the transformed
 // target, done only when that point lies within r_c of the slab.
+#include <type_traits>
+
 #include "devmath.h"
 #include "erfcx_fit.h"
 #include "rbe2d_internal.h"
@@ -168,16 +170,15 @@ struct RealArgs {
     Layout lay;
     int n_sys, n_waves;         // n_waves: padded real-space waves of all systems
     int nblocks;                // logical blocks (the grid is rounded up to a multiple of 8)
-    int round_min;              // keep draining the pair queues while this many lanes hold work
     double4 *freal;
     double2 *dgreal;
     double *rpart;              // per wave
 };
 
 template <bool FP32> struct RealTypes;
-// Q: ring capacity per lane (a power of two); U: source loads in flight per lane
-template <> struct RealTypes<true> { using T = float; using V4 = float4; static constexpr int Q = 8, U = 4; };
-template <> struct RealTypes<false> { using T = double; using V4 = double4; static constexpr int Q = 4, U = 2; };
+// U: source loads in flight per lane
+template <> struct RealTypes<true> { using T = float; using V4 = float4; static constexpr int U = 4; };
+template <> struct RealTypes<false> { using T = double; using V4 = double4; static constexpr int U = 2; };
 
 // erfc(alpha d)/d (ec) and the radial force factor fs = [erfc(a d)/d + 2a/sqrt(pi) e^{-a^2 d^2}]/d^2
 __device__ __forceinline__ void pair_terms(float r2, float alpha, float c2a, float *ec, float *fs) {
@@ -200,6 +201,118 @@ __device__ __forceinline__ void pair_terms(double r2, double alpha, double c2a, 
     *fs = fma(c2a, e, v) / r2;
 }
 
+// ---------------------------------------------------------------------------
+// Queues of accepted pairs.  The scan appends pairs (displacement from the
+// source to the target, source charge); evaluating erfc/exp for them is
+// deferred so that it runs with as many lanes busy as possible.  Both give
+// the sums of the queued pairs' force and potential terms in FP64.
+// ---------------------------------------------------------------------------
+
+// FP32 kernel: a ring of Q entries per lane.  A round evaluates the oldest
+// entry of every lane that holds one; the FP32 sums of a drain (at most Q
+// pairs per lane) are folded into FP64.  Cheap routing (every result stays in
+// its lane) at the price of idle lanes in the rounds.
+template <int Q, int U>
+struct LaneRings {
+    static constexpr int kRoundMin = 40;   // keep draining while this many lanes hold pairs
+    float4 (*ring)[kBlock];
+    int tid, head = 0, cnt = 0;
+    float sx = 0, sy = 0, sz = 0, sp = 0;
+    double gx = 0, gy = 0, gz = 0, gp = 0;
+    __device__ LaneRings(float4 (*r)[kBlock], int t) : ring(r), tid(t) {}
+    __device__ void push(bool acc, float dx, float dy, float dz, float qs) {
+        if (acc) {
+            ring[(head + cnt) & (Q - 1)][tid] = make_float4(dx, dy, dz, qs);
+            cnt++;
+        }
+    }
+    __device__ bool full() const { return __ballot(cnt > Q - U) != 0; }
+    __device__ void round(float alpha, float c2a) {
+        if (cnt > 0) {
+            const float4 e = ring[head][tid];
+            head = (head + 1) & (Q - 1);
+            cnt--;
+            const float r2 = e.x * e.x + e.y * e.y + e.z * e.z;
+            float ec, fs;
+            pair_terms(r2, alpha, c2a, &ec, &fs);
+            const float qf = e.w * fs;
+            sx += qf * e.x; sy += qf * e.y; sz += qf * e.z; sp += e.w * ec;
+        }
+    }
+    __device__ void fold() {
+        gx += (double)sx; gy += (double)sy; gz += (double)sz; gp += (double)sp;
+        sx = sy = sz = sp = 0;
+    }
+    // make room for U more pairs per lane
+    __device__ void drain(float alpha, float c2a) {
+        do {
+            round(alpha, c2a);
+        } while (__ballot(cnt > Q - U) != 0 || __popcll(__ballot(cnt > 0)) >= kRoundMin);
+        fold();
+    }
+    __device__ void flush(float alpha, float c2a) {
+        while (__ballot(cnt > 0) != 0) round(alpha, c2a);
+        fold();
+    }
+};
+
+// FP64 kernel: one queue shared by the wave (compacted with a ballot prefix,
+// entries tagged with the target's lane), evaluated 64 entries at a time with
+// every lane busy; results go to per-target LDS accumulators by LDS atomic
+// adds.  Worth its routing cost where a pair evaluation is expensive.
+template <int QW, int U>
+struct WaveQueue {
+    double4 *ent;         // [QW] entries of this wave
+    unsigned char *own;   // [QW] owning lane
+    double *acc;          // [4][64] per-target sums
+    int lane, qn = 0;     // qn: entries queued (wave-uniform)
+    double gx = 0, gy = 0, gz = 0, gp = 0;
+    __device__ WaveQueue(double4 *e, unsigned char *o, double *a, int l) : ent(e), own(o), acc(a), lane(l) {
+        for (int c = 0; c < 4; c++) acc[c * kWave + lane] = 0.0;
+    }
+    __device__ void push(bool ok, double dx, double dy, double dz, double qs) {
+        const uint64_t m = __ballot(ok);
+        if (ok) {
+            const int slot = qn + __popcll(m & ((1ull << lane) - 1ull));
+            ent[slot] = make_double4(dx, dy, dz, qs);
+            own[slot] = (unsigned char)lane;
+        }
+        qn += __popcll(m);
+    }
+    __device__ bool full() const { return qn > QW - U * kWave; }
+    // evaluate the top n <= 64 entries, one per lane
+    __device__ void round(int n, double alpha, double c2a) {
+        __builtin_amdgcn_wave_barrier();   // entries were written by other lanes of the wave
+        const int base = qn - n;
+        if (lane < n) {
+            const double4 e = ent[base + lane];
+            const int o = own[base + lane];
+            const double r2 = e.x * e.x + e.y * e.y + e.z * e.z;
+            double ec, fs;
+            pair_terms(r2, alpha, c2a, &ec, &fs);
+            const double qf = e.w * fs;
+            atomicAdd(&acc[o], qf * e.x);
+            atomicAdd(&acc[kWave + o], qf * e.y);
+            atomicAdd(&acc[2 * kWave + o], qf * e.z);
+            atomicAdd(&acc[3 * kWave + o], e.w * ec);
+        }
+        qn = base;
+    }
+    __device__ void fold() {
+        __builtin_amdgcn_wave_barrier();
+        gx += acc[lane]; gy += acc[kWave + lane]; gz += acc[2 * kWave + lane]; gp += acc[3 * kWave + lane];
+        for (int c = 0; c < 4; c++) acc[c * kWave + lane] = 0.0;
+    }
+    __device__ void drain(double alpha, double c2a) {
+        while (qn >= kWave) round(kWave, alpha, c2a);
+        fold();
+    }
+    __device__ void flush(double alpha, double c2a) {
+        while (qn > 0) round(min(qn, kWave), alpha, c2a);
+        fold();
+    }
+};
+
 __device__ __forceinline__ int wave_max(int v) {
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
@@ -217,23 +330,45 @@ __device__ __forceinline__ int wave_min(int v) {
 // each z-layer within r_c and each x-column, the sources lie in one
 // contiguous run of cells along y (two runs where the range wraps around the
 // periodic y boundary), culled to the y-extent the sphere of radius r_c
-// allows in that layer and column.  Pairs within r_c go to a per-lane ring
-// buffer in LDS, drained in rounds in which every lane holding a pair
-// evaluates erfc/exp for it, so the transcendental work is spent on accepted
-// pairs only.  The FP64 variant reads 32-byte FP64 source records.  The FP32
+// allows in that layer and column.  Pairs within r_c are appended to a
+// queue shared by the wave in LDS (compacted with a ballot prefix, tagged
+// with the target's lane) and evaluated 64 at a time, one per lane, so the
+// erfc/exp work runs with every lane busy whatever the spread of accepted
+// pairs over the targets; the results go to per-target LDS accumulators by
+// LDS atomic adds, which the owning lane folds into FP64 after each drain.  The FP64 variant reads 32-byte FP64 source records.  The FP32
 // variant reads 16-byte fixed-point records: a displacement is an exact
 // integer difference rounded once to FP32, so its error is one position
 // quantum (period / 2^32); pairs so close that this would matter (the closest
 // pairs dominate the force) are recomputed from the FP64 records.  It
 // evaluates erfc/exp and the per-drain partial sums in FP32 and accumulates
-// the drains in FP64.
+// the drains in FP64.  The order of every sum is fixed by the data, so the
+// results are bitwise reproducible.
+template <typename Queue> __device__ Queue make_queue(unsigned char *lds, int tid);
+template <>
+__device__ LaneRings<8, 4> make_queue<LaneRings<8, 4>>(unsigned char *lds, int tid) {
+    return LaneRings<8, 4>(reinterpret_cast<float4(*)[kBlock]>(lds), tid);
+}
+template <>
+__device__ WaveQueue<256, 2> make_queue<WaveQueue<256, 2>>(unsigned char *lds, int tid) {
+    constexpr int kQ = 256;
+    const int wid = tid / kWave, lane = tid % kWave;
+    double4 *ent = reinterpret_cast<double4 *>(lds) + wid * kQ;
+    double *acc = reinterpret_cast<double *>(lds + (kBlock / kWave) * kQ * sizeof(double4)) + wid * 4 * kWave;
+    unsigned char *own = lds + (kBlock / kWave) * (kQ * sizeof(double4) + 4 * kWave * sizeof(double)) + wid * kQ;
+    return WaveQueue<kQ, 2>(ent, own, acc, lane);
+}
+
 template <bool FP32, bool WANT_DG>
 __global__ __launch_bounds__(kBlock) void k_real(RealArgs a) {
     using T = typename RealTypes<FP32>::T;
-    using V4 = typename RealTypes<FP32>::V4;
-    constexpr int Q = RealTypes<FP32>::Q;
     constexpr int U = RealTypes<FP32>::U;
-    __shared__ V4 queue[Q][kBlock];
+    constexpr int NW = kBlock / kWave;
+    constexpr int kRingQ = 8;      // FP32: ring entries per lane
+    constexpr int kWaveQ = 256;    // FP64: queue entries per wave
+    using Queue = typename std::conditional<FP32, LaneRings<kRingQ, U>, WaveQueue<kWaveQ, U>>::type;
+    constexpr size_t kLds = FP32 ? sizeof(float4) * kRingQ * kBlock
+                                 : NW * (kWaveQ * (sizeof(double4) + 1) + 4 * kWave * sizeof(double));
+    __shared__ __align__(16) unsigned char lds[kLds];
     const double4 *src = a.src;
     const int tid = threadIdx.x;
     // Blocks are dealt round-robin to the 8 XCDs: give each XCD a contiguous
@@ -244,7 +379,7 @@ __global__ __launch_bounds__(kBlock) void k_real(RealArgs a) {
     const int t = lb * kBlock + tid;
     // the system of this wave (system ranges are padded to whole waves)
     const int r = __builtin_amdgcn_readfirstlane(find_sys(a.lay.sbase, a.n_sys, t & ~(kWave - 1)));
-    const SysDesc &d = a.sys[r];
+    const SysDesc d = a.sys[r];   // a copy: loop-invariant values stay in registers
     const int shift = a.lay.sbase[r] - a.lay.off[r];    // unpadded -> padded sorted position
     const bool active = t - a.lay.sbase[r] < a.lay.off[r + 1] - a.lay.off[r];
     const Family *fams = a.fam + (int64_t)r * kMaxFamilies;
@@ -282,44 +417,7 @@ __global__ __launch_bounds__(kBlock) void k_real(RealArgs a) {
             lzhi = min(d.ncz - 1, (int)floor((tz + d.rc + rmarg) * d.inv_hz));
         }
         const int wzlo = wave_min(lzlo), wzhi = wave_max(lzhi);
-        double gfx = 0, gfy = 0, gfz = 0, gph = 0;
-        T sx = 0, sy = 0, szz = 0, sp = 0;   // FP32 partial sums within one drain
-        int head = 0, cnt = 0;               // per-lane ring buffer of accepted pairs in LDS
-        // one round: every lane with a queued pair evaluates its oldest one
-        auto round = [&]() {
-            if (cnt > 0) {
-                const V4 e = queue[head][tid];
-                head = (head + 1) & (Q - 1);
-                cnt--;
-                const T r2 = e.x * e.x + e.y * e.y + e.z * e.z;
-                T ec, fs;
-                pair_terms(r2, alpha, c2a, &ec, &fs);
-                const T qf = e.w * fs;
-                sx += qf * e.x;
-                sy += qf * e.y;
-                szz += qf * e.z;
-                sp += e.w * ec;
-            }
-        };
-        auto fold = [&]() {
-            gfx += (double)sx; gfy += (double)sy; gfz += (double)szz; gph += (double)sp;
-            sx = sy = szz = sp = 0;
-        };
-        // make room for U more pairs in every lane's ring: rounds while a lane
-        // holds more than Q - U pairs or enough lanes still hold work (a lane
-        // evaluates at most Q pairs per drain before the FP64 fold)
-        auto drain = [&]() {
-            do {
-                round();
-            } while (__ballot(cnt > Q - U) != 0 || __popcll(__ballot(cnt > 0)) >= a.round_min);
-            fold();
-        };
-        auto push = [&](T dx, T dy, T dz, T qs) {
-            V4 e;
-            e.x = dx; e.y = dy; e.z = dz; e.w = qs;
-            queue[(head + cnt) & (Q - 1)][tid] = e;
-            cnt++;
-        };
+        Queue qu = make_queue<Queue>(lds, tid);
         // scan one run of sources [jb, jb + len) for pairs within r_c.  The
         // trip count is the wave maximum, so drains always run with every
         // lane.  Loads are issued U at a time ahead of their use: the loop is
@@ -333,48 +431,45 @@ __global__ __launch_bounds__(kBlock) void k_real(RealArgs a) {
                 // each to FP32; exact FP64 geometry for pairs within `near`
                 const uint4 *p16 = a.src16 + jb;
                 for (int m0 = 0; m0 < maxlen; m0 += U) {
-                    if (__ballot(cnt > Q - U) != 0) drain();
+                    if (qu.full()) qu.drain(alpha, c2a);
                     uint4 sv[U];
 #pragma unroll
                     for (int k = 0; k < U; k++) sv[k] = m0 + k < len ? p16[m0 + k] : make_uint4(0, 0, 0, 0);
 #pragma unroll
                     for (int k = 0; k < U; k++) {
                         const int m = m0 + k;
-                        if (m >= len) continue;
                         float dx = (float)(int)(xtf - sv[k].x) * d.ux;
                         float dy = (float)(int)(ytf - sv[k].y) * d.uy;
                         float dz = (float)(int)(tzf - sv[k].z) * d.uz;
                         const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                        if (r2 < d.rc2f && m != self) {
-                            if (r2 < d.near2f) {
-                                const double4 s64 = p[m];
-                                double ex = xt - s64.x, ey = yt - s64.y;
-                                ex -= d.Lx * rint(ex / d.Lx);
-                                ey -= d.Ly * rint(ey / d.Ly);
-                                dx = (float)ex; dy = (float)ey; dz = (float)(tz - s64.z);
-                            }
-                            push(dx, dy, dz, __uint_as_float(sv[k].w));
+                        const bool acc = m < len && r2 < d.rc2f && m != self;
+                        if (acc && r2 < d.near2f) {
+                            const double4 s64 = p[m];
+                            double ex = xt - s64.x, ey = yt - s64.y;
+                            ex -= d.Lx * rint(ex / d.Lx);
+                            ey -= d.Ly * rint(ey / d.Ly);
+                            dx = (float)ex; dy = (float)ey; dz = (float)(tz - s64.z);
                         }
+                        qu.push(acc, dx, dy, dz, __uint_as_float(sv[k].w));
                     }
                 }
                 return;
             }
             for (int m0 = 0; m0 < maxlen; m0 += U) {
-                if (__ballot(cnt > Q - U) != 0) drain();
+                if (qu.full()) qu.drain(alpha, c2a);
                 double4 sv[U];
 #pragma unroll
                 for (int k = 0; k < U; k++) sv[k] = m0 + k < len ? p[m0 + k] : make_double4(0, 0, 0, 0);
 #pragma unroll
                 for (int k = 0; k < U; k++) {
                     const int m = m0 + k;
-                    if (m >= len) continue;
                     double dx = xt - sv[k].x;
                     double dy = yt - sv[k].y;
                     if (allx) dx -= d.Lx * rint(dx / d.Lx);
                     if (ally) dy -= d.Ly * rint(dy / d.Ly);
                     const double dz = tz - sv[k].z;
                     const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-                    if (r2 < d.rc2 && m != self) push((T)dx, (T)dy, (T)dz, (T)sv[k].w);
+                    qu.push(m < len && r2 < d.rc2 && m != self, (T)dx, (T)dy, (T)dz, (T)sv[k].w);
                 }
             }
         };
@@ -426,13 +521,12 @@ __global__ __launch_bounds__(kBlock) void k_real(RealArgs a) {
                 if (__ballot(len2 > 0) != 0) scan(jb2, len2, xt, me.y - sy2, self2);
             }
         }
-        while (__ballot(cnt > 0) != 0) round();
-        fold();
-        fx = fma(w, gfx, fx);
-        fy = fma(w, gfy, fy);
-        fz = fma(w * zsign, gfz, fz);
-        phi = fma(w, gph, phi);
-        if (WANT_DG) { dpt = fma(dwt, gph, dpt); dpb = fma(dwb, gph, dpb); }
+        qu.flush(alpha, c2a);
+        fx = fma(w, qu.gx, fx);
+        fy = fma(w, qu.gy, fy);
+        fz = fma(w * zsign, qu.gz, fz);
+        phi = fma(w, qu.gp, phi);
+        if (WANT_DG) { dpt = fma(dwt, qu.gp, dpt); dpb = fma(dwb, qu.gp, dpb); }
     }
     double qphi = 0.0, qdt = 0.0, qdb = 0.0;
     if (active) {
@@ -479,7 +573,6 @@ hipError_t launch_real(rbe2d_ctx *h, const double *pos, const double *q, bool wa
     RealArgs r;
     r.src = h->w.sorted; r.src16 = h->w.src16; r.sidx = h->w.sidx; r.scell = h->w.scell; r.start = h->w.start;
     r.sys = h->w.sys; r.fam = h->w.fam; r.lay = h->w.lay; r.n_sys = h->n_sys; r.n_waves = h->n_swaves;
-    r.round_min = h->round_min;
     r.freal = h->w.freal; r.dgreal = h->w.dgreal; r.rpart = h->w.rpart;
     const int nbs = (h->n_swaves * kWave + kBlock - 1) / kBlock;
     r.nblocks = nbs;
