@@ -188,7 +188,8 @@ def run_grad(R, torch, steps):
     def fwd_bwd():
         s.energy(P_, Q_, out=E)
         s.energy_backward(P_, Q_, gE)
-    fwd_bwd()
+    for _ in range(3):
+        fwd_bwd()
     out["energy_fwd_bwd_fp64"] = w.N * steps / timed(torch, fwd_bwd, steps)
     fn = R.energy_function()
     gamma = torch.tensor([w.gamma_top, w.gamma_bot], dtype=torch.float64, device="cuda", requires_grad=True)
@@ -198,7 +199,8 @@ def run_grad(R, torch, steps):
     def autograd_step():
         e = fn.apply(Pg, Qg, gamma, s)
         e.backward()
-    autograd_step()
+    for _ in range(3):
+        autograd_step()
     out["autograd_fp64"] = w.N * steps / timed(torch, autograd_step, steps)
     s.forces(P_, Q_, out=F)
     out["plain_fp64_forces"] = w.N * steps / timed(torch, lambda: s.forces(P_, Q_, out=F), steps)

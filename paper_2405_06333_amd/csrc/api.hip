@@ -346,6 +346,11 @@ rbe2d_status create_handle(int n, const rbe2d_params *ps, bool batch, rbe2d_hand
     if (h->precision == RBE2D_PREC_FP32_PHASE) A(&w.src16, h->cap_sorted);
     A(&w.freal, nc); A(&w.dgreal, nc);
     A(&w.rpart, 3 * (h->cap_sorted / kWave));
+    // the split is only used when there are too few targets to fill the chip
+    h->split_cap = std::min<int64_t>(nc, 1 << 18);
+    A(&w.freal_s, kMaxRealSplit * h->split_cap);
+    A(&w.dgreal_s, kMaxRealSplit * h->split_cap);
+    A(&w.rpart_s, kMaxRealSplit * 3 * (h->cap_sorted / kWave));
     A(&w.err, 4);
     A(&w.step, 1);
     std::vector<SysDesc> descs(n);

@@ -26,6 +26,7 @@ constexpr int kKChunk64 = 8;         // k-vectors per structure-factor block, FP
 constexpr int kPPad = 16;            // P is padded to a multiple of this
 constexpr int kMaxFamilies = 128;    // real-space image families (order, side) per system
 constexpr int kWave = 64;
+constexpr int kMaxRealSplit = 5;     // real space: column groups a target's pair work may be split into
 constexpr double kPi = 3.14159265358979323846;
 
 // One family of image sources for the real-space sum, seen from the target:
@@ -115,6 +116,11 @@ struct Workspace {
     double4 *freal = nullptr;   // per caller particle: F_real (x, y, z), phi_real
     double2 *dgreal = nullptr;  // per caller particle: d phi_real / d gamma_{top,bot}
     double *rpart = nullptr;    // per real-space wave: sum q phi, sum q dphi/dg_top, .../dg_bot
+    // partial real-space outputs when the pair work of each target is split
+    // over several blocks (small N): [split][split_cap] / [split][waves]
+    double4 *freal_s = nullptr;
+    double2 *dgreal_s = nullptr;
+    double *rpart_s = nullptr;
     int *err = nullptr;         // device error word
     long long *step = nullptr;  // device MD step counter (graph replays)
 };
@@ -141,6 +147,7 @@ struct rbe2d_ctx {
     int64_t cap_particles = 0;       // padded k-space capacity (all systems)
     int64_t cap_sorted = 0;          // padded real-space capacity
     int total_cells = 0;
+    int64_t split_cap = 0;           // targets per split of the partial real-space outputs
     bool kset_valid = false;
     // current layout (host mirror); a layout is uploaded when it changes
     std::vector<int> lay_host;       // 5 x (n_sys + 1): off, pbase, bbase, tbase, sbase

@@ -9,6 +9,7 @@
 // target (x_i, y_i, sz z_i + cz) -- a reflection for odd l, a shift for even
 // l -- so every image family is another cell search around the transformed
 // target, done only when that point lies within r_c of the slab.
+#include <algorithm>
 #include <type_traits>
 
 #include "devmath.h"
@@ -173,6 +174,12 @@ struct RealArgs {
     double4 *freal;
     double2 *dgreal;
     double *rpart;              // per wave
+    int nsplit;                 // > 1: block row y handles x-columns y, y + nsplit, ... of every target
+    int64_t split_stride;       // targets per split in the partial outputs
+    int rsplit_stride;          // waves per split in the partial wave sums
+    double4 *freal_s;
+    double2 *dgreal_s;
+    double *rpart_s;
 };
 
 template <bool FP32> struct RealTypes;
@@ -477,7 +484,7 @@ __global__ __launch_bounds__(kBlock) void k_real(RealArgs a) {
         for (int lz = wzlo; lz <= wzhi; lz++) {
             const bool lay_on = lz >= lzlo && lz <= lzhi;
             const double dzmin = fmax(0.0, fmax(lz * d.hz - tz, tz - (lz + 1) * d.hz));
-            for (int ox = xlo; ox <= xhi; ox++) {
+            for (int ox = xlo + (int)blockIdx.y; ox <= xhi; ox += a.nsplit) {
                 const int dxc = allx ? ox - cx : ox;       // column offset in cells
                 int cxx = allx ? ox : cx + ox;
                 if (!allx) cxx += cxx < 0 ? d.ncx : (cxx >= d.ncx ? -d.ncx : 0);
@@ -532,10 +539,18 @@ __global__ __launch_bounds__(kBlock) void k_real(RealArgs a) {
     if (active) {
         const int i = a.sidx[t];
         const double qi = me.w * d.pref;
-        a.freal[i] = make_double4(qi * fx, qi * fy, qi * fz, d.pref * phi);
+        const double4 fo = make_double4(qi * fx, qi * fy, qi * fz, d.pref * phi);
+        const double2 go = make_double2(d.pref * dpt, d.pref * dpb);
+        if (a.nsplit > 1) {
+            const int64_t o = (int64_t)blockIdx.y * a.split_stride + i;
+            a.freal_s[o] = fo;
+            if (WANT_DG) a.dgreal_s[o] = go;
+        } else {
+            a.freal[i] = fo;
+            if (WANT_DG) a.dgreal[i] = go;
+        }
         qphi = qi * phi;
         if (WANT_DG) {
-            a.dgreal[i] = make_double2(d.pref * dpt, d.pref * dpb);
             qdt = qi * dpt;
             qdb = qi * dpb;
         }
@@ -545,9 +560,36 @@ __global__ __launch_bounds__(kBlock) void k_real(RealArgs a) {
     if (WANT_DG) { qdt = wave_sum(qdt); qdb = wave_sum(qdb); }
     if ((tid & (kWave - 1)) == 0 && t / kWave < a.n_waves) {
         const int wv = t / kWave;
-        a.rpart[3 * wv] = qphi;
-        a.rpart[3 * wv + 1] = qdt;
-        a.rpart[3 * wv + 2] = qdb;
+        double *o = a.nsplit > 1 ? a.rpart_s + 3 * ((int64_t)blockIdx.y * a.rsplit_stride + wv) : a.rpart + 3 * wv;
+        o[0] = qphi;
+        o[1] = qdt;
+        o[2] = qdb;
+    }
+}
+
+// sum of the split partial outputs, in split order
+__global__ __launch_bounds__(kBlock) void k_real_combine(RealArgs a, int n_total, int want_dg) {
+    const int g = blockIdx.x * kBlock + threadIdx.x;
+    if (g < n_total) {
+        double4 f = a.freal_s[g];
+        double2 dg = want_dg ? a.dgreal_s[g] : make_double2(0.0, 0.0);
+        for (int s = 1; s < a.nsplit; s++) {
+            const double4 v = a.freal_s[(int64_t)s * a.split_stride + g];
+            f.x += v.x; f.y += v.y; f.z += v.z; f.w += v.w;
+            if (want_dg) {
+                const double2 u = a.dgreal_s[(int64_t)s * a.split_stride + g];
+                dg.x += u.x; dg.y += u.y;
+            }
+        }
+        a.freal[g] = f;
+        if (want_dg) a.dgreal[g] = dg;
+    }
+    if (g < a.n_waves) {
+        for (int c = 0; c < 3; c++) {
+            double v = 0.0;
+            for (int s = 0; s < a.nsplit; s++) v += a.rpart_s[3 * ((int64_t)s * a.rsplit_stride + g) + c];
+            a.rpart[3 * g + c] = v;
+        }
     }
 }
 
@@ -574,17 +616,31 @@ hipError_t launch_real(rbe2d_ctx *h, const double *pos, const double *q, bool wa
     r.src = h->w.sorted; r.src16 = h->w.src16; r.sidx = h->w.sidx; r.scell = h->w.scell; r.start = h->w.start;
     r.sys = h->w.sys; r.fam = h->w.fam; r.lay = h->w.lay; r.n_sys = h->n_sys; r.n_waves = h->n_swaves;
     r.freal = h->w.freal; r.dgreal = h->w.dgreal; r.rpart = h->w.rpart;
+    r.freal_s = h->w.freal_s; r.dgreal_s = h->w.dgreal_s; r.rpart_s = h->w.rpart_s;
+    r.split_stride = h->split_cap;
+    r.rsplit_stride = (int)(h->cap_sorted / kWave);
+    // too few targets to fill the chip: split each target's x-columns over
+    // several blocks (about 4096 waves in flight is enough)
+    r.nsplit = 1;
+    if (h->n_total <= h->split_cap)
+        r.nsplit = (int)std::min<int64_t>(kMaxRealSplit, std::max<int64_t>(1, 4096 / std::max(1, h->n_swaves)));
     const int nbs = (h->n_swaves * kWave + kBlock - 1) / kBlock;
     r.nblocks = nbs;
     const int nb8 = (nbs + 7) / 8 * 8;
     const bool fp32 = h->precision == RBE2D_PREC_FP32_PHASE;
+    const dim3 grid(nb8, r.nsplit);
     prof_begin(h, 4, s);
     if (fp32) {
-        if (want_dg) hipLaunchKernelGGL((k_real<true, true>), dim3(nb8), dim3(kBlock), 0, s, r);
-        else hipLaunchKernelGGL((k_real<true, false>), dim3(nb8), dim3(kBlock), 0, s, r);
+        if (want_dg) hipLaunchKernelGGL((k_real<true, true>), grid, dim3(kBlock), 0, s, r);
+        else hipLaunchKernelGGL((k_real<true, false>), grid, dim3(kBlock), 0, s, r);
     } else {
-        if (want_dg) hipLaunchKernelGGL((k_real<false, true>), dim3(nb8), dim3(kBlock), 0, s, r);
-        else hipLaunchKernelGGL((k_real<false, false>), dim3(nb8), dim3(kBlock), 0, s, r);
+        if (want_dg) hipLaunchKernelGGL((k_real<false, true>), grid, dim3(kBlock), 0, s, r);
+        else hipLaunchKernelGGL((k_real<false, false>), grid, dim3(kBlock), 0, s, r);
+    }
+    if (r.nsplit > 1) {
+        const int64_t n = std::max<int64_t>(h->n_total, h->n_swaves);
+        hipLaunchKernelGGL(k_real_combine, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, r,
+                           (int)h->n_total, (int)want_dg);
     }
     prof_end(h, 4, s);
     return hipGetLastError();

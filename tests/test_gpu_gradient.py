@@ -177,3 +177,7 @@ def test_autograd_function(torch, R):
     assert np.array_equal(G_.grad.cpu().numpy(), dg)
     F = slab.forces(to_dev(torch, pos), to_dev(torch, q)).cpu().numpy()
     assert np.allclose(dr, -3.0 * F, rtol=1e-12, atol=1e-12 * np.abs(F).max())
+    # gamma other than the slab's contrasts is refused
+    G_bad = torch.tensor([w.gamma_top, 0.5], dtype=torch.float64, device="cuda", requires_grad=True)
+    with pytest.raises(ValueError):
+        Fn.apply(P_, Q_, G_bad, slab)

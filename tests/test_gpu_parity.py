@@ -113,7 +113,7 @@ def test_ragged_and_degenerate(torch, R, orc, precision, case):
     w = inputs.small_random(100 + N, N, L=10.0, H=H, gamma_top=gt, gamma_bot=gb, alpha=1.1, r_c=rc,
                             P=P, M=M, margin=0.05)
     F, E, ref, _ = run_pair(torch, R, orc, w, precision)
-    assert_parity(F, E, ref, TOL[precision] * (3 if precision == "fp32" else 1))
+    assert_parity(F, E, ref, TOL[precision])
 
 
 def test_small_box_minimum_image(torch, R, orc):
