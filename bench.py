@@ -50,6 +50,7 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=20000, help="particles in the oracle's rho sample")
     ap.add_argument("--cpu-targets", type=int, default=32, help="oracle force targets")
     ap.add_argument("--side-steps", type=int, default=10, help="steps of each side measurement (0 = skip)")
+    ap.add_argument("--no-autotune", action="store_true", help="use the built-in launch heuristics")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (HBM counter calibration)")
     return ap.parse_args()
@@ -75,7 +76,7 @@ def expected_real_pairs(w, nz=4000):
     return float(rho * w.N * np.mean(direct + img))
 
 
-def run_md(R, torch, w, precision, steps, warmup, profile, use_graph=False):
+def run_md(R, torch, w, precision, steps, warmup, profile, use_graph=False, autotune=True):
     from paper_2405_06333_amd import inputs
     pos, q = inputs.sample(w)
     dev = "cuda"
@@ -85,6 +86,7 @@ def run_md(R, torch, w, precision, steps, warmup, profile, use_graph=False):
     F_ = torch.zeros_like(P_)
     slab = R.Slab(**w.slab_kwargs(), precision=precision, n_max=w.N)
     slab.sample_kset(w.seed, 0)
+    tuned = slab.autotune(P_, Q_) if autotune else None
     slab.forces(P_, Q_, out=F_)
     zlo, zhi = w.margin, w.H - w.margin
     step = 1
@@ -103,7 +105,7 @@ def run_md(R, torch, w, precision, steps, warmup, profile, use_graph=False):
     prof = slab.profile_read() if profile else None
     slab.check()
     finite = bool(torch.isfinite(F_).all().item() and torch.isfinite(P_).all().item())
-    return (t1 - t0), prof, finite
+    return (t1 - t0), prof, finite, tuned
 
 
 def timed(torch, fn, steps):
@@ -115,7 +117,7 @@ def timed(torch, fn, steps):
     return time.perf_counter() - t0
 
 
-def run_batch(R, torch, steps):
+def run_batch(R, torch, steps, autotune=True):
     """64 replicas of uneven N and different contrasts: batched MD steps
     (graph replays) in FP32 phases and in FP64, against the plain path --
     one single-system FP64 handle per replica, stepped one after another."""
@@ -135,6 +137,8 @@ def run_batch(R, torch, steps):
         Q_ = torch.as_tensor(q, device="cuda")
         V_ = torch.zeros_like(P_)
         b.sample_kset(ws[0].seed, 0)
+        if autotune:
+            out[f"tuned_{prec}"] = b.autotune(off, P_, Q_)
         F_ = b.forces(off, P_, Q_)
         b.md_run(off, P_, V_, Q_, F_, ws[0].dt, margin, ws[0].seed, 1, 2, use_graph=True)
         t = timed(torch, lambda: b.md_run(off, P_, V_, Q_, F_, ws[0].dt, margin, ws[0].seed, 3, steps,
@@ -152,6 +156,8 @@ def run_batch(R, torch, steps):
              for r in range(len(ws))]
     for r, s in enumerate(slabs):
         s.sample_kset(ws[r].seed, 0)
+        if autotune:
+            s.autotune(views[r][0], views[r][2])
         s.forces(views[r][0], views[r][2], out=views[r][3])
 
     def plain_steps(step0, n):
@@ -169,7 +175,7 @@ def run_batch(R, torch, steps):
     return out
 
 
-def run_grad(R, torch, steps):
+def run_grad(R, torch, steps, autotune=True):
     """Differentiable energy: forward energy + hand-written adjoint (dE/dr,
     dE/dq, dE/dgamma, rho(k) recomputed) per step, against plain FP64 forces
     on the same system and k-set."""
@@ -181,6 +187,8 @@ def run_grad(R, torch, steps):
     out = {"workload": f"gradient: N={w.N}, {w.Lx:g}x{w.Ly:g}x{w.H:g}, P={w.P}, M={w.M}", "unit": "particle-steps/s"}
     s = R.Slab(**w.slab_kwargs(), precision="fp64", n_max=w.N)
     s.set_kset(s.draw_kset(w.seed, 0))
+    if autotune:
+        out["tuned"] = s.autotune(P_, Q_)
     gE = torch.ones((), dtype=torch.float64, device="cuda")
     E = torch.empty(5, dtype=torch.float64, device="cuda")
     F = torch.empty_like(P_)
@@ -268,7 +276,8 @@ def main():
     from paper_2405_06333_amd import inputs, rbe2d as R
     R.lib()
     w = inputs.LARGE_MD
-    secs, prof, finite = run_md(R, torch, w, a.precision, a.steps, a.warmup, profile=True)
+    secs, prof, finite, tuned = run_md(R, torch, w, a.precision, a.steps, a.warmup, profile=True,
+                                       autotune=not a.no_autotune)
     ms_step = secs * 1e3 / a.steps
     value = w.N * a.steps / secs
 
@@ -303,15 +312,16 @@ def main():
 
     fp64 = None
     if a.fp64_steps > 0 and a.precision != "fp64":
-        s64, _, _ = run_md(R, torch, w, "fp64", a.fp64_steps, 1, profile=False)
+        s64, _, _, _ = run_md(R, torch, w, "fp64", a.fp64_steps, 1, profile=False, autotune=not a.no_autotune)
         fp64 = {"value": w.N * a.fp64_steps / s64, "unit": "particle-steps/s", "steps": a.fp64_steps}
 
     graph = batch = grad = None
     if a.side_steps > 0:
-        sg, _, _ = run_md(R, torch, w, a.precision, a.side_steps, 1, profile=False, use_graph=True)
+        sg, _, _, _ = run_md(R, torch, w, a.precision, a.side_steps, 1, profile=False, use_graph=True,
+                             autotune=not a.no_autotune)
         graph = {"value": w.N * a.side_steps / sg, "unit": "particle-steps/s", "steps": a.side_steps}
-        batch = run_batch(R, torch, a.side_steps)
-        grad = run_grad(R, torch, a.side_steps)
+        batch = run_batch(R, torch, a.side_steps, autotune=not a.no_autotune)
+        grad = run_grad(R, torch, a.side_steps, autotune=not a.no_autotune)
     cpu = None if a.no_cpu_baseline else cpu_baseline(w, a.cpu_sample, a.cpu_targets)
     out = {
         "metric": METRIC,
@@ -337,6 +347,7 @@ def main():
         "md_graph": graph,
         "batched_replicas": batch,
         "differentiable": grad,
+        "launch_params": tuned,
         "kernels": kern,
         "finite": finite,
     }

@@ -220,6 +220,21 @@ rbe2d_status rbe2d_batch_md_run(rbe2d_handle h, const int64_t *offsets, double *
                                 uint64_t seed, int64_t step0, int32_t n_steps, int32_t use_graph,
                                 void *stream);
 
+/* Autotuner.  Times, with HIP events on `stream`, the candidate launch
+ * parameters of the evaluation for the particle layout given by offsets
+ * (host, n_sys + 1 int64, as in rbe2d_batch_forces; {0, N} for a single
+ * system) on the caller's pos and q (device) and the current k-set:
+ * particles per thread of the structure-factor tiles (1..16), the k-range
+ * split of the force pass (1..64) and, for small systems, the x-column split
+ * of the pair work (1..5).  The fastest are kept in the handle and used by
+ * every later call with the same per-system counts (other layouts use the
+ * built-in heuristics); a cached MD graph is dropped.  Writes the three
+ * choices to chosen (host int[3]) when not NULL.  Synchronises `stream`;
+ * not to be called during graph capture.  Results of later calls change only
+ * by summation order.  Errors as rbe2d_batch_forces. */
+rbe2d_status rbe2d_autotune(rbe2d_handle h, const int64_t *offsets, const double *pos, const double *q,
+                            int32_t *chosen, void *stream);
+
 /* Kernel timing (tracing).  rbe2d_profile_enable(h, n) creates n event
  * pairs per kernel class and from then on brackets every launch of each
  * class with HIP events on the launch stream (n = 0 turns timing off and

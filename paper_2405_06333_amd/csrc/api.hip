@@ -397,13 +397,21 @@ rbe2d_status set_layout(rbe2d_ctx *h, const int64_t *counts, hipStream_t s) {
     }
     const bool fp32 = h->precision == RBE2D_PREC_FP32_PHASE;
     const int nkc = h->P_pad / (fp32 ? kKChunk32 : kKChunk64);
-    // tile size: enough tiles to fill the chip, padding under ~10% of the particles
-    int per = choose_tile(total, nkc);
-    for (; per > 1; per >>= 1) {
-        int64_t padded = 0;
-        const int64_t tile = (int64_t)kBlock * per;
-        for (int r = 0; r < n; r++) padded += (counts[r] + tile - 1) / tile * tile;
-        if (padded <= total + total / 10 + tile) break;
+    h->tuned_now = !h->tune.counts.empty() && std::equal(counts, counts + n, h->tune.counts.begin());
+    int per;
+    if (h->force_per) {
+        per = h->force_per;
+    } else if (h->tuned_now && h->tune.per) {
+        per = h->tune.per;
+    } else {
+        // tile size: enough tiles to fill the chip, padding under ~10% of the particles
+        per = choose_tile(total, nkc);
+        for (; per > 1; per >>= 1) {
+            int64_t padded = 0;
+            const int64_t tile = (int64_t)kBlock * per;
+            for (int r = 0; r < n; r++) padded += (counts[r] + tile - 1) / tile * tile;
+            if (padded <= total + total / 10 + tile) break;
+        }
     }
     const int tile = kBlock * per;
     std::vector<int> lay(5 * (n + 1), 0);
@@ -737,6 +745,106 @@ rbe2d_status rbe2d_batch_md_run(rbe2d_handle h, const int64_t *offsets, double *
     if (!(dt > 0.0) || !(wall_margin > 0.0 && 2 * wall_margin < hmin) || n_steps < 0)
         return fail(h, RBE2D_E_INVAL, "need dt > 0, 0 < wall_margin < H/2, n_steps >= 0");
     return md_run(h, pos, vel, q, F, dt, wall_margin, wall_margin, seed, step0, n_steps, use_graph != 0, s);
+}
+
+rbe2d_status rbe2d_autotune(rbe2d_handle h, const int64_t *offsets, const double *pos, const double *q,
+                            int32_t *chosen, void *stream) {
+    if (!h) return fail(nullptr, RBE2D_E_INVAL, "handle is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    if (!offsets) return fail(h, RBE2D_E_INVAL, "offsets is NULL");
+    if (offsets[0] != 0) return fail(h, RBE2D_E_INVAL, "offsets[0] must be 0");
+    std::vector<int64_t> counts(h->n_sys);
+    for (int r = 0; r < h->n_sys; r++) {
+        counts[r] = offsets[r + 1] - offsets[r];
+        if (counts[r] < 0 || counts[r] > h->sys[r].p.n_max)
+            return fail(h, RBE2D_E_INVAL, "system %d: N outside [0, n_max]", r);
+    }
+    int64_t total = 0;
+    for (int64_t c : counts) total += c;
+    if (!h->kset_valid) return fail(h, RBE2D_E_STATE, "no k-set: call rbe2d_set_kset or rbe2d_sample_kset");
+    if (total > 0 && (!pos || !q)) return fail(h, RBE2D_E_INVAL, "pos or q is NULL");
+    RBE2D_TRY(h, hipStreamSynchronize(s), "autotune sync");
+    free_graph(h);                 // a captured step holds the old launch parameters
+    h->tune = rbe2d_ctx::Tuning();
+    const int prof_n = h->prof.n;
+    h->prof.n = 0;                 // the trials are not traced
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    rbe2d_status st = RBE2D_OK;
+    hipError_t he = hipEventCreate(&e0);
+    if (he == hipSuccess) he = hipEventCreate(&e1);
+    // minimum over reps of the duration of the launches `fn` enqueues
+    auto time = [&](auto fn, int reps, float *best) -> rbe2d_status {
+        *best = 1e30f;
+        for (int i = 0; i < reps; i++) {
+            RBE2D_TRY(h, hipEventRecord(e0, s), "autotune event");
+            RBE2D_TRY(h, fn(), "autotune launch");
+            RBE2D_TRY(h, hipEventRecord(e1, s), "autotune event");
+            RBE2D_TRY(h, hipEventSynchronize(e1), "autotune sync");
+            float ms = 0.0f;
+            RBE2D_TRY(h, hipEventElapsedTime(&ms, e0, e1), "autotune elapsed");
+            *best = std::min(*best, ms);
+        }
+        return RBE2D_OK;
+    };
+    int best_per = 1, best_ks = 1, best_rs = 1;
+    if (he != hipSuccess) st = hipfail(h, he, "autotune events");
+    // 1. particles per thread of the structure-factor tiles
+    float tbest = 1e30f;
+    for (int per = kMaxTileThreads; st == RBE2D_OK && per >= 1 && total > 0; per >>= 1) {
+        h->force_per = per;
+        st = set_layout(h, counts.data(), s);
+        float t = 0.0f;
+        if (st == RBE2D_OK)
+            st = time([&] {
+                hipError_t e = launch_prep(h, pos, q, s);
+                return e == hipSuccess ? launch_kcoef_sf(h, s) : e;
+            }, 3, &t);
+        if (st == RBE2D_OK && t < tbest) { tbest = t; best_per = per; }
+    }
+    // 2. k-range split of the force pass (the per-k records of the chosen tiling)
+    h->force_per = best_per;
+    if (st == RBE2D_OK) st = set_layout(h, counts.data(), s);
+    if (st == RBE2D_OK && total > 0) {
+        const hipError_t e = launch_prep(h, pos, q, s);
+        if (e != hipSuccess) st = hipfail(h, e, "autotune prep");
+        else if ((he = launch_kcoef_sf(h, s)) != hipSuccess) st = hipfail(h, he, "autotune sf");
+    }
+    tbest = 1e30f;
+    for (int ks = 1; st == RBE2D_OK && ks <= 64 && total > 0; ks <<= 1) {
+        if ((int64_t)ks * h->n_blocks > std::min<int64_t>(64 * (h->cap_particles / kBlock), 4096)) break;
+        h->force_ksplit = ks;
+        float t = 0.0f;
+        // the real-space output array serves as scratch for the forces
+        st = time([&] {
+            return launch_kforce(h, pos, q, (double *)h->w.freal, nullptr, RBE2D_KSPACE, false, false, false,
+                                 nullptr, s);
+        }, 3, &t);
+        if (st == RBE2D_OK && t < tbest) { tbest = t; best_ks = ks; }
+    }
+    h->force_ksplit = 0;
+    // 3. column-group split of the pair work (small systems only)
+    tbest = 1e30f;
+    for (int rs = 1; st == RBE2D_OK && rs <= kMaxRealSplit && total > 0 && total <= h->split_cap; rs++) {
+        h->force_rsplit = rs;
+        float t = 0.0f;
+        st = time([&] { return launch_real(h, pos, q, false, s); }, 3, &t);
+        if (st == RBE2D_OK && t < tbest) { tbest = t; best_rs = rs; }
+    }
+    h->force_rsplit = 0;
+    h->force_per = 0;
+    h->prof.n = prof_n;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (st) return st;
+    h->tune.counts = counts;
+    h->tune.per = best_per;
+    h->tune.ksplit = best_ks;
+    h->tune.rsplit = best_rs;
+    st = set_layout(h, counts.data(), s);
+    if (st) return st;
+    if (chosen) { chosen[0] = best_per; chosen[1] = best_ks; chosen[2] = best_rs; }
+    RBE2D_TRY(h, hipStreamSynchronize(s), "autotune sync");
+    return RBE2D_OK;
 }
 
 rbe2d_status rbe2d_profile_enable(rbe2d_handle h, int32_t n_events) {

@@ -11,6 +11,8 @@
 //    fract(nx fxh) + nx fxl + ... keeps ~1e-8 revolution accuracy, and the
 //    hardware v_sin_f32/v_cos_f32 take revolutions directly.
 //  * FP64 path: plain FP64 phase and a quarter-turn-reduced Taylor sincos.
+#include <algorithm>
+
 #include "devmath.h"
 #include "rbe2d_internal.h"
 
@@ -565,7 +567,14 @@ hipError_t launch_kforce(rbe2d_ctx *h, const double *pos, const double *q, doubl
     a.fpart = h->w.fpart; a.F = F; a.dEdq = dEdq; a.gE = gE;
     a.accumulate = accumulate; a.add_real = add_real; a.want_pot = want_pot;
     a.do_kspace = (flags & RBE2D_KSPACE) != 0; a.do_ibc = (flags & RBE2D_IBC) != 0;
-    const int split = a.do_kspace ? choose_ksplit(h->n_blocks, h->P) : 1;
+    int split = 1;
+    if (a.do_kspace) {
+        split = h->force_ksplit ? h->force_ksplit
+                                : (h->tuned_now && h->tune.ksplit ? h->tune.ksplit : choose_ksplit(h->n_blocks, h->P));
+        // the partial buffer holds 4096 blocks' worth (or 64 splits of every block)
+        while (split > 1 && (int64_t)split * h->n_blocks > std::min<int64_t>(64 * (h->cap_particles / kBlock), 4096))
+            split >>= 1;
+    }
     a.k_per_split = (h->P + split - 1) / split;
     a.split = split > 1;
     const bool fp32 = h->precision == RBE2D_PREC_FP32_PHASE;

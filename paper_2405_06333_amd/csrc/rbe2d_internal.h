@@ -163,6 +163,14 @@ struct rbe2d_ctx {
     int32_t *kstage = nullptr;       // pinned staging of host k-set uploads
     hipEvent_t kev = nullptr;        // completion of the last upload from kstage
     bool kev_pending = false;
+    // launch parameters: tuned for one particle layout by rbe2d_autotune, else
+    // heuristic; force_* override both while the tuner times candidates
+    struct Tuning {
+        std::vector<int64_t> counts;   // per-system particle counts the values were tuned for
+        int per = 0, ksplit = 0, rsplit = 0;
+    } tune;
+    bool tuned_now = false;          // the current layout is the tuned one
+    int force_per = 0, force_ksplit = 0, force_rsplit = 0;
     // cached graph of one MD step
     hipGraphExec_t md_exec = nullptr;
     hipGraph_t md_graph = nullptr;

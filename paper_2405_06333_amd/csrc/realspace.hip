@@ -16,6 +16,19 @@
 #include "erfcx_fit.h"
 #include "rbe2d_internal.h"
 
+// Compile-time parameters of the FP32 pair kernel (measured best on the
+// 1e6-ion slab: 16-entry rings halve the occupancy, 2 loads in flight leave
+// latency exposed, the drain threshold hardly matters).
+#ifndef RBE2D_REAL_U32
+#define RBE2D_REAL_U32 4      // source loads in flight per lane
+#endif
+#ifndef RBE2D_RING_Q
+#define RBE2D_RING_Q 8        // ring entries per lane (a power of two)
+#endif
+#ifndef RBE2D_ROUND_MIN
+#define RBE2D_ROUND_MIN 40    // keep draining while this many lanes hold pairs
+#endif
+
 namespace rbe2d {
 
 __global__ void k_fill(uint32_t *p, int64_t n) {
@@ -184,7 +197,7 @@ struct RealArgs {
 
 template <bool FP32> struct RealTypes;
 // U: source loads in flight per lane
-template <> struct RealTypes<true> { using T = float; using V4 = float4; static constexpr int U = 4; };
+template <> struct RealTypes<true> { using T = float; using V4 = float4; static constexpr int U = RBE2D_REAL_U32; };
 template <> struct RealTypes<false> { using T = double; using V4 = double4; static constexpr int U = 2; };
 
 // erfc(alpha d)/d (ec) and the radial force factor fs = [erfc(a d)/d + 2a/sqrt(pi) e^{-a^2 d^2}]/d^2
@@ -221,7 +234,7 @@ __device__ __forceinline__ void pair_terms(double r2, double alpha, double c2a, 
 // its lane) at the price of idle lanes in the rounds.
 template <int Q, int U>
 struct LaneRings {
-    static constexpr int kRoundMin = 40;   // keep draining while this many lanes hold pairs
+    static constexpr int kRoundMin = RBE2D_ROUND_MIN;   // keep draining while this many lanes hold pairs
     float4 (*ring)[kBlock];
     int tid, head = 0, cnt = 0;
     float sx = 0, sy = 0, sz = 0, sp = 0;
@@ -352,8 +365,9 @@ __device__ __forceinline__ int wave_min(int v) {
 // results are bitwise reproducible.
 template <typename Queue> __device__ Queue make_queue(unsigned char *lds, int tid);
 template <>
-__device__ LaneRings<8, 4> make_queue<LaneRings<8, 4>>(unsigned char *lds, int tid) {
-    return LaneRings<8, 4>(reinterpret_cast<float4(*)[kBlock]>(lds), tid);
+__device__ LaneRings<RBE2D_RING_Q, RBE2D_REAL_U32> make_queue<LaneRings<RBE2D_RING_Q, RBE2D_REAL_U32>>(
+    unsigned char *lds, int tid) {
+    return LaneRings<RBE2D_RING_Q, RBE2D_REAL_U32>(reinterpret_cast<float4(*)[kBlock]>(lds), tid);
 }
 template <>
 __device__ WaveQueue<256, 2> make_queue<WaveQueue<256, 2>>(unsigned char *lds, int tid) {
@@ -370,7 +384,7 @@ __global__ __launch_bounds__(kBlock) void k_real(RealArgs a) {
     using T = typename RealTypes<FP32>::T;
     constexpr int U = RealTypes<FP32>::U;
     constexpr int NW = kBlock / kWave;
-    constexpr int kRingQ = 8;      // FP32: ring entries per lane
+    constexpr int kRingQ = RBE2D_RING_Q;   // FP32: ring entries per lane
     constexpr int kWaveQ = 256;    // FP64: queue entries per wave
     using Queue = typename std::conditional<FP32, LaneRings<kRingQ, U>, WaveQueue<kWaveQ, U>>::type;
     constexpr size_t kLds = FP32 ? sizeof(float4) * kRingQ * kBlock
@@ -622,8 +636,12 @@ hipError_t launch_real(rbe2d_ctx *h, const double *pos, const double *q, bool wa
     // too few targets to fill the chip: split each target's x-columns over
     // several blocks (about 4096 waves in flight is enough)
     r.nsplit = 1;
-    if (h->n_total <= h->split_cap)
-        r.nsplit = (int)std::min<int64_t>(kMaxRealSplit, std::max<int64_t>(1, 4096 / std::max(1, h->n_swaves)));
+    if (h->n_total <= h->split_cap) {
+        if (h->force_rsplit) r.nsplit = h->force_rsplit;
+        else if (h->tuned_now && h->tune.rsplit) r.nsplit = h->tune.rsplit;
+        else r.nsplit = (int)std::min<int64_t>(kMaxRealSplit, std::max<int64_t>(1, 4096 / std::max(1, h->n_swaves)));
+        r.nsplit = std::max(1, std::min(kMaxRealSplit, r.nsplit));
+    }
     const int nbs = (h->n_swaves * kWave + kBlock - 1) / kBlock;
     r.nblocks = nbs;
     const int nb8 = (nbs + 7) / 8 * 8;

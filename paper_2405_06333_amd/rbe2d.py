@@ -24,7 +24,7 @@ EXPORTS = ("rbe2d_create", "rbe2d_destroy", "rbe2d_query", "rbe2d_draw_kset", "r
            "rbe2d_sample_kset", "rbe2d_get_kset", "rbe2d_forces", "rbe2d_energy",
            "rbe2d_energy_backward", "rbe2d_md_run", "rbe2d_profile_enable", "rbe2d_profile_read",
            "rbe2d_check", "rbe2d_last_error", "rbe2d_batch_create", "rbe2d_query_system",
-           "rbe2d_batch_forces", "rbe2d_batch_md_run")
+           "rbe2d_batch_forces", "rbe2d_batch_md_run", "rbe2d_autotune")
 PROF_SLOTS = ("prep", "sf_pass", "assemble", "cell_build", "real_pairs", "force_scatter", "energy",
               "integrator", "ksample")
 
@@ -75,6 +75,7 @@ def lib():
         L.rbe2d_batch_forces.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_uint32, _vp]
         L.rbe2d_batch_md_run.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_double,
                                          ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _vp]
+        L.rbe2d_autotune.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
         L.rbe2d_profile_enable.argtypes = [_vp, ctypes.c_int32]
         L.rbe2d_profile_read.argtypes = [_vp, _vp, _vp, ctypes.c_int32]
         L.rbe2d_check.argtypes = [_vp, _vp]
@@ -225,6 +226,20 @@ class Slab:
             float(z_lo), float(z_hi), ctypes.c_uint64(seed), int(step0), int(n_steps), int(bool(use_graph)),
             _stream()))
 
+    def autotune(self, pos, q):
+        """Time the candidate launch parameters for this N on these inputs and
+        keep the fastest; returns {per, ksplit, rsplit}."""
+        import torch
+        N = int(q.shape[0])
+        return self._autotune(np.array([0, N], dtype=np.int64), _dptr(pos, torch.float64, (N, 3), "pos"),
+                              _dptr(q, torch.float64, (N,), "q"))
+
+    def _autotune(self, off, p, q):
+        ch = np.zeros(3, dtype=np.int32)
+        self._ok(lib().rbe2d_autotune(self._h, ctypes.c_void_p(off.ctypes.data), p, q,
+                                      ctypes.c_void_p(ch.ctypes.data), _stream()))
+        return {"per": int(ch[0]), "ksplit": int(ch[1]), "rsplit": int(ch[2])}
+
     def profile_enable(self, n_events):
         self._ok(lib().rbe2d_profile_enable(self._h, int(n_events)))
 
@@ -312,6 +327,12 @@ class BatchedSlab(Slab):
             _dptr(q, torch.float64, (N,), "q"), _dptr(F, torch.float64, (N, 3), "F"),
             _dptr(E, torch.float64, (self.n_sys, 5), "energy"), flags, _stream()))
         return (F, E) if want_energy else F
+
+    def autotune(self, offsets, pos, q):
+        import torch
+        off = self._off(offsets)
+        N = int(off[-1])
+        return self._autotune(off, _dptr(pos, torch.float64, (N, 3), "pos"), _dptr(q, torch.float64, (N,), "q"))
 
     def md_run(self, offsets, pos, vel, q, F, dt, wall_margin, seed, step0, n_steps, use_graph=False):
         import torch

@@ -244,3 +244,51 @@ def test_replica_batch_sampled_parity(torch, R, orc):
                            kset[r], targets=tg)
         err = rel_rms(F[off[r] + tg], ref.F)
         assert err <= 1e-5, f"replica {r}: sampled force rel-RMS {err:.3e}"
+
+
+def test_autotune_single_keeps_results(torch, R, orc):
+    w = inputs.DIELECTRIC
+    pos, q = inputs.sample(w)
+    s = R.Slab(**w.slab_kwargs(), precision="fp64", n_max=w.N)
+    kset = s.draw_kset(w.seed, 0)
+    s.set_kset(kset)
+    P_, Q_ = to_dev(torch, pos), to_dev(torch, q)
+    F0, E0 = s.forces(P_, Q_, want_energy=True)
+    ch = s.autotune(P_, Q_)
+    assert ch["per"] in (1, 2, 4, 8, 16) and ch["ksplit"] in (1, 2, 4, 8, 16, 32, 64) and 1 <= ch["rsplit"] <= 5
+    F1, E1 = s.forces(P_, Q_, want_energy=True)
+    s.check()
+    F0, F1 = F0.cpu().numpy(), F1.cpu().numpy()
+    assert rel_rms(F1, F0) <= 1e-12
+    assert np.allclose(E1.cpu().numpy(), E0.cpu().numpy(), rtol=1e-12, atol=1e-12 * float(np.abs(E0.cpu().numpy()).sum()))
+    ref = orc.evaluate(oracle_slab(orc, w, s.Lz_ext), pos, q, kset)
+    assert rel_rms(F1, ref.F) <= 1e-9
+
+
+def test_autotune_batch_then_graph(torch, R, orc):
+    ws = MIXED
+    pos, q, counts = batch_inputs(ws)
+    b = make_batch(R, ws, "fp32")
+    off = b.offsets(counts)
+    b.set_kset(b.draw_kset(5, 0))
+    P_, Q_ = to_dev(torch, pos), to_dev(torch, q)
+    ch = b.autotune(off, P_, Q_)
+    assert ch["per"] in (1, 2, 4, 8, 16)
+    kset = b.get_kset()
+    F = b.forces(off, P_, Q_).cpu().numpy()
+    for r, w in enumerate(ws):
+        if not w.N:
+            continue
+        ref = orc.evaluate(oracle_slab(orc, w, b.Lz_ext[r]), pos[off[r]:off[r + 1]], q[off[r]:off[r + 1]], kset[r])
+        assert rel_rms(F[off[r]:off[r + 1]], ref.F) <= 1e-5
+    # tuned launch parameters inside a captured MD step
+    runs = []
+    for use_graph in (False, True):
+        P2, V2, Q2 = _md_state(torch, pos, q, 3)
+        b.set_kset(kset)
+        F2 = b.forces(off, P2, Q2)
+        b.md_run(off, P2, V2, Q2, F2, 1e-3, 0.04, 6, 0, 3, use_graph=use_graph)
+        b.check()
+        runs.append([t.cpu().numpy() for t in (P2, V2, F2)])
+    for x, y in zip(runs[0], runs[1]):
+        assert np.array_equal(x, y)
