@@ -150,18 +150,32 @@ __global__ void k_ktable(const int32_t *kset, int n_sys, int P, int P_pad, float
 //    Lanes own particles, the k-chunk is wave-uniform (scalar loads).
 // ---------------------------------------------------------------------------
 
+// Blocks are dealt round-robin to the 8 XCDs.  Map block b to (tile, k-chunk)
+// so that XCD b mod 8 runs all k-chunks of its tiles back to back: a tile is
+// then fetched into one XCD's L2 once instead of once per k-chunk.  The grid
+// has ceil(n_tiles / 8) * 8 * nkc blocks; blocks past the last tile exit.
+struct TileChunk {
+    int tile, kc;
+};
+__device__ __forceinline__ TileChunk tile_chunk(int b, int nkc) {
+    const int j = b >> 3;
+    return TileChunk{(j / nkc) * 8 + (b & 7), j % nkc};
+}
+
 template <int KC>
 __global__ __launch_bounds__(kBlock) void k_sf32(const float4 *__restrict__ p32,
                                                  const float4 *__restrict__ kn, const int *tbase,
-                                                 int n_sys, int per_thread, int P_pad,
+                                                 int n_sys, int per_thread, int P_pad, int n_tiles,
                                                  float *__restrict__ part) {
     __shared__ float sh[kBlock / 64][64];
-    const int r = find_sys(tbase, n_sys, (int)blockIdx.x);
-    const float4 *knr = kn + (int64_t)r * P_pad + blockIdx.y * KC;
+    const TileChunk tc = tile_chunk((int)blockIdx.x, P_pad / KC);
+    if (tc.tile >= n_tiles) return;
+    const int r = find_sys(tbase, n_sys, tc.tile);
+    const float4 *knr = kn + (int64_t)r * P_pad + tc.kc * KC;
     float acc[4 * KC];
 #pragma unroll
     for (int v = 0; v < 4 * KC; v++) acc[v] = 0.0f;
-    const int64_t base = (int64_t)blockIdx.x * kBlock * per_thread + threadIdx.x;
+    const int64_t base = (int64_t)tc.tile * kBlock * per_thread + threadIdx.x;
     for (int m = 0; m < per_thread; m++) {
         const int64_t i = base + (int64_t)m * kBlock;
         const float4 a = p32[2 * i];
@@ -188,22 +202,24 @@ __global__ __launch_bounds__(kBlock) void k_sf32(const float4 *__restrict__ p32,
         float t = 0.0f;
 #pragma unroll
         for (int w = 0; w < kBlock / 64; w++) t += sh[w][threadIdx.x];
-        part[((int64_t)blockIdx.x * P_pad + blockIdx.y * KC) * 4 + threadIdx.x] = t;
+        part[((int64_t)tc.tile * P_pad + tc.kc * KC) * 4 + threadIdx.x] = t;
     }
 }
 
 template <int KC>
 __global__ __launch_bounds__(kBlock) void k_sf64(const double4 *__restrict__ p64,
                                                  const double4 *__restrict__ kn, const int *tbase,
-                                                 int n_sys, int per_thread, int P_pad,
+                                                 int n_sys, int per_thread, int P_pad, int n_tiles,
                                                  double *__restrict__ part) {
     __shared__ double sh[kBlock / 64][4 * KC];
-    const int r = find_sys(tbase, n_sys, (int)blockIdx.x);
-    const double4 *knr = kn + (int64_t)r * P_pad + blockIdx.y * KC;
+    const TileChunk tc = tile_chunk((int)blockIdx.x, P_pad / KC);
+    if (tc.tile >= n_tiles) return;
+    const int r = find_sys(tbase, n_sys, tc.tile);
+    const double4 *knr = kn + (int64_t)r * P_pad + tc.kc * KC;
     double acc[4 * KC];
 #pragma unroll
     for (int v = 0; v < 4 * KC; v++) acc[v] = 0.0;
-    const int64_t base = (int64_t)blockIdx.x * kBlock * per_thread + threadIdx.x;
+    const int64_t base = (int64_t)tc.tile * kBlock * per_thread + threadIdx.x;
     for (int m = 0; m < per_thread; m++) {
         const int64_t i = base + (int64_t)m * kBlock;
         const double4 a = p64[i];
@@ -229,7 +245,7 @@ __global__ __launch_bounds__(kBlock) void k_sf64(const double4 *__restrict__ p64
         double t = 0.0;
 #pragma unroll
         for (int w = 0; w < kBlock / 64; w++) t += sh[w][threadIdx.x];
-        part[((int64_t)blockIdx.x * P_pad + blockIdx.y * KC) * 4 + threadIdx.x] = t;
+        part[((int64_t)tc.tile * P_pad + tc.kc * KC) * 4 + threadIdx.x] = t;
     }
 }
 
@@ -357,14 +373,15 @@ hipError_t launch_kcoef_sf(rbe2d_ctx *h, hipStream_t s) {
                        h->P_pad, h->w.kn32, h->w.kn64);
     prof_begin(h, 1, s);
     if (h->n_tiles > 0) {
+        const int tiles8 = (h->n_tiles + 7) / 8 * 8;
         if (fp32) {
-            dim3 g(h->n_tiles, h->P_pad / kKChunk32);
-            hipLaunchKernelGGL(k_sf32<kKChunk32>, g, dim3(kBlock), 0, s, h->w.p32, h->w.kn32,
-                               h->w.lay.tbase, h->n_sys, h->per, h->P_pad, (float *)h->w.sfpart);
+            const dim3 g((unsigned)tiles8 * (h->P_pad / kKChunk32));
+            hipLaunchKernelGGL(k_sf32<kKChunk32>, g, dim3(kBlock), 0, s, h->w.p32, h->w.kn32, h->w.lay.tbase,
+                               h->n_sys, h->per, h->P_pad, h->n_tiles, (float *)h->w.sfpart);
         } else {
-            dim3 g(h->n_tiles, h->P_pad / kKChunk64);
-            hipLaunchKernelGGL(k_sf64<kKChunk64>, g, dim3(kBlock), 0, s, h->w.p64, h->w.kn64,
-                               h->w.lay.tbase, h->n_sys, h->per, h->P_pad, (double *)h->w.sfpart);
+            const dim3 g((unsigned)tiles8 * (h->P_pad / kKChunk64));
+            hipLaunchKernelGGL(k_sf64<kKChunk64>, g, dim3(kBlock), 0, s, h->w.p64, h->w.kn64, h->w.lay.tbase,
+                               h->n_sys, h->per, h->P_pad, h->n_tiles, (double *)h->w.sfpart);
         }
     }
     prof_end(h, 1, s);
