@@ -39,6 +39,39 @@ SLOTS_REAL = 24    # per pair within r_c: d2 (5), cutoff (1), rsqrt (2), exp (2+
                    # (rcp 2 + 9 FMA), force factor (2); pairs outside r_c not counted
 
 
+# HBM traffic of the dominant kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE
+# (profiles/), valid only while the kernel sources are the ones it was taken on
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "real_pairs_large_md_traffic.txt")
+TRAFFIC_SOURCES = ("realspace.hip", "rbe2d_internal.h", "devmath.h", "erfcx_fit.h")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, "paper_2405_06333_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    """Bytes per launch from the committed counter summary, or None when it is
+    missing, for another kernel, or taken on other kernel sources."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith(" "):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("bench_kernel") != kernel or kv.get("source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -300,7 +333,7 @@ def main():
         ach = work / t_dom / 1e12
         peak = VALU_LANE_SLOTS / 1e12
         roof = {"bound": "alu", "kernel": dom, "achieved": round(ach, 3), "peak": round(peak, 3),
-                "unit": "Tlane-slot/s", "frac": round(ach / peak, 4), "traffic": None}
+                "unit": "Tlane-slot/s", "frac": round(ach / peak, 4), "traffic": measured_traffic(dom)}
     for k, slots, units in (("sf_pass", SLOTS_SF, NP), ("force_scatter", SLOTS_FORCE, NP),
                             ("real_pairs", SLOTS_REAL, pairs_real)):
         t, n = prof[k]
