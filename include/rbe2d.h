@@ -130,8 +130,10 @@ rbe2d_status rbe2d_draw_kset(const rbe2d_params *p, uint64_t seed, uint64_t stre
                              int32_t *n_out);
 
 /* Makes n (P x 3 int32, host or device per n_is_device) the handle's k-set.
- * Entries must be nonzero vectors with |n_d| < 2^20; a host array is
- * checked (RBE2D_E_INVAL), a device array is not. */
+ * Entries must be nonzero vectors with |n_d| < 2^20 (FP32 phases: |n_d| <
+ * 2^b, the smallest power of two above every |n| the sampler can draw for
+ * the system); a host array is checked (RBE2D_E_INVAL), a device array is
+ * not. */
 rbe2d_status rbe2d_set_kset(rbe2d_handle h, const int32_t *n, int n_is_device, void *stream);
 
 /* Draws the handle's k-set on the device (same vectors as rbe2d_draw_kset

@@ -189,7 +189,9 @@ rbe2d_status setup_system(const rbe2d_params *pin, SysHost &sh) {
     }
     int bits = 0;
     while ((1 << bits) <= nall) bits++;
-    d.fh_bits = std::max(1, 23 - bits);
+    // fh keeps 22 - bits fraction bits: n fh then has at most 22 significant
+    // bits for |n| < 2^bits, and nx fxh + ny fyh at most 23, so both are exact
+    d.fh_bits = std::max(1, 22 - bits);
     d.scale_h = std::ldexp(1.0, d.fh_bits);
     if (p.precision == RBE2D_PREC_FP32_PHASE && bits > 20)
         return fail(nullptr, RBE2D_E_INVAL, "k-range too wide for FP32 phases (alpha L too large)");
@@ -624,7 +626,7 @@ rbe2d_status rbe2d_set_kset(rbe2d_handle h, const int32_t *n, int n_is_device, v
     }
     for (int r = 0; r < h->n_sys; r++) {
         const SysDesc &d = h->sys[r].d;
-        const int64_t lim = h->precision == RBE2D_PREC_FP32_PHASE ? ((int64_t)1 << (24 - d.fh_bits))
+        const int64_t lim = h->precision == RBE2D_PREC_FP32_PHASE ? ((int64_t)1 << (22 - d.fh_bits))
                                                                   : ((int64_t)1 << 20);
         for (int l = 0; l < h->P; l++) {
             const int32_t *v = n + 3 * ((size_t)r * h->P + l);

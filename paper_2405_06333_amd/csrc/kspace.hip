@@ -6,10 +6,12 @@
 //
 // Phases are carried in revolutions: k.r / 2pi = nx fx + ny fy + nz fz with
 // fx = x/Lx wrapped into [0,1), fy = y/Ly, fz = z/Lz_ext.
-//  * FP32 path: f is split into fh (fh_bits fraction bits, so n*fh is exact
-//    in FP32 for |n| < 2^(24-fh_bits)) and fl = f - fh; the phase
-//    fract(nx fxh) + nx fxl + ... keeps ~1e-8 revolution accuracy, and the
-//    hardware v_sin_f32/v_cos_f32 take revolutions directly.
+//  * FP32 path: f is split into fh (fh_bits = 22 - b fraction bits, where
+//    every |n| < 2^b) and fl = f - fh.  Then n fh has at most 22 significant
+//    bits and nx fxh + ny fyh at most 23, so both are exact in FP32; the
+//    phase fract(nx fxh + ny fyh) + nx fxl + ny fyl (and likewise in z)
+//    keeps ~1e-8 revolution accuracy, and the hardware v_sin_f32/v_cos_f32
+//    take revolutions directly.
 //  * FP64 path: plain FP64 phase and a quarter-turn-reduced Taylor sincos.
 #include <algorithm>
 
@@ -183,7 +185,8 @@ __global__ __launch_bounds__(kBlock) void k_sf32(const float4 *__restrict__ p32,
 #pragma unroll
         for (int kk = 0; kk < KC; kk++) {
             const float4 n = knr[kk];
-            float pxy = fractf(n.x * a.x) + fractf(n.y * a.z);
+            // nx fxh + ny fyh is exact (see the header comment)
+            float pxy = fractf(fmaf(n.y, a.z, n.x * a.x));
             pxy = fmaf(n.x, a.y, pxy);
             pxy = fmaf(n.y, a.w, pxy);
             const float pz = fmaf(n.z, b.y, fractf(n.z * b.x));
@@ -479,7 +482,7 @@ __global__ __launch_bounds__(kBlock) void k_force32(ForceArgs a) {
                 const float4 n = kn[l];
                 const float4 kv = kf[2 * l];
                 const float4 ab = kf[2 * l + 1];
-                float pxy = fractf(n.x * pa.x) + fractf(n.y * pa.z);
+                float pxy = fractf(fmaf(n.y, pa.z, n.x * pa.x));
                 pxy = fmaf(n.x, pa.y, pxy);
                 pxy = fmaf(n.y, pa.w, pxy);
                 const float pz = fmaf(n.z, pb.y, fractf(n.z * pb.x));
