@@ -75,6 +75,8 @@ def _declare(L):
     L.orc_self.restype = ctypes.c_double
     L.orc_real.argtypes = [ctypes.c_int64, _D, _D, ctypes.POINTER(_Box), ctypes.c_int64, _I64,
                            _D, _D, _D, _D]
+    L.orc_short.argtypes = [ctypes.c_int64, _D, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                            ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double, _D, _D, _D]
 
 
 def _p(a, t=_D):
@@ -495,3 +497,74 @@ def deterministic_energy(slab: Slab, pos, q, cut=40.0):
     (ELC and remainder terms dropped) -- the quantity RBE estimates."""
     n, c = full_kset(slab, cut)
     return evaluate(slab, pos, q, n, c)
+
+
+# ---------------------------------------------------------------------------
+# MD around the path (Sec. 3.5 and Sec. 4.1): short-range forces and one
+# Langevin step.  Test infrastructure like everything in this module.
+# ---------------------------------------------------------------------------
+
+def short_range(pos, Lx, Ly, H, sigma, eps, sigma_w, eps_w):
+    """Purely repulsive shifted-truncated LJ between ions and against the two
+    walls (brute force).  Returns (F (N,3), E_pair, E_wall)."""
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    N = pos.shape[0]
+    F = np.zeros((N, 3))
+    ep = ctypes.c_double()
+    ew = ctypes.c_double()
+    lib().orc_short(N, _p(pos), Lx, Ly, H, sigma, eps, sigma_w, eps_w, _p(F), ctypes.byref(ep),
+                    ctypes.byref(ew))
+    return F, ep.value, ew.value
+
+
+THERMO_STREAM = 1 << 63   # stream ids of the thermostat noise: this bit set
+
+
+def thermo_normals(seed, stream, n):
+    """n x 3 standard normals of the Langevin noise: SplitMix64 counter-mode
+    uniforms (the k-sampler's generator, stream id with the top bit set) and
+    the Box-Muller transform (cosine branch): for particle i and component c,
+    u1, u2 = uniforms 2(3i+c), 2(3i+c)+1 and xi = sqrt(-2 ln(1-u1)) cos(2 pi u2)."""
+    key = _stream_key(seed, (THERMO_STREAM + stream) & _M64)
+    out = np.empty((n, 3))
+    for i in range(n):
+        for c in range(3):
+            k = 3 * i + c
+            u1 = _uniform(key, 2 * k)
+            u2 = _uniform(key, 2 * k + 1)
+            out[i, c] = math.sqrt(-2.0 * math.log(1.0 - u1)) * math.cos(2.0 * math.pi * u2)
+    return out
+
+
+def fold_z(z, v, zlo, zhi):
+    """Specular reflection at zlo and zhi, applied as often as needed."""
+    W = zhi - zlo
+    u = z - zlo
+    m = math.floor(u / W)
+    rem = u - m * W
+    if int(abs(m)) % 2 == 1:
+        return zhi - rem, -v
+    return zlo + rem, v
+
+
+def baoab_step(pos, vel, F, dt, gamma, kT, normals, Lx, Ly, zlo, zhi, force):
+    """One BAOAB step (Leimkuhler and Matthews, 2013) of the Langevin equation
+    of Sec. 3.5 with unit masses: v += dt/2 F; r += dt/2 v;
+    v = c1 v + c2 xi (c1 = exp(-gamma dt), c2 = sqrt((1 - c1^2) kT));
+    r += dt/2 v; x, y wrapped, z reflected at zlo, zhi; F = force(r);
+    v += dt/2 F.  With gamma = 0 it is velocity Verlet."""
+    c1 = math.exp(-gamma * dt)
+    c2 = math.sqrt((1.0 - c1 * c1) * kT)
+    pos = np.array(pos, dtype=np.float64)
+    vel = np.array(vel, dtype=np.float64)
+    vel = vel + 0.5 * dt * F
+    pos = pos + 0.5 * dt * vel
+    vel = c1 * vel + c2 * normals
+    pos = pos + 0.5 * dt * vel
+    pos[:, 0] -= Lx * np.floor(pos[:, 0] / Lx)
+    pos[:, 1] -= Ly * np.floor(pos[:, 1] / Ly)
+    for i in range(pos.shape[0]):
+        pos[i, 2], vel[i, 2] = fold_z(pos[i, 2], vel[i, 2], zlo, zhi)
+    Fn = force(pos)
+    vel = vel + 0.5 * dt * Fn
+    return pos, vel, Fn

@@ -510,3 +510,67 @@ void orc_real(int64_t N, const double *pos, const double *q, const orc_box *b,
     free(gp);
     free(gm);
 }
+
+/* ------------------------------------------------------------------ */
+/* Short-range forces of the MD around the path (Sec. 4.1): purely      */
+/* repulsive shifted-truncated LJ between ions (cut at 2^(1/6) sigma,   */
+/* shifted by +eps so that it vanishes there), and the same form in the */
+/* distance to each wall (z = 0 and z = H) with sigma_w, eps_w (reading: */
+/* the wall form is not printed).  Brute force over all pairs, minimum  */
+/* image in x and y.                                                    */
+/* ------------------------------------------------------------------ */
+
+static double lj_shifted(double s2_over_r2, double eps, double *f_over_r2_times_r2)
+{
+    /* returns U; *f... = -dU/dr * r (i.e. r * |F|) */
+    double s6 = s2_over_r2 * s2_over_r2 * s2_over_r2;
+    *f_over_r2_times_r2 = 24.0 * eps * (2.0 * s6 * s6 - s6);
+    return 4.0 * eps * (s6 * s6 - s6 + 0.25);
+}
+
+void orc_short(int64_t N, const double *pos, double Lx, double Ly, double H, double sigma, double eps,
+               double sigma_w, double eps_w, double *F, double *E_pair, double *E_wall)
+{
+    const double rcut2 = pow(2.0, 1.0 / 3.0) * sigma * sigma;
+    const double hcut = pow(2.0, 1.0 / 6.0) * sigma_w;
+    double ep = 0.0, ew = 0.0;
+#pragma omp parallel for schedule(static) reduction(+ : ep, ew)
+    for (int64_t i = 0; i < N; i++) {
+        double fx = 0.0, fy = 0.0, fz = 0.0;
+        if (eps != 0.0) {
+            for (int64_t j = 0; j < N; j++) {
+                if (j == i) continue;
+                double dx = pos[3 * i] - pos[3 * j];
+                double dy = pos[3 * i + 1] - pos[3 * j + 1];
+                double dz = pos[3 * i + 2] - pos[3 * j + 2];
+                dx -= Lx * rint(dx / Lx);
+                dy -= Ly * rint(dy / Ly);
+                double r2 = dx * dx + dy * dy + dz * dz;
+                if (!(r2 < rcut2)) continue;
+                double rf;
+                double u = lj_shifted(sigma * sigma / r2, eps, &rf);
+                fx += rf / r2 * dx;
+                fy += rf / r2 * dy;
+                fz += rf / r2 * dz;
+                ep += 0.5 * u;
+            }
+        }
+        if (eps_w != 0.0) {
+            double z = pos[3 * i + 2];
+            double h[2] = {z, H - z};
+            double sgn[2] = {1.0, -1.0};
+            for (int w = 0; w < 2; w++) {
+                if (!(h[w] > 0.0 && h[w] < hcut)) continue;
+                double rf;
+                double u = lj_shifted(sigma_w * sigma_w / (h[w] * h[w]), eps_w, &rf);
+                fz += sgn[w] * rf / h[w];
+                ew += u;
+            }
+        }
+        F[3 * i] = fx;
+        F[3 * i + 1] = fy;
+        F[3 * i + 2] = fz;
+    }
+    if (E_pair) *E_pair = ep;
+    if (E_wall) *E_wall = ew;
+}

@@ -28,6 +28,11 @@
 #ifndef RBE2D_ROUND_MIN
 #define RBE2D_ROUND_MIN 40    // keep draining while this many lanes hold pairs
 #endif
+#ifdef RBE2D_REAL_WAVES_PER_EU  // occupancy hint for the pair kernel (register budget)
+#define RBE2D_REAL_OCC __attribute__((amdgpu_waves_per_eu(RBE2D_REAL_WAVES_PER_EU, 8)))
+#else
+#define RBE2D_REAL_OCC
+#endif
 
 namespace rbe2d {
 
@@ -380,7 +385,7 @@ __device__ WaveQueue<256, 2> make_queue<WaveQueue<256, 2>>(unsigned char *lds, i
 }
 
 template <bool FP32, bool WANT_DG>
-__global__ __launch_bounds__(kBlock) void k_real(RealArgs a) {
+__global__ __launch_bounds__(kBlock) RBE2D_REAL_OCC void k_real(RealArgs a) {
     using T = typename RealTypes<FP32>::T;
     constexpr int U = RealTypes<FP32>::U;
     constexpr int NW = kBlock / kWave;

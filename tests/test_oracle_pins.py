@@ -410,3 +410,116 @@ def test_sampler_is_deterministic_per_seed_and_stream(orc):
     b = orc.draw_kset(s, seed=0)
     c = orc.draw_kset(s, seed=0, stream=1)
     assert np.array_equal(a, b) and not np.array_equal(a, c)
+
+
+# ---------------------------------------------------------------------------
+# MD around the path: short-range forces, thermostat noise, BAOAB step
+# ---------------------------------------------------------------------------
+
+def _wca_pair(orc, r, sigma=1.0, eps=1.0):
+    pos = np.array([[1.0, 1.0, 2.0], [1.0 + r, 1.0, 2.0]])
+    return orc.short_range(pos, 10.0, 10.0, 4.0, sigma, eps, 0.5, 0.0)
+
+
+def test_wca_special_values_and_cutoff(orc):
+    """At r = sigma the shifted-truncated LJ equals eps; at its minimum
+    r = 2^(1/6) sigma both energy and force vanish (continuous truncation);
+    beyond it nothing acts; the pair forces are equal and opposite."""
+    F, e, _ = _wca_pair(orc, 1.0)
+    assert abs(e - 1.0) < 1e-14
+    rc = 2.0 ** (1.0 / 6.0)
+    F, e, _ = _wca_pair(orc, rc * (1 - 1e-9))
+    assert abs(e) < 1e-12 and np.abs(F).max() < 1e-6
+    F, e, _ = _wca_pair(orc, rc * (1 + 1e-9))
+    assert e == 0.0 and np.abs(F).max() == 0.0
+    F, e, _ = _wca_pair(orc, 0.95)
+    assert np.allclose(F[0], -F[1], rtol=0, atol=1e-12) and F[0, 0] < 0 < F[1, 0]
+
+
+def test_wca_and_wall_forces_are_minus_gradients(orc):
+    # jittered lattice of spacing 1.05 (pairs straddle the 1.12 cutoff), a few
+    # closer pairs, and particles near both walls; periodic in x and y
+    rng = np.random.default_rng(3)
+    L, H = 6.3, 5.0
+    g = np.arange(6) * 1.05
+    pos = np.array([[x, y, z] for x in g for y in g for z in (0.9, 1.95, 3.0, 4.05)])
+    pos += rng.uniform(-0.08, 0.08, pos.shape)
+    pos[1] = pos[0] + [0.8, 0.3, 0.2]
+    pos[3, 2] = 0.4
+    pos[4, 2] = H - 0.35
+    sig, eps, sw, ew = 1.0, 1.3, 0.5, 0.7
+    F, _, _ = orc.short_range(pos, L, L, H, sig, eps, sw, ew)
+    h = 1e-6
+    for i in (0, 1, 3, 4, 7):
+        for c in range(3):
+            pp = pos.copy(); pp[i, c] += h
+            pm = pos.copy(); pm[i, c] -= h
+            _, e1, w1 = orc.short_range(pp, L, L, H, sig, eps, sw, ew)
+            _, e2, w2 = orc.short_range(pm, L, L, H, sig, eps, sw, ew)
+            fd = -((e1 + w1) - (e2 + w2)) / (2 * h)
+            assert abs(fd - F[i, c]) <= 1e-5 * (1 + abs(F[i, c])), (i, c, fd, F[i, c])
+    assert np.abs(F[:, :2].sum(0)).max() < 1e-9     # walls act in z only
+
+
+def test_wall_force_mirror_symmetry(orc):
+    H = 5.0
+    for z in (0.2, 0.4, 0.55):
+        F1, _, w1 = orc.short_range(np.array([[1.0, 1.0, z]]), 4.0, 4.0, H, 1.0, 0.0, 0.5, 1.0)
+        F2, _, w2 = orc.short_range(np.array([[1.0, 1.0, H - z]]), 4.0, 4.0, H, 1.0, 0.0, 0.5, 1.0)
+        assert abs(w1 - w2) <= 1e-12 * abs(w1) and abs(F1[0, 2] + F2[0, 2]) <= 1e-12 * abs(F1[0, 2])
+        assert (F1[0, 2] > 0) == (z < 0.5 * 2 ** (1 / 6))
+
+
+def test_thermo_normals_are_standard_normal(orc):
+    from scipy import stats
+    x = orc.thermo_normals(5, 17, 3000).ravel()
+    assert abs(x.mean()) < 4 / np.sqrt(x.size)
+    assert abs(x.var() - 1) < 4 * np.sqrt(2 / x.size)
+    assert stats.kstest(x, "norm").pvalue > 1e-3
+    y = orc.thermo_normals(5, 18, 10).ravel()
+    z = orc.thermo_normals(6, 17, 10).ravel()
+    assert not np.allclose(x[:30], y) and not np.allclose(x[:30], z)
+    assert np.array_equal(orc.thermo_normals(5, 17, 10).ravel(), x[:30])
+
+
+def _harmonic(center, k=1.0):
+    return lambda p: -k * (p - center)
+
+
+def test_baoab_without_friction_is_time_reversible(orc):
+    """gamma = 0: one step forward, then one step with the velocities
+    reversed, returns to the start (velocity Verlet is time-reversible)."""
+    rng = np.random.default_rng(1)
+    c = np.array([5.0, 5.0, 5.0])
+    force = _harmonic(c, 2.0)
+    pos = c + rng.normal(0, 0.5, (20, 3))
+    vel = rng.normal(0, 1, (20, 3))
+    F = force(pos)
+    z = np.zeros((20, 3))
+    p1, v1, F1 = orc.baoab_step(pos, vel, F, 0.01, 0.0, 1.0, z, 100.0, 100.0, 0.0, 10.0, force)
+    p2, v2, _ = orc.baoab_step(p1, -v1, F1, 0.01, 0.0, 1.0, z, 100.0, 100.0, 0.0, 10.0, force)
+    assert np.allclose(p2, pos, atol=1e-12) and np.allclose(-v2, vel, atol=1e-12)
+    # and energy stays within O(dt^2) over many steps
+    e0 = 0.5 * (vel ** 2).sum() + (pos - c).var(axis=None) * 0 + ((pos - c) ** 2).sum()
+    p, v, Fc = pos, vel, F
+    for _ in range(500):
+        p, v, Fc = orc.baoab_step(p, v, Fc, 0.01, 0.0, 1.0, z, 100.0, 100.0, 0.0, 10.0, force)
+    e1 = 0.5 * (v ** 2).sum() + ((p - c) ** 2).sum()
+    assert abs(e1 - e0) < 1e-3 * e0
+
+
+def test_baoab_thermostat_reaches_equipartition(orc):
+    """No forces: the O step alone drives every velocity component to the
+    Maxwell distribution of temperature kT (fluctuation-dissipation)."""
+    n, kT = 400, 2.0
+    pos = np.tile([5.0, 5.0, 5.0], (n, 1))
+    vel = np.zeros((n, 3))
+    F = np.zeros((n, 3))
+    zero = lambda p: np.zeros_like(p)  # noqa: E731
+    v2 = []
+    for step in range(60):
+        xi = orc.thermo_normals(9, step, n)
+        pos, vel, F = orc.baoab_step(pos, vel, F, 0.05, 2.0, kT, xi, 10.0, 10.0, 0.0, 10.0, zero)
+        if step >= 30:
+            v2.append((vel ** 2).mean())
+    assert abs(np.mean(v2) - kT) < 0.06 * kT
