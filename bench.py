@@ -249,6 +249,32 @@ def run_grad(R, torch, steps, autotune=True):
     return out
 
 
+def run_langevin(R, torch, w, precision, steps, autotune=True):
+    """The large slab as charged soft spheres: positions thinned to a 0.9
+    minimum distance, WCA ions (sigma = eps = 1) and walls (sigma = 0.5,
+    eps = 1), BAOAB at kT = 1, gamma = 1; graph-replayed steps."""
+    from paper_2405_06333_amd import inputs
+    wt = w.with_(extra={"dmin": 0.9})
+    pos, q = inputs.sample(wt)
+    md = R.md_params(gamma=1.0, kT=1.0, sigma=1.0, eps=1.0, sigma_wall=0.5, eps_wall=1.0, wall_margin=0.1)
+    P_ = torch.as_tensor(pos, device="cuda")
+    Q_ = torch.as_tensor(q, device="cuda")
+    V_ = torch.zeros_like(P_)
+    slab = R.Slab(**w.slab_kwargs(), precision=precision, n_max=w.N)
+    slab.sample_kset(w.seed, 0)
+    if autotune:
+        slab.autotune(P_, Q_)
+    F_ = slab.forces(P_, Q_)
+    slab.short_forces(P_, Q_, md, F=F_)
+    slab.md_run_ex(P_, V_, Q_, F_, w.dt, md, w.seed, 1, 2, use_graph=True)
+    t = timed(torch, lambda: slab.md_run_ex(P_, V_, Q_, F_, w.dt, md, w.seed, 3, steps, use_graph=True), 1)
+    slab.check()
+    kin = float((V_ ** 2).mean().item())
+    return {"value": w.N * steps / t, "unit": "particle-steps/s", "steps": steps,
+            "thermostat": "BAOAB Langevin kT=1 gamma=1", "short_range": "WCA ions sigma=1 eps=1, walls sigma=0.5",
+            "kinetic_T_after": round(kin, 4), "finite": bool(torch.isfinite(P_).all().item())}
+
+
 def copy_probe(torch, mib):
     """A plain device copy of `mib` MiB, three times: the reference reading
     for the HBM byte counters."""
@@ -348,11 +374,12 @@ def main():
         s64, _, _, _ = run_md(R, torch, w, "fp64", a.fp64_steps, 1, profile=False, autotune=not a.no_autotune)
         fp64 = {"value": w.N * a.fp64_steps / s64, "unit": "particle-steps/s", "steps": a.fp64_steps}
 
-    graph = batch = grad = None
+    graph = batch = grad = langevin = None
     if a.side_steps > 0:
         sg, _, _, _ = run_md(R, torch, w, a.precision, a.side_steps, 1, profile=False, use_graph=True,
                              autotune=not a.no_autotune)
         graph = {"value": w.N * a.side_steps / sg, "unit": "particle-steps/s", "steps": a.side_steps}
+        langevin = run_langevin(R, torch, w, a.precision, a.side_steps, autotune=not a.no_autotune)
         batch = run_batch(R, torch, a.side_steps, autotune=not a.no_autotune)
         grad = run_grad(R, torch, a.side_steps, autotune=not a.no_autotune)
     cpu = None if a.no_cpu_baseline else cpu_baseline(w, a.cpu_sample, a.cpu_targets)
@@ -378,6 +405,7 @@ def main():
         "cpu_baseline": cpu,
         "plain_fp64_gpu": fp64,
         "md_graph": graph,
+        "md_langevin_wca": langevin,
         "batched_replicas": batch,
         "differentiable": grad,
         "launch_params": tuned,

@@ -222,6 +222,55 @@ rbe2d_status rbe2d_batch_md_run(rbe2d_handle h, const int64_t *offsets, double *
                                 uint64_t seed, int64_t step0, int32_t n_steps, int32_t use_graph,
                                 void *stream);
 
+/* ---------------------------------------------------------------------------
+ * MD around the path (Sec. 3.5, Sec. 4.1): Langevin thermostat and the
+ * short-range repulsion of the primitive model.  Not part of the RBE2D
+ * estimator; they make thermostatted runs of charged soft spheres possible.
+ *   Ion-ion: purely repulsive shifted-truncated LJ,
+ *     U = 4 eps [(sigma/r)^12 - (sigma/r)^6 + 1/4] for r < 2^(1/6) sigma,
+ *     real ions only (no images), minimum image in x and y.
+ *   Walls: the same form in the distance h to z = 0 and to z = H with
+ *     sigma_wall, eps_wall (the paper gives only these two parameters).
+ *   Thermostat: the Langevin equation m dv = (F - gamma v) dt
+ *     + sqrt(2 gamma kT) dW (unit masses), integrated with BAOAB
+ *     (Leimkuhler and Matthews 2013): v += dt/2 F; r += dt/2 v;
+ *     v = c1 v + c2 xi (c1 = exp(-gamma dt), c2 = sqrt((1 - c1^2) kT));
+ *     r += dt/2 v; new forces; v += dt/2 F.  gamma = 0 is velocity Verlet.
+ *     xi: standard normals from the k-sampler's SplitMix64 generator keyed by
+ *     (seed, 2^63 + stream) with stream = step * n_sys + system, uniforms
+ *     u1, u2 at counters 2(3i+c), 2(3i+c)+1 for particle i (index within its
+ *     system) and component c, xi = sqrt(-2 ln(1-u1)) cos(2 pi u2).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    double gamma;              /* friction rate (1/time), >= 0                         */
+    double kT;                 /* thermostat temperature (energy units), >= 0          */
+    double sigma, eps;         /* ion-ion WCA; eps = 0 turns it off (sigma > 0 else)   */
+    double sigma_wall, eps_wall; /* wall WCA; eps_wall = 0 turns it off                */
+    double wall_margin;        /* integrator reflects z at wall_margin and H - wall_margin;
+                                  0 < wall_margin < H/2 of every system                */
+} rbe2d_md_params;
+
+/* Short-range forces of *mp at the given positions: ADDS the ion-ion and
+ * wall forces to F (device, offsets[n_sys] x 3) and, if energy is not NULL,
+ * writes {E_ion_ion, E_wall} per system (device, 2 doubles per system).
+ * offsets as in rbe2d_batch_forces ({0, N} for a single system); pos, q
+ * device (q fills the cell list's records).  Enqueued only.  Errors:
+ * RBE2D_E_INVAL (offsets, parameters, NULL arrays). */
+rbe2d_status rbe2d_short_forces(rbe2d_handle h, const int64_t *offsets, const double *pos,
+                                const double *q, double *F, double *energy,
+                                const rbe2d_md_params *mp, void *stream);
+
+/* n_steps BAOAB steps of all systems: forces are the RBE2D forces
+ * (RBE2D_ALL, a fresh device k-set per step from (seed, step * n_sys +
+ * system)) plus the short-range forces of *mp.  F must hold the total
+ * forces of the initial positions on entry (rbe2d_forces or
+ * rbe2d_batch_forces, then rbe2d_short_forces).  Same graph and stream
+ * semantics as rbe2d_md_run; offsets as in rbe2d_batch_forces. */
+rbe2d_status rbe2d_md_run_ex(rbe2d_handle h, const int64_t *offsets, double *pos, double *vel,
+                             const double *q, double *F, double dt, const rbe2d_md_params *mp,
+                             uint64_t seed, int64_t step0, int32_t n_steps, int32_t use_graph,
+                             void *stream);
+
 /* Autotuner.  Times, with HIP events on `stream`, the candidate launch
  * parameters of the evaluation for the particle layout given by offsets
  * (host, n_sys + 1 int64, as in rbe2d_batch_forces; {0, N} for a single
@@ -246,8 +295,9 @@ rbe2d_status rbe2d_autotune(rbe2d_handle h, const int64_t *offsets, const double
  * class launched more than n times between reads keeps its first n).
  * Classes: 0 prep, 1 structure-factor pass, 2 per-k reduce/assemble,
  * 3 cell-list build, 4 real-space pairs, 5 force scatter, 6 energies,
- * 7 integrator, 8 k-sampler.  Not to be used while a graph is captured. */
-enum { RBE2D_PROF_SLOTS = 9 };
+ * 7 integrator, 8 k-sampler, 9 short-range forces.  Not to be used while a
+ * graph is captured. */
+enum { RBE2D_PROF_SLOTS = 10 };
 rbe2d_status rbe2d_profile_enable(rbe2d_handle h, int32_t n_events);
 rbe2d_status rbe2d_profile_read(rbe2d_handle h, double *ms, int64_t *launches, int32_t n_slots);
 

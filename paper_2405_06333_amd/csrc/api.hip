@@ -353,6 +353,7 @@ rbe2d_status create_handle(int n, const rbe2d_params *ps, bool batch, rbe2d_hand
     A(&w.freal_s, kMaxRealSplit * h->split_cap);
     A(&w.dgreal_s, kMaxRealSplit * h->split_cap);
     A(&w.rpart_s, kMaxRealSplit * 3 * (h->cap_sorted / kWave));
+    A(&w.spart, 2 * (h->cap_sorted / kWave));
     A(&w.err, 4);
     A(&w.step, 1);
     std::vector<SysDesc> descs(n);
@@ -484,17 +485,52 @@ rbe2d_status run_forces(rbe2d_ctx *h, const double *pos, const double *q, double
     return RBE2D_OK;
 }
 
-// one velocity-Verlet step; the k-set is drawn with the device step counter
-// when dev_step is set (graph replays), else with stream id `step`
+rbe2d_status md_extra(rbe2d_ctx *h, const rbe2d_md_params *mp, double dt, MdExtra *mx) {
+    if (!mp) return fail(h, RBE2D_E_INVAL, "md params are NULL");
+    const double vals[] = {mp->gamma, mp->kT, mp->sigma, mp->eps, mp->sigma_wall, mp->eps_wall, mp->wall_margin};
+    for (double v : vals)
+        if (!std::isfinite(v)) return fail(h, RBE2D_E_INVAL, "non-finite md parameter");
+    if (mp->gamma < 0 || mp->kT < 0 || mp->eps < 0 || mp->eps_wall < 0)
+        return fail(h, RBE2D_E_INVAL, "gamma, kT, eps, eps_wall must be >= 0");
+    if ((mp->eps > 0 && !(mp->sigma > 0)) || (mp->eps_wall > 0 && !(mp->sigma_wall > 0)))
+        return fail(h, RBE2D_E_INVAL, "sigma, sigma_wall must be > 0 where eps, eps_wall are");
+    double hmin = h->sys[0].p.H;
+    for (const SysHost &sh : h->sys) hmin = std::min(hmin, sh.p.H);
+    if (!(mp->wall_margin > 0 && 2 * mp->wall_margin < hmin))
+        return fail(h, RBE2D_E_INVAL, "need 0 < wall_margin < H/2");
+    const double rlj = std::pow(2.0, 1.0 / 6.0) * mp->sigma;
+    for (const SysHost &sh : h->sys)
+        if (mp->eps > 0 && 2 * rlj > std::min(sh.p.Lx, sh.p.Ly))
+            return fail(h, RBE2D_E_INVAL, "ion-ion LJ cutoff exceeds half the box");
+    mx->c1 = std::exp(-mp->gamma * dt);
+    mx->c2 = std::sqrt((1.0 - mx->c1 * mx->c1) * mp->kT);
+    mx->sig2 = mp->sigma * mp->sigma;
+    mx->eps = mp->eps;
+    mx->rc2 = rlj * rlj;
+    mx->sigw2 = mp->sigma_wall * mp->sigma_wall;
+    mx->epsw = mp->eps_wall;
+    mx->hcut = std::pow(2.0, 1.0 / 6.0) * mp->sigma_wall;
+    mx->margin = mp->wall_margin;
+    return RBE2D_OK;
+}
+
+// one step: velocity Verlet, or BAOAB with short-range forces when mx is
+// set; the k-set (and the thermostat noise) use the device step counter when
+// dev_step is set (graph replays), else stream id `step`
 rbe2d_status md_step(rbe2d_ctx *h, double *pos, double *vel, const double *q, double *F, double dt,
                      double zlo, double zhi_from_top, uint64_t seed, int64_t step, bool dev_step,
-                     hipStream_t s) {
-    RBE2D_TRY(h, launch_md_kick_drift(h, pos, vel, F, dt, zlo, zhi_from_top, s), "md drift");
-    RBE2D_TRY(h, launch_sample(h, seed, (uint64_t)step * (uint64_t)h->n_sys, dev_step ? h->w.step : nullptr, s),
-              "md sample");
+                     const MdExtra *mx, hipStream_t s) {
+    const uint64_t sbase = (uint64_t)step * (uint64_t)h->n_sys;
+    if (mx)
+        RBE2D_TRY(h, launch_md_kick_drift_langevin(h, pos, vel, F, dt, *mx, seed, sbase,
+                                                   dev_step ? h->w.step : nullptr, s), "md drift");
+    else
+        RBE2D_TRY(h, launch_md_kick_drift(h, pos, vel, F, dt, zlo, zhi_from_top, s), "md drift");
+    RBE2D_TRY(h, launch_sample(h, seed, sbase, dev_step ? h->w.step : nullptr, s), "md sample");
     rbe2d_status st = run_common(h, pos, q, RBE2D_ALL, false, s);
     if (st) return st;
     RBE2D_TRY(h, launch_kforce(h, pos, q, F, nullptr, RBE2D_ALL, false, false, true, nullptr, s), "md force");
+    if (mx && mx->short_on()) RBE2D_TRY(h, launch_short(h, *mx, F, nullptr, s), "md short-range");
     RBE2D_TRY(h, launch_md_kick(h, vel, F, dt, s), "md kick");
     if (dev_step) RBE2D_TRY(h, launch_step_inc(h, s), "md step counter");
     return RBE2D_OK;
@@ -503,12 +539,12 @@ rbe2d_status md_step(rbe2d_ctx *h, double *pos, double *vel, const double *q, do
 // n_steps MD steps, eager or as replays of one captured step
 rbe2d_status md_run(rbe2d_ctx *h, double *pos, double *vel, const double *q, double *F, double dt, double zlo,
                     double zhi_from_top, uint64_t seed, int64_t step0, int32_t n_steps, bool use_graph,
-                    hipStream_t s) {
+                    const MdExtra *mx, hipStream_t s) {
     if (n_steps <= 0) return RBE2D_OK;
     h->kset_valid = true;
     if (!use_graph) {
         for (int32_t it = 0; it < n_steps; it++) {
-            rbe2d_status st = md_step(h, pos, vel, q, F, dt, zlo, zhi_from_top, seed, step0 + it, false, s);
+            rbe2d_status st = md_step(h, pos, vel, q, F, dt, zlo, zhi_from_top, seed, step0 + it, false, mx, s);
             if (st) return st;
         }
         return RBE2D_OK;
@@ -518,6 +554,9 @@ rbe2d_status md_run(rbe2d_ctx *h, double *pos, double *vel, const double *q, dou
     std::vector<uint64_t> key = {(uint64_t)(uintptr_t)pos, (uint64_t)(uintptr_t)vel, (uint64_t)(uintptr_t)q,
                                  (uint64_t)(uintptr_t)F, bits(dt), bits(zlo), bits(zhi_from_top), seed,
                                  (uint64_t)h->per};
+    if (mx)
+        for (double v : {mx->c1, mx->c2, mx->sig2, mx->eps, mx->rc2, mx->sigw2, mx->epsw, mx->hcut, mx->margin})
+            key.push_back(bits(v));
     key.insert(key.end(), h->lay_host.begin(), h->lay_host.end());
     if (!h->md_exec || key != h->md_key) {
         free_graph(h);
@@ -528,7 +567,7 @@ rbe2d_status md_run(rbe2d_ctx *h, double *pos, double *vel, const double *q, dou
         hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         rbe2d_status st = RBE2D_OK;
         if (e == hipSuccess) {
-            st = md_step(h, pos, vel, q, F, dt, zlo, zhi_from_top, seed, 0, true, cs);
+            st = md_step(h, pos, vel, q, F, dt, zlo, zhi_from_top, seed, 0, true, mx, cs);
             hipGraph_t g = nullptr;
             const hipError_t e2 = hipStreamEndCapture(cs, &g);
             if (st == RBE2D_OK && e2 != hipSuccess) st = hipfail(h, e2, "end capture");
@@ -731,7 +770,7 @@ rbe2d_status rbe2d_md_run(rbe2d_handle h, int64_t N, double *pos, double *vel, c
     if (N > 0 && (!pos || !vel || !q || !F)) return fail(h, RBE2D_E_INVAL, "NULL array");
     if (!(dt > 0.0) || !(z_lo > 0.0 && z_lo < z_hi && z_hi < sh.p.H) || n_steps < 0)
         return fail(h, RBE2D_E_INVAL, "need dt > 0, 0 < z_lo < z_hi < H, n_steps >= 0");
-    return md_run(h, pos, vel, q, F, dt, z_lo, sh.p.H - z_hi, seed, step0, n_steps, use_graph != 0, s);
+    return md_run(h, pos, vel, q, F, dt, z_lo, sh.p.H - z_hi, seed, step0, n_steps, use_graph != 0, nullptr, s);
 }
 
 rbe2d_status rbe2d_batch_md_run(rbe2d_handle h, const int64_t *offsets, double *pos, double *vel, const double *q,
@@ -746,7 +785,38 @@ rbe2d_status rbe2d_batch_md_run(rbe2d_handle h, const int64_t *offsets, double *
     for (const SysHost &sh : h->sys) hmin = std::min(hmin, sh.p.H);
     if (!(dt > 0.0) || !(wall_margin > 0.0 && 2 * wall_margin < hmin) || n_steps < 0)
         return fail(h, RBE2D_E_INVAL, "need dt > 0, 0 < wall_margin < H/2, n_steps >= 0");
-    return md_run(h, pos, vel, q, F, dt, wall_margin, wall_margin, seed, step0, n_steps, use_graph != 0, s);
+    return md_run(h, pos, vel, q, F, dt, wall_margin, wall_margin, seed, step0, n_steps, use_graph != 0, nullptr,
+                  s);
+}
+
+rbe2d_status rbe2d_short_forces(rbe2d_handle h, const int64_t *offsets, const double *pos, const double *q,
+                                double *F, double *energy, const rbe2d_md_params *mp, void *stream) {
+    if (!h) return fail(nullptr, RBE2D_E_INVAL, "handle is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    MdExtra mx;
+    rbe2d_status st = md_extra(h, mp, 1.0, &mx);
+    if (st) return st;
+    st = layout_from_offsets(h, offsets, s);
+    if (st) return st;
+    if (h->n_total > 0 && (!pos || !q || !F)) return fail(h, RBE2D_E_INVAL, "NULL array");
+    if (mx.short_on()) RBE2D_TRY(h, launch_cells(h, pos, q, s), "cell list");
+    RBE2D_TRY(h, launch_short(h, mx, F, energy, s), "short-range launch");
+    return RBE2D_OK;
+}
+
+rbe2d_status rbe2d_md_run_ex(rbe2d_handle h, const int64_t *offsets, double *pos, double *vel, const double *q,
+                             double *F, double dt, const rbe2d_md_params *mp, uint64_t seed, int64_t step0,
+                             int32_t n_steps, int32_t use_graph, void *stream) {
+    if (!h) return fail(nullptr, RBE2D_E_INVAL, "handle is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    if (!(dt > 0.0) || n_steps < 0) return fail(h, RBE2D_E_INVAL, "need dt > 0, n_steps >= 0");
+    MdExtra mx;
+    rbe2d_status st = md_extra(h, mp, dt, &mx);
+    if (st) return st;
+    st = layout_from_offsets(h, offsets, s);
+    if (st) return st;
+    if (h->n_total > 0 && (!pos || !vel || !q || !F)) return fail(h, RBE2D_E_INVAL, "NULL array");
+    return md_run(h, pos, vel, q, F, dt, mx.margin, mx.margin, seed, step0, n_steps, use_graph != 0, &mx, s);
 }
 
 rbe2d_status rbe2d_autotune(rbe2d_handle h, const int64_t *offsets, const double *pos, const double *q,

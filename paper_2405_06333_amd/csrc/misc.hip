@@ -184,6 +184,63 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(const SysDesc *sys, Layou
     }
 }
 
+// BAOAB up to the force evaluation (Langevin equation, unit masses):
+// v += dt/2 F; r += dt/2 v; v = c1 v + c2 xi; r += dt/2 v; wrap / reflect.
+// xi: Box-Muller normals from the SplitMix64 stream (seed, 2^63 + step n_sys
+// + system), uniforms 2(3i+c) and 2(3i+c)+1 for particle i of its system.
+__global__ __launch_bounds__(kBlock) void k_kick_drift_langevin(const SysDesc *sys, Layout lay, int n_sys,
+                                                                int n_total, double *pos, double *vel,
+                                                                const double *F, double dt, double c1, double c2,
+                                                                double margin, uint64_t seed, uint64_t stream_base,
+                                                                const long long *dev_step) {
+    const int g = blockIdx.x * kBlock + threadIdx.x;
+    if (g >= n_total) return;
+    const int r = find_sys(lay.off, n_sys, g);
+    const SysDesc &d = sys[r];
+    const int64_t i = g;
+    const uint64_t local = (uint64_t)(g - lay.off[r]);
+    const uint64_t base = dev_step ? (uint64_t)(*dev_step) * (uint64_t)n_sys : stream_base;
+    const uint64_t key = stream_key(seed, kThermoStream + base + (uint64_t)r);
+    const double h = 0.5 * dt;
+    double v[3], x[3];
+    for (int c = 0; c < 3; c++) {
+        v[c] = fma(h, F[3 * i + c], vel[3 * i + c]);
+        x[c] = fma(h, v[c], pos[3 * i + c]);
+        const uint64_t k = 3 * local + c;
+        const double u1 = uniform01(key, 2 * k), u2 = uniform01(key, 2 * k + 1);
+        const double xi = sqrt(-2.0 * log(1.0 - u1)) * cos(2.0 * kPi * u2);
+        v[c] = fma(c1, v[c], c2 * xi);
+        x[c] = fma(h, v[c], x[c]);
+    }
+    x[0] -= d.Lx * floor(x[0] / d.Lx);
+    x[1] -= d.Ly * floor(x[1] / d.Ly);
+    const double zlo = margin, zhi = d.H - margin;
+    const double W = zhi - zlo;
+    const double u = x[2] - zlo;
+    const double m = floor(u / W);
+    const double rem = u - m * W;
+    const bool odd = fmod(fabs(m), 2.0) == 1.0;
+    x[2] = odd ? zhi - rem : zlo + rem;
+    if (odd) v[2] = -v[2];
+    x[2] = fmin(fmax(x[2], zlo), zhi);
+    for (int c = 0; c < 3; c++) {
+        vel[3 * i + c] = v[c];
+        pos[3 * i + c] = x[c];
+    }
+}
+
+hipError_t launch_md_kick_drift_langevin(rbe2d_ctx *h, double *pos, double *vel, const double *F, double dt,
+                                         const MdExtra &mx, uint64_t seed, uint64_t stream_base,
+                                         const long long *dev_step, hipStream_t s) {
+    if (h->n_total == 0) return hipSuccess;
+    prof_begin(h, 7, s);
+    hipLaunchKernelGGL(k_kick_drift_langevin, dim3((unsigned)((h->n_total + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                       s, h->w.sys, h->w.lay, h->n_sys, (int)h->n_total, pos, vel, F, dt, mx.c1, mx.c2, mx.margin,
+                       seed, stream_base, dev_step);
+    prof_end(h, 7, s);
+    return hipGetLastError();
+}
+
 __global__ __launch_bounds__(kBlock) void k_kick(int64_t n3, double *vel, const double *F, double dt) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n3) return;

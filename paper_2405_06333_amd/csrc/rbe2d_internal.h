@@ -121,9 +121,20 @@ struct Workspace {
     double4 *freal_s = nullptr;
     double2 *dgreal_s = nullptr;
     double *rpart_s = nullptr;
+    double *spart = nullptr;    // per real-space wave: short-range pair and wall energies
     int *err = nullptr;         // device error word
     long long *step = nullptr;  // device MD step counter (graph replays)
 };
+
+// MD extras in the form the kernels use (from rbe2d_md_params).
+struct MdExtra {
+    double c1, c2;                 // BAOAB O-step: v = c1 v + c2 xi
+    double sig2, eps, rc2;         // ion-ion WCA: sigma^2, eps, (2^(1/6) sigma)^2
+    double sigw2, epsw, hcut;      // wall WCA: sigma_w^2, eps_w, 2^(1/6) sigma_w
+    double margin;                 // reflecting walls of the integrator
+    bool short_on() const { return eps != 0.0 || epsw != 0.0; }
+};
+constexpr uint64_t kThermoStream = 1ull << 63;   // stream ids of the thermostat noise
 
 // Host copy of one system's setup.
 struct SysHost {
@@ -188,6 +199,12 @@ hipError_t launch_kforce(rbe2d_ctx *h, const double *pos, const double *q, doubl
                          uint32_t flags, bool accumulate, bool want_pot, bool add_real, const double *gE,
                          hipStream_t s);
 hipError_t launch_real(rbe2d_ctx *h, const double *pos, const double *q, bool want_dg, hipStream_t s);
+hipError_t launch_cells(rbe2d_ctx *h, const double *pos, const double *q, hipStream_t s);
+hipError_t launch_pairs(rbe2d_ctx *h, bool want_dg, hipStream_t s);
+hipError_t launch_short(rbe2d_ctx *h, const MdExtra &mx, double *F, double *energy, hipStream_t s);
+hipError_t launch_md_kick_drift_langevin(rbe2d_ctx *h, double *pos, double *vel, const double *F, double dt,
+                                         const MdExtra &mx, uint64_t seed, uint64_t stream_base,
+                                         const long long *dev_step, hipStream_t s);
 hipError_t launch_energy(rbe2d_ctx *h, double *energy, uint32_t flags, const double *gE, double *dEdgamma,
                          hipStream_t s);
 hipError_t launch_sample(rbe2d_ctx *h, uint64_t seed, uint64_t stream_id, const long long *dev_step,

@@ -613,6 +613,11 @@ __global__ __launch_bounds__(kBlock) void k_real_combine(RealArgs a, int n_total
 }
 
 hipError_t launch_real(rbe2d_ctx *h, const double *pos, const double *q, bool want_dg, hipStream_t s) {
+    hipError_t e = launch_cells(h, pos, q, s);
+    return e == hipSuccess ? launch_pairs(h, want_dg, s) : e;
+}
+
+hipError_t launch_cells(rbe2d_ctx *h, const double *pos, const double *q, hipStream_t s) {
     if (h->n_total == 0) return hipSuccess;
     CellArgs c;
     c.pos = pos; c.q = q; c.sys = h->w.sys; c.lay = h->w.lay; c.n_sys = h->n_sys;
@@ -631,6 +636,11 @@ hipError_t launch_real(rbe2d_ctx *h, const double *pos, const double *q, bool wa
     hipLaunchKernelGGL(k_cell_scatter, dim3(nb), dim3(kBlock), 0, s, c);
     hipLaunchKernelGGL(k_cell_rank, dim3(nb), dim3(kBlock), 0, s, c);
     prof_end(h, 3, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_pairs(rbe2d_ctx *h, bool want_dg, hipStream_t s) {
+    if (h->n_total == 0) return hipSuccess;
     RealArgs r;
     r.src = h->w.sorted; r.src16 = h->w.src16; r.sidx = h->w.sidx; r.scell = h->w.scell; r.start = h->w.start;
     r.sys = h->w.sys; r.fam = h->w.fam; r.lay = h->w.lay; r.n_sys = h->n_sys; r.n_waves = h->n_swaves;
@@ -666,6 +676,132 @@ hipError_t launch_real(rbe2d_ctx *h, const double *pos, const double *q, bool wa
                            (int)h->n_total, (int)want_dg);
     }
     prof_end(h, 4, s);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Short-range forces of the MD (purely repulsive shifted-truncated LJ between
+// ions and against the walls), on the cell list of the pair kernel.  One
+// thread per target in cell order; the cells within the LJ cutoff of the
+// target's cell are searched (all columns or rows of a small box once).
+// Forces are added to F; per-wave energy sums go to spart.
+// ---------------------------------------------------------------------------
+
+struct ShortArgs {
+    const double4 *src;
+    const int *sidx, *scell, *start;
+    const SysDesc *sys;
+    Layout lay;
+    int n_sys, n_waves;
+    MdExtra mx;
+    double *F;
+    double *spart;
+};
+
+__device__ __forceinline__ double lj_rep(double s2_over_r2, double eps, double *r_times_f) {
+    const double s6 = s2_over_r2 * s2_over_r2 * s2_over_r2;
+    *r_times_f = 24.0 * eps * (2.0 * s6 * s6 - s6);
+    return 4.0 * eps * (s6 * s6 - s6 + 0.25);
+}
+
+__global__ __launch_bounds__(kBlock) void k_short(ShortArgs a) {
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    const int r = __builtin_amdgcn_readfirstlane(find_sys(a.lay.sbase, a.n_sys, t & ~(kWave - 1)));
+    const SysDesc d = a.sys[r];
+    const int shift = a.lay.sbase[r] - a.lay.off[r];
+    const bool active = t - a.lay.sbase[r] < a.lay.off[r + 1] - a.lay.off[r];
+    double fx = 0, fy = 0, fz = 0, ep = 0, ew = 0;
+    if (active) {
+        const double4 me = a.src[t];
+        const int cid = a.scell[t];
+        const int cy = cid % d.ncy, cx = (cid / d.ncy) % d.ncx, cz = cid / (d.ncy * d.ncx);
+        const double xt = me.x + cx * d.hx;   // wrapped x of the target
+        if (a.mx.eps != 0.0) {
+            const double rc = sqrt(a.mx.rc2);
+            const int rx = (int)ceil(rc / d.hx), ry = (int)ceil(rc / d.hy), rz = (int)ceil(rc / d.hz);
+            const bool allx = d.ncx <= 2 * rx, ally = d.ncy <= 2 * ry;
+            const int x0 = allx ? 0 : cx - rx, x1 = allx ? d.ncx - 1 : cx + rx;
+            const int y0 = ally ? 0 : cy - ry, y1 = ally ? d.ncy - 1 : cy + ry;
+            const int z0 = max(0, cz - rz), z1 = min(d.ncz - 1, cz + rz);
+            const int *start = a.start + d.cbase;
+            for (int lz = z0; lz <= z1; lz++)
+                for (int ix = x0; ix <= x1; ix++) {
+                    const int cxx = (ix + d.ncx) % d.ncx;
+                    for (int iy = y0; iy <= y1; iy++) {
+                        const int cyy = (iy + d.ncy) % d.ncy;
+                        const int c = (lz * d.ncx + cxx) * d.ncy + cyy;
+                        const int b = start[c] + shift, e = start[c + 1] + shift;
+                        for (int j = b; j < e; j++) {
+                            if (j == t) continue;
+                            const double4 sj = a.src[j];
+                            double dx = xt - (sj.x + cxx * d.hx);
+                            double dy = me.y - sj.y;
+                            dx -= d.Lx * rint(dx / d.Lx);
+                            dy -= d.Ly * rint(dy / d.Ly);
+                            const double dz = me.z - sj.z;
+                            const double r2 = dx * dx + dy * dy + dz * dz;
+                            if (r2 < a.mx.rc2) {
+                                double rf;
+                                ep += 0.5 * lj_rep(a.mx.sig2 / r2, a.mx.eps, &rf);
+                                fx += rf / r2 * dx; fy += rf / r2 * dy; fz += rf / r2 * dz;
+                            }
+                        }
+                    }
+                }
+        }
+        if (a.mx.epsw != 0.0) {
+            const double hb = me.z, ht = d.H - me.z;
+            double rf;
+            if (hb > 0.0 && hb < a.mx.hcut) { ew += lj_rep(a.mx.sigw2 / (hb * hb), a.mx.epsw, &rf); fz += rf / hb; }
+            if (ht > 0.0 && ht < a.mx.hcut) { ew += lj_rep(a.mx.sigw2 / (ht * ht), a.mx.epsw, &rf); fz -= rf / ht; }
+        }
+        const int i = a.sidx[t];
+        a.F[3 * (int64_t)i] += fx;
+        a.F[3 * (int64_t)i + 1] += fy;
+        a.F[3 * (int64_t)i + 2] += fz;
+    }
+    ep = wave_sum(ep);
+    ew = wave_sum(ew);
+    if ((threadIdx.x & (kWave - 1)) == 0 && t / kWave < a.n_waves) {
+        a.spart[2 * (t / kWave)] = ep;
+        a.spart[2 * (t / kWave) + 1] = ew;
+    }
+}
+
+// per-system sums of the wave energies, fixed order
+__global__ __launch_bounds__(kBlock) void k_short_energy(const double *spart, Layout lay, double *energy) {
+    __shared__ double sh[kBlock / 64];
+    const int r = blockIdx.x;
+    double ep = 0, ew = 0;
+    for (int wv = lay.sbase[r] / kWave + threadIdx.x; wv < lay.sbase[r + 1] / kWave; wv += kBlock) {
+        ep += spart[2 * wv];
+        ew += spart[2 * wv + 1];
+    }
+    ep = block_sum(ep, sh);
+    ew = block_sum(ew, sh);
+    if (threadIdx.x == 0) {
+        energy[2 * r] = ep;
+        energy[2 * r + 1] = ew;
+    }
+}
+
+hipError_t launch_short(rbe2d_ctx *h, const MdExtra &mx, double *F, double *energy, hipStream_t s) {
+    prof_begin(h, 9, s);
+    if (h->n_total > 0 && mx.short_on()) {
+        ShortArgs a;
+        a.src = h->w.sorted; a.sidx = h->w.sidx; a.scell = h->w.scell; a.start = h->w.start;
+        a.sys = h->w.sys; a.lay = h->w.lay; a.n_sys = h->n_sys; a.n_waves = h->n_swaves;
+        a.mx = mx; a.F = F; a.spart = h->w.spart;
+        hipLaunchKernelGGL(k_short, dim3((h->n_swaves * kWave + kBlock - 1) / kBlock), dim3(kBlock), 0, s, a);
+    }
+    if (energy) {
+        if (h->n_total > 0 && mx.short_on()) {
+            hipLaunchKernelGGL(k_short_energy, dim3(h->n_sys), dim3(kBlock), 0, s, h->w.spart, h->w.lay, energy);
+        } else {
+            (void)launch_fill(energy, (int64_t)h->n_sys * 2 * sizeof(double), s);
+        }
+    }
+    prof_end(h, 9, s);
     return hipGetLastError();
 }
 

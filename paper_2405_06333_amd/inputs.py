@@ -70,10 +70,34 @@ def positions(rng, N, Lx, Ly, H, margin):
     return np.ascontiguousarray(np.stack([x, y, z], axis=1))
 
 
+def thinned_positions(rng, N, Lx, Ly, H, margin, dmin, max_rounds=500):
+    """Uniform positions as positions(), then every particle closer than dmin
+    to another one (minimum image in x and y) is redrawn until none is: the
+    start of runs with a short-range repulsion."""
+    from scipy.spatial import cKDTree
+    pos = positions(rng, N, Lx, Ly, H, margin)
+    if N < 2:
+        return pos
+    box = [Lx, Ly, 4.0 * H]   # z is not periodic: its period exceeds every distance
+    for _ in range(max_rounds):
+        pos[:, 0] %= Lx
+        pos[:, 1] %= Ly
+        pairs = cKDTree(pos, boxsize=box).query_pairs(dmin, output_type="ndarray")
+        if len(pairs) == 0:
+            return pos
+        redo = np.unique(pairs[:, 1])
+        pos[redo] = positions(rng, len(redo), Lx, Ly, H, margin)
+    raise RuntimeError("could not place the particles at the requested minimum distance")
+
+
 def sample(w: Workload):
-    """(pos (N,3), q (N,)) for a workload, from numpy's default_rng(seed)."""
+    """(pos (N,3), q (N,)) for a workload, from numpy's default_rng(seed);
+    with extra["dmin"] the positions are thinned to that minimum distance."""
     rng = np.random.default_rng(w.seed)
-    pos = positions(rng, w.N, w.Lx, w.Ly, w.H, w.margin)
+    if w.extra.get("dmin"):
+        pos = thinned_positions(rng, w.N, w.Lx, w.Ly, w.H, w.margin, w.extra["dmin"])
+    else:
+        pos = positions(rng, w.N, w.Lx, w.Ly, w.H, w.margin)
     return pos, charges(w.N, w.valence)
 
 

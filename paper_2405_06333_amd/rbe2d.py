@@ -24,9 +24,10 @@ EXPORTS = ("rbe2d_create", "rbe2d_destroy", "rbe2d_query", "rbe2d_draw_kset", "r
            "rbe2d_sample_kset", "rbe2d_get_kset", "rbe2d_forces", "rbe2d_energy",
            "rbe2d_energy_backward", "rbe2d_md_run", "rbe2d_profile_enable", "rbe2d_profile_read",
            "rbe2d_check", "rbe2d_last_error", "rbe2d_batch_create", "rbe2d_query_system",
-           "rbe2d_batch_forces", "rbe2d_batch_md_run", "rbe2d_autotune")
+           "rbe2d_batch_forces", "rbe2d_batch_md_run", "rbe2d_autotune", "rbe2d_short_forces",
+           "rbe2d_md_run_ex")
 PROF_SLOTS = ("prep", "sf_pass", "assemble", "cell_build", "real_pairs", "force_scatter", "energy",
-              "integrator", "ksample")
+              "integrator", "ksample", "short_range")
 
 
 class RBE2DError(RuntimeError):
@@ -43,6 +44,18 @@ class Params(ctypes.Structure):
                 ("P", ctypes.c_int32), ("M", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("n_max", ctypes.c_int64),
                 ("coulomb_prefactor", ctypes.c_double)]
+
+
+class MdParams(ctypes.Structure):
+    """rbe2d_md_params: Langevin thermostat (BAOAB) and short-range repulsion."""
+    _fields_ = [("gamma", ctypes.c_double), ("kT", ctypes.c_double), ("sigma", ctypes.c_double),
+                ("eps", ctypes.c_double), ("sigma_wall", ctypes.c_double), ("eps_wall", ctypes.c_double),
+                ("wall_margin", ctypes.c_double)]
+
+
+def md_params(gamma=0.0, kT=0.0, sigma=1.0, eps=0.0, sigma_wall=0.5, eps_wall=0.0, wall_margin=0.1):
+    return MdParams(float(gamma), float(kT), float(sigma), float(eps), float(sigma_wall), float(eps_wall),
+                    float(wall_margin))
 
 
 _lib = None
@@ -76,6 +89,9 @@ def lib():
         L.rbe2d_batch_md_run.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_double,
                                          ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _vp]
         L.rbe2d_autotune.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
+        L.rbe2d_short_forces.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(MdParams), _vp]
+        L.rbe2d_md_run_ex.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_double, ctypes.POINTER(MdParams),
+                                      ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _vp]
         L.rbe2d_profile_enable.argtypes = [_vp, ctypes.c_int32]
         L.rbe2d_profile_read.argtypes = [_vp, _vp, _vp, ctypes.c_int32]
         L.rbe2d_check.argtypes = [_vp, _vp]
@@ -226,6 +242,41 @@ class Slab:
             float(z_lo), float(z_hi), ctypes.c_uint64(seed), int(step0), int(n_steps), int(bool(use_graph)),
             _stream()))
 
+    def _offsets_for(self, N):
+        return np.array([0, N], dtype=np.int64)
+
+    def _short(self, off, pos, q, F, want_energy, md):
+        import torch
+        N = int(off[-1])
+        n_sys = len(off) - 1
+        if F is None:
+            F = torch.zeros((N, 3), dtype=torch.float64, device=pos.device)
+        E = torch.empty((n_sys, 2), dtype=torch.float64, device=pos.device) if want_energy else None
+        self._ok(lib().rbe2d_short_forces(
+            self._h, ctypes.c_void_p(off.ctypes.data), _dptr(pos, torch.float64, (N, 3), "pos"),
+            _dptr(q, torch.float64, (N,), "q"), _dptr(F, torch.float64, (N, 3), "F"),
+            _dptr(E, torch.float64, None, "energy"), ctypes.byref(md), _stream()))
+        return (F, E) if want_energy else F
+
+    def _md_ex(self, off, pos, vel, q, F, dt, md, seed, step0, n_steps, use_graph):
+        import torch
+        N = int(off[-1])
+        self._ok(lib().rbe2d_md_run_ex(
+            self._h, ctypes.c_void_p(off.ctypes.data), _dptr(pos, torch.float64, (N, 3), "pos"),
+            _dptr(vel, torch.float64, (N, 3), "vel"), _dptr(q, torch.float64, (N,), "q"),
+            _dptr(F, torch.float64, (N, 3), "F"), float(dt), ctypes.byref(md), ctypes.c_uint64(seed),
+            int(step0), int(n_steps), int(bool(use_graph)), _stream()))
+
+    def short_forces(self, pos, q, md, F=None, want_energy=False):
+        """Adds the short-range forces of md (MdParams) to F (new zeros if None);
+        with want_energy also returns {E_ion_ion, E_wall} (device (1, 2))."""
+        return self._short(self._offsets_for(int(q.shape[0])), pos, q, F, want_energy, md)
+
+    def md_run_ex(self, pos, vel, q, F, dt, md, seed, step0, n_steps, use_graph=False):
+        """BAOAB steps with the short-range forces of md; F must hold the total
+        initial forces (forces() + short_forces())."""
+        self._md_ex(self._offsets_for(int(q.shape[0])), pos, vel, q, F, dt, md, seed, step0, n_steps, use_graph)
+
     def autotune(self, pos, q):
         """Time the candidate launch parameters for this N on these inputs and
         keep the fastest; returns {per, ksplit, rsplit}."""
@@ -327,6 +378,12 @@ class BatchedSlab(Slab):
             _dptr(q, torch.float64, (N,), "q"), _dptr(F, torch.float64, (N, 3), "F"),
             _dptr(E, torch.float64, (self.n_sys, 5), "energy"), flags, _stream()))
         return (F, E) if want_energy else F
+
+    def short_forces(self, offsets, pos, q, md, F=None, want_energy=False):
+        return self._short(self._off(offsets), pos, q, F, want_energy, md)
+
+    def md_run_ex(self, offsets, pos, vel, q, F, dt, md, seed, step0, n_steps, use_graph=False):
+        self._md_ex(self._off(offsets), pos, vel, q, F, dt, md, seed, step0, n_steps, use_graph)
 
     def autotune(self, offsets, pos, q):
         import torch
