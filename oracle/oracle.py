@@ -568,3 +568,98 @@ def baoab_step(pos, vel, F, dt, gamma, kT, normals, Lx, Ly, zlo, zhi, force):
     Fn = force(pos)
     vel = vel + 0.5 * dt * Fn
     return pos, vel, Fn
+
+
+# ---------------------------------------------------------------------------
+# Parameter selection (Sec. 2.4, Theorem 3.2, Eq. (3.23)) and the stochastic
+# error of the k-space force (Theorem 2.2).  Test infrastructure.
+# ---------------------------------------------------------------------------
+
+def image_truncation_estimate(M, g_top, g_bot, H, Lmax):
+    """Eq. (3.37) with unit constant: |g_top|^floor((M+1)/2) |g_bot|^ceil((M+1)/2)
+    exp(-2 pi H (M-1) / max(Lx, Ly))."""
+    a = abs(g_top) ** ((M + 1) // 2) if (M + 1) // 2 else 1.0
+    b = abs(g_bot) ** ((M + 2) // 2) if (M + 2) // 2 else 1.0
+    return a * b * math.exp(-2.0 * math.pi * H * (M - 1) / Lmax)
+
+
+def image_order_for(tol, g_top, g_bot, H, Lmax, M_max=64):
+    """Smallest M >= 0 whose Eq. (3.37) estimate is at most tol (Theorem 3.2)."""
+    for M in range(0, M_max + 1):
+        if image_truncation_estimate(M, g_top, g_bot, H, Lmax) <= tol:
+            return M
+    return M_max
+
+
+def suggest_params(N, Lx, Ly, H, g_top, g_bot, tol):
+    """alpha = (N / (Lx Ly H))^(1/3) (Sec. 2.4, independent of Lz); r_c such
+    that the real-space tail exp(-alpha^2 r_c^2) is tol, at most min(Lx, Ly)/2
+    (then alpha follows r_c); M from Theorem 3.2; Lz from Eq. (3.23) at tol."""
+    lg = math.log(1.0 / tol)
+    alpha = (N / (Lx * Ly * H)) ** (1.0 / 3.0)
+    rc = math.sqrt(lg) / alpha
+    if rc > 0.5 * min(Lx, Ly):
+        rc = 0.5 * min(Lx, Ly)
+        alpha = math.sqrt(lg) / rc
+    M = image_order_for(tol, g_top, g_bot, H, max(Lx, Ly))
+    Lz = lz_ext(Lx, Ly, H, M, alpha, tol)
+    return dict(alpha=alpha, r_c=rc, M=M, Lz=Lz)
+
+
+def kspace_terms(slab: Slab, pos, q, n, c):
+    """Per-k contributions t_l(i) to the k-space force (Eqs. (3.25)-(3.26),
+    reading R2): -q_i c_l [k_l Im(e^{-i k_l.r_i} A_l) + khat_l Im(e^{-i khat_l.r_i} B_l)],
+    A = rho^M + (1 + conj Y_even) rho, B = conj(Y_odd) rho.  Shape (P, N, 3)."""
+    pos, q = _prep(pos, q)
+    n = np.ascontiguousarray(n, dtype=np.int32).reshape(-1, 3)
+    P = n.shape[0]
+    b = slab.box()
+    rho = np.zeros(2 * P)
+    rhohat = np.zeros(2 * P)
+    lib().orc_rho(len(q), _p(pos), _p(q), ctypes.byref(b), P, _p(n, _I32), 0, _p(rho))
+    lib().orc_rho(len(q), _p(pos), _p(q), ctypes.byref(b), P, _p(n, _I32), 1, _p(rhohat))
+    Yo = np.zeros(2 * P)
+    Ye = np.zeros(2 * P)
+    lib().orc_Y(ctypes.byref(b), P, _p(n, _I32), _p(Yo), _p(Ye))
+    cz = lambda a: a[0::2] + 1j * a[1::2]  # noqa: E731
+    rho, rhohat, Yo, Ye = cz(rho), cz(rhohat), cz(Yo), cz(Ye)
+    rhoM = (1 + Ye) * rho + Yo * rhohat
+    A = rhoM + (1 + np.conj(Ye)) * rho
+    B = np.conj(Yo) * rho
+    k = kvectors(slab, n)
+    kh = k * np.array([1.0, 1.0, -1.0])
+    ph = pos @ k.T          # (N, P)
+    phh = pos @ kh.T
+    X = np.imag(np.exp(-1j * ph) * A[None, :])
+    Y = np.imag(np.exp(-1j * phh) * B[None, :])
+    t = -(q[:, None, None] * np.asarray(c)[None, :, None]) * (X[:, :, None] * k[None] + Y[:, :, None] * kh[None])
+    return np.transpose(t, (1, 0, 2))
+
+
+def force_variance_estimate(slab: Slab, pos, q, n, c=None):
+    """Unbiased estimate, from one batch, of E|Xi_i|^2 of Theorem 2.2 (the
+    variance of the RBE k-space force of particle i): the per-k terms are
+    i.i.d. given the positions, F = sum_l t_l, so the sample variance gives
+    (P sum_l |t_l|^2 - |F|^2) / (P - 1)."""
+    n = np.asarray(n).reshape(-1, 3)
+    P = n.shape[0]
+    c = rbe_weights(slab, n) if c is None else c
+    t = kspace_terms(slab, pos, q, n, c)
+    F = t.sum(axis=0)
+    return (P * (t * t).sum(axis=(0, 2)) - (F * F).sum(axis=1)) / (P - 1)
+
+
+def force_variance_exact(slab: Slab, pos, q, P, cut=40.0):
+    """Theorem 2.2 written out over every k (deterministic sum): with per-k force
+    g(k) = P t(k) at batch weight 2 pi S/(V P k^2) and sampling probability
+    p(k) = exp(-k^2/4alpha^2)/S, E|Xi_i|^2 = (sum_k p(k) |g_i(k)|^2 - |F_i|^2)/P,
+    F_i = sum_k p(k) g_i(k) the deterministic k-space force."""
+    n, _ = full_kset(slab, cut)
+    S = norm_S(slab.alpha, slab.Lx, slab.Ly, slab.Lz)
+    k = kvectors(slab, n)
+    k2 = (k * k).sum(axis=1)
+    pk = np.exp(-k2 / (4.0 * slab.alpha ** 2)) / S
+    g = kspace_terms(slab, pos, q, n, 2.0 * np.pi * S / (slab.V * k2))   # one sample's force, P = 1
+    F = (pk[:, None, None] * g).sum(axis=0)
+    second = (pk[:, None] * (g * g).sum(axis=2)).sum(axis=0)
+    return (second - (F * F).sum(axis=1)) / P

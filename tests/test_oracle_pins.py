@@ -523,3 +523,67 @@ def test_baoab_thermostat_reaches_equipartition(orc):
         if step >= 30:
             v2.append((vel ** 2).mean())
     assert abs(np.mean(v2) - kT) < 0.06 * kT
+
+
+# ---------------------------------------------------------------------------
+# Parameter selection and the stochastic force error
+# ---------------------------------------------------------------------------
+
+def test_image_order_reproduces_the_papers_example(orc):
+    """After Theorem 3.2: for H about max(Lx, Ly) and |gamma| = 1, an accuracy
+    of 1e-5 needs M = 3 image levels."""
+    assert orc.image_order_for(1e-5, 1.0, 1.0, 10.0, 10.0) == 3
+    assert orc.image_order_for(1e-5, -1.0, 1.0, 10.0, 10.0) == 3
+    # no interface: no image is needed; one interface: its single image
+    assert orc.image_order_for(1e-5, 0.0, 0.0, 10.0, 100.0) == 0
+    assert orc.image_order_for(1e-5, 0.0, 0.9, 10.0, 100.0) == 1
+
+
+@pytest.mark.parametrize("g,H,L,tol", [(0.9, 10.0, 50.0, 1e-5), (0.95, 40.0, 800.0, 1e-5), (0.5, 5.0, 20.0, 1e-8),
+                                       (1.0, 3.0, 9.0, 1e-4)])
+def test_image_order_matches_closed_form(orc, g, H, L, tol):
+    """For |gamma_top| = |gamma_bot| the smallest admissible M is Eq. (3.38)
+    rounded up."""
+    a = 4 * np.pi * H / L
+    lg = np.log(g * g)
+    closed = (2 * np.log(tol) - a - lg) / (lg - a)
+    assert orc.image_order_for(tol, g, -g, H, L) == max(0, int(np.ceil(closed - 1e-12)))
+
+
+def test_suggested_parameters(orc):
+    s = orc.suggest_params(10_000, 50.0, 50.0, 10.0, 0.9, 0.9, 1e-5)
+    assert abs(s["alpha"] - (10_000 / 25_000.0) ** (1 / 3)) < 1e-15
+    assert abs(np.exp(-(s["alpha"] * s["r_c"]) ** 2) - 1e-5) < 1e-12
+    assert s["Lz"] >= (s["M"] + 1) * 10.0
+    assert orc.image_truncation_estimate(s["M"], 0.9, 0.9, 10.0, 50.0) <= 1e-5 < \
+        orc.image_truncation_estimate(s["M"] - 1, 0.9, 0.9, 10.0, 50.0)
+    # a dilute small box: r_c is capped at half the box and alpha follows it
+    s = orc.suggest_params(10, 10.0, 10.0, 5.0, 0.0, 0.0, 1e-5)
+    assert s["r_c"] == 5.0 and abs(s["alpha"] * 5.0 - np.sqrt(np.log(1e5))) < 1e-12 and s["M"] == 0
+
+
+@pytest.mark.parametrize("gammas,M", [((0.0, 0.0), 0), ((0.8, -0.6), 4)])
+def test_force_variance_estimate_is_unbiased(orc, gammas, M):
+    """Theorem 2.2: over many independent batches, the mean of the one-batch
+    estimates and the observed variance of the force both equal the variance
+    written out over every k."""
+    sl = orc.Slab(Lx=8, Ly=8, H=4, g_top=gammas[0], g_bot=gammas[1], alpha=0.8, rc=3.5, M=M, P=10)
+    rng = np.random.default_rng(0)
+    N = 24
+    pos = np.column_stack([rng.uniform(0, 8, N), rng.uniform(0, 8, N), rng.uniform(0.3, 3.7, N)])
+    q = np.where(np.arange(N) < N // 2, 1.0, -1.0)
+    exact = orc.force_variance_exact(sl, pos, q, 10)
+    est, Fs = [], []
+    for s in range(400):
+        n = orc.draw_kset(sl, 3, s)
+        c = orc.rbe_weights(sl, n)
+        t = orc.kspace_terms(sl, pos, q, n, c)
+        Fs.append(t.sum(axis=0))
+        est.append(orc.force_variance_estimate(sl, pos, q, n, c))
+    Fs = np.array(Fs)
+    emp = ((Fs - Fs.mean(axis=0)) ** 2).sum(axis=2).mean(axis=0)
+    assert abs(np.mean(est, axis=0).sum() / exact.sum() - 1) < 0.05
+    assert abs(emp.sum() / exact.sum() - 1) < 0.08
+    # and the per-k terms add up to the oracle's k-space force
+    _, F, *_ = orc.kspace(sl, pos, q, n, c)
+    assert np.abs(Fs[-1] - F).max() < 1e-12 * np.abs(F).max()
