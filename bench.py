@@ -138,6 +138,12 @@ def run_md(R, torch, w, precision, steps, warmup, profile, use_graph=False, auto
     prof = slab.profile_read() if profile else None
     slab.check()
     finite = bool(torch.isfinite(F_).all().item() and torch.isfinite(P_).all().item())
+    if profile:
+        # stochastic error of the k-space force at this P (Theorem 2.2), on the
+        # final configuration and k-set: rms of the per-particle estimate
+        var = slab.force_variance(P_, Q_)
+        tuned = {"launch_params": tuned, "kspace_force_sigma_rms": float(var.mean().sqrt().item()),
+                 "total_force_rms": float((F_ * F_).sum(dim=1).mean().sqrt().item())}
     return (t1 - t0), prof, finite, tuned
 
 
@@ -408,7 +414,10 @@ def main():
         "md_langevin_wca": langevin,
         "batched_replicas": batch,
         "differentiable": grad,
-        "launch_params": tuned,
+        "launch_params": tuned["launch_params"] if tuned else None,
+        "kspace_force_error": ({"sigma_rms": tuned["kspace_force_sigma_rms"], "force_rms": tuned["total_force_rms"],
+                                "P": w.P, "estimator": "sample variance of the per-k force terms (Theorem 2.2)"}
+                               if tuned else None),
         "kernels": kern,
         "finite": finite,
     }

@@ -271,6 +271,35 @@ rbe2d_status rbe2d_md_run_ex(rbe2d_handle h, const int64_t *offsets, double *pos
                              uint64_t seed, int64_t step0, int32_t n_steps, int32_t use_graph,
                              void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Parameter selection and the stochastic error of the k-space force.
+ * ------------------------------------------------------------------------- */
+
+/* Pure host function.  Fills, for N charges in an Lx x Ly x H slab with the
+ * given contrasts and a target tolerance tol in (0, 1):
+ *   alpha = (N / (Lx Ly H))^(1/3) (Sec. 2.4: independent of Lz);
+ *   r_c such that exp(-alpha^2 r_c^2) = tol, at most min(Lx, Ly)/2 (then
+ *     alpha = sqrt(ln(1/tol)) / r_c);
+ *   M, the smallest order (<= 64) whose image truncation estimate of
+ *     Theorem 3.2, |gamma_top|^floor((M+1)/2) |gamma_bot|^ceil((M+1)/2)
+ *     exp(-2 pi H (M-1) / max(Lx, Ly)), is at most tol;
+ *   eps_lz = tol and Lz_ext from Eq. (3.23);
+ * and copies Lx, Ly, H, gamma_top, gamma_bot into *p.  P, precision, n_max,
+ * reserved and coulomb_prefactor are left as they are.  Errors:
+ * RBE2D_E_INVAL. */
+rbe2d_status rbe2d_suggest_params(int64_t N, double Lx, double Ly, double H, double gamma_top,
+                                  double gamma_bot, double tol, rbe2d_params *p);
+
+/* Per-particle estimate of E|Xi_i|^2, the variance of the RBE k-space force
+ * of particle i (Theorem 2.2), from the current k-set: the P per-k force
+ * terms t_l(i) are i.i.d. given the positions and sum to F_i^k, so
+ * var_i = (P sum_l |t_l(i)|^2 - |F_i^k|^2) / (P - 1) is unbiased (0 when
+ * P = 1).  var: device, offsets[n_sys] doubles.  offsets as in
+ * rbe2d_batch_forces ({0, N} for a single system).  Enqueued only.  Errors
+ * as rbe2d_batch_forces. */
+rbe2d_status rbe2d_force_variance(rbe2d_handle h, const int64_t *offsets, const double *pos,
+                                  const double *q, double *var, void *stream);
+
 /* Autotuner.  Times, with HIP events on `stream`, the candidate launch
  * parameters of the evaluation for the particle layout given by offsets
  * (host, n_sys + 1 int64, as in rbe2d_batch_forces; {0, N} for a single

@@ -789,6 +789,59 @@ rbe2d_status rbe2d_batch_md_run(rbe2d_handle h, const int64_t *offsets, double *
                   s);
 }
 
+rbe2d_status rbe2d_force_variance(rbe2d_handle h, const int64_t *offsets, const double *pos, const double *q,
+                                  double *var, void *stream) {
+    if (!h) return fail(nullptr, RBE2D_E_INVAL, "handle is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    rbe2d_status st = layout_from_offsets(h, offsets, s);
+    if (st) return st;
+    st = check_arrays(h, pos, q);
+    if (st) return st;
+    if (h->n_total > 0 && !var) return fail(h, RBE2D_E_INVAL, "var is NULL");
+    st = run_common(h, pos, q, RBE2D_KSPACE, false, s);
+    if (st) return st;
+    RBE2D_TRY(h, launch_kforce(h, pos, q, nullptr, nullptr, RBE2D_KSPACE, false, false, false, nullptr, s, var),
+              "variance launch");
+    return RBE2D_OK;
+}
+
+rbe2d_status rbe2d_suggest_params(int64_t N, double Lx, double Ly, double H, double gamma_top, double gamma_bot,
+                                  double tol, rbe2d_params *p) {
+    if (!p) return fail(nullptr, RBE2D_E_INVAL, "params is NULL");
+    if (N < 1 || !finite_pos(Lx) || !finite_pos(Ly) || !finite_pos(H))
+        return fail(nullptr, RBE2D_E_INVAL, "need N >= 1 and finite Lx, Ly, H > 0");
+    if (!(tol > 0.0 && tol < 1.0)) return fail(nullptr, RBE2D_E_INVAL, "tol must be in (0, 1)");
+    if (!(std::fabs(gamma_top) <= 1.0) || !(std::fabs(gamma_bot) <= 1.0))
+        return fail(nullptr, RBE2D_E_INVAL, "|gamma_top|, |gamma_bot| must be <= 1");
+    const double lg = std::log(1.0 / tol);
+    // alpha ~ (N / (Lx Ly H))^(1/3), independent of Lz (Sec. 2.4)
+    double alpha = std::cbrt((double)N / (Lx * Ly * H));
+    // real-space tail exp(-alpha^2 r_c^2) = tol, with r_c <= min(Lx, Ly)/2
+    double rc = std::sqrt(lg) / alpha;
+    if (rc > 0.5 * std::min(Lx, Ly)) {
+        rc = 0.5 * std::min(Lx, Ly);
+        alpha = std::sqrt(lg) / rc;
+    }
+    // smallest M whose image truncation estimate of Theorem 3.2 is within tol
+    const double decay = 2.0 * kPi * H / std::max(Lx, Ly);
+    int M = 0;
+    for (; M < 64; M++) {
+        int a, b;
+        exponents(M + 1, -1, &a, &b);   // floor((M+1)/2) of gamma_top, ceil((M+1)/2) of gamma_bot
+        const double est = ipow(std::fabs(gamma_top), a) * ipow(std::fabs(gamma_bot), b) * std::exp(-decay * (M - 1));
+        if (est <= tol) break;
+    }
+    p->alpha = alpha;
+    p->r_c = rc;
+    p->M = M;
+    p->gamma_top = gamma_top;
+    p->gamma_bot = gamma_bot;
+    p->Lx = Lx; p->Ly = Ly; p->H = H;
+    p->eps_lz = tol;
+    p->Lz_ext = auto_lz(p);
+    return RBE2D_OK;
+}
+
 rbe2d_status rbe2d_short_forces(rbe2d_handle h, const int64_t *offsets, const double *pos, const double *q,
                                 double *F, double *energy, const rbe2d_md_params *mp, void *stream) {
     if (!h) return fail(nullptr, RBE2D_E_INVAL, "handle is NULL");

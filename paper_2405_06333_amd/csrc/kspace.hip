@@ -352,8 +352,8 @@ __global__ __launch_bounds__(64) void k_assemble(AssembleArgs a) {
     rec[3] = c * Ar; rec[4] = c * Ai; rec[5] = c * Br; rec[6] = c * Bi;
     rec[7] = e; rec[8] = de[0]; rec[9] = de[1];
     rec[10] = nx; rec[11] = ny; rec[12] = nz;
-    rec[13] = rr; rec[14] = ri; rec[15] = 0.0;
-    a.kf32[2 * kg] = make_float4((float)kx, (float)ky, (float)kz, 0.0f);
+    rec[13] = rr; rec[14] = ri; rec[15] = kx * kx + ky * ky;
+    a.kf32[2 * kg] = make_float4((float)kx, (float)ky, (float)kz, (float)(kx * kx + ky * ky));
     a.kf32[2 * kg + 1] = make_float4((float)(c * Ar), (float)(c * Ai), (float)(c * Br), (float)(c * Bi));
 }
 
@@ -421,8 +421,9 @@ struct ForceArgs {
     double *fpart;           // [split][n_threads][4] when splitting
     double *F;               // final output (caller order, N x 3)
     double *dEdq;            // final dE/dq when want_pot
+    double *var;             // force-variance estimate per particle (variance mode)
     const double *gE;        // scale of the backward outputs (device scalar) or null
-    int accumulate, add_real, want_pot, do_kspace, do_ibc, split;
+    int accumulate, add_real, want_pot, want_var, do_kspace, do_ibc, split;
 };
 
 __device__ __forceinline__ void finish_particle(const ForceArgs &a, int r, int64_t g, double fx,
@@ -430,6 +431,12 @@ __device__ __forceinline__ void finish_particle(const ForceArgs &a, int r, int64
     const SysDesc &d = a.sys[r];
     const double *sc = a.scal + 8 * r;
     const double qi = a.q[g];
+    if (a.want_var) {
+        // pot carries sum_l |t_l|^2 / q_i^2: (P sum |t|^2 - |F|^2) / (P - 1)
+        const double P = (double)a.P;
+        a.var[g] = a.P > 1 ? qi * qi * (P * pot - (fx * fx + fy * fy + fz * fz)) / (P - 1.0) : 0.0;
+        return;
+    }
     double Fx = 0, Fy = 0, Fz = 0, ph = 0;
     if (a.do_kspace) {
         Fx = -qi * fx; Fy = -qi * fy; Fz = -qi * fz;
@@ -459,7 +466,9 @@ __device__ __forceinline__ void finish_particle(const ForceArgs &a, int r, int64
     }
 }
 
-template <bool WANT_POT>
+// MODE 0: forces; 1: forces and potentials (adjoint); 2: forces and the sum
+// of the squared per-k force terms (variance estimate)
+template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_force32(ForceArgs a) {
     const int b = blockIdx.x;
     const int r = find_sys(a.lay.bbase, a.n_sys, b);
@@ -495,10 +504,11 @@ __global__ __launch_bounds__(kBlock) void k_force32(ForceArgs a) {
                 fx = fmaf(kv.x, sp, fx);
                 fy = fmaf(kv.y, sp, fy);
                 fz = fmaf(kv.z, sm, fz);
-                if (WANT_POT) {
+                if (MODE == 1) {
                     pt = fmaf(ab.x, c1f, pt); pt = fmaf(ab.y, s1f, pt);
                     pt = fmaf(ab.z, c2f, pt); pt = fmaf(ab.w, s2f, pt);
                 }
+                if (MODE == 2) pt = fmaf(kv.w * sp, sp, fmaf(kv.z * sm, kv.z * sm, pt));
             }
             Fx += fx; Fy += fy; Fz += fz; Pt += pt;
         }
@@ -511,7 +521,7 @@ __global__ __launch_bounds__(kBlock) void k_force32(ForceArgs a) {
     }
 }
 
-template <bool WANT_POT>
+template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_force64(ForceArgs a) {
     const int b = blockIdx.x;
     const int r = find_sys(a.lay.bbase, a.n_sys, b);
@@ -540,10 +550,11 @@ __global__ __launch_bounds__(kBlock) void k_force64(ForceArgs a) {
             fx = fma(rec[0], sp, fx);
             fy = fma(rec[1], sp, fy);
             fz = fma(rec[2], sm, fz);
-            if (WANT_POT) {
+            if (MODE == 1) {
                 pt = fma(rec[3], c1, pt); pt = fma(rec[4], s1, pt);
                 pt = fma(rec[5], c2, pt); pt = fma(rec[6], s2, pt);
             }
+            if (MODE == 2) pt = fma(rec[15] * sp, sp, fma(rec[2] * sm, rec[2] * sm, pt));
         }
     }
     if (a.split) {
@@ -577,15 +588,15 @@ int choose_ksplit(int64_t nb, int P) {
 
 hipError_t launch_kforce(rbe2d_ctx *h, const double *pos, const double *q, double *F, double *dEdq,
                          uint32_t flags, bool accumulate, bool want_pot, bool add_real, const double *gE,
-                         hipStream_t s) {
+                         hipStream_t s, double *var) {
     if (h->n_total == 0) return hipSuccess;
     ForceArgs a;
     a.p32 = h->w.p32; a.p64 = h->w.p64; a.kn32 = h->w.kn32; a.kn64 = h->w.kn64;
     a.kf32 = h->w.kf32; a.krec = h->w.krec; a.lay = h->w.lay; a.sys = h->w.sys;
     a.n_sys = h->n_sys; a.P = h->P; a.P_pad = h->P_pad; a.n_threads = h->n_blocks * kBlock;
     a.pos = pos; a.q = q; a.scal = h->w.scal; a.freal = h->w.freal;
-    a.fpart = h->w.fpart; a.F = F; a.dEdq = dEdq; a.gE = gE;
-    a.accumulate = accumulate; a.add_real = add_real; a.want_pot = want_pot;
+    a.fpart = h->w.fpart; a.F = F; a.dEdq = dEdq; a.gE = gE; a.var = var;
+    a.accumulate = accumulate; a.add_real = add_real; a.want_pot = want_pot; a.want_var = var != nullptr;
     a.do_kspace = (flags & RBE2D_KSPACE) != 0; a.do_ibc = (flags & RBE2D_IBC) != 0;
     int split = 1;
     if (a.do_kspace) {
@@ -601,11 +612,13 @@ hipError_t launch_kforce(rbe2d_ctx *h, const double *pos, const double *q, doubl
     dim3 g(h->n_blocks, split);
     prof_begin(h, 5, s);
     if (fp32) {
-        if (want_pot) hipLaunchKernelGGL(k_force32<true>, g, dim3(kBlock), 0, s, a);
-        else hipLaunchKernelGGL(k_force32<false>, g, dim3(kBlock), 0, s, a);
+        if (var) hipLaunchKernelGGL(k_force32<2>, g, dim3(kBlock), 0, s, a);
+        else if (want_pot) hipLaunchKernelGGL(k_force32<1>, g, dim3(kBlock), 0, s, a);
+        else hipLaunchKernelGGL(k_force32<0>, g, dim3(kBlock), 0, s, a);
     } else {
-        if (want_pot) hipLaunchKernelGGL(k_force64<true>, g, dim3(kBlock), 0, s, a);
-        else hipLaunchKernelGGL(k_force64<false>, g, dim3(kBlock), 0, s, a);
+        if (var) hipLaunchKernelGGL(k_force64<2>, g, dim3(kBlock), 0, s, a);
+        else if (want_pot) hipLaunchKernelGGL(k_force64<1>, g, dim3(kBlock), 0, s, a);
+        else hipLaunchKernelGGL(k_force64<0>, g, dim3(kBlock), 0, s, a);
     }
     if (a.split) hipLaunchKernelGGL(k_force_combine, dim3(h->n_blocks), dim3(kBlock), 0, s, a, split);
     prof_end(h, 5, s);

@@ -66,7 +66,7 @@ struct SysDesc {
 // Per-k record written by the reduce/assemble kernel (FP64):
 //   [0..2] kx, ky, kz      [3..6] c*A (re, im), c*B (re, im)
 //   [7] e_l = c Re(rho conj(rho^M))   [8..9] d e_l / d gamma_{top,bot}
-//   [10..12] nx, ny, nz (as doubles)  [13..14] rho (re, im)
+//   [10..12] nx, ny, nz (as doubles)  [13..14] rho (re, im)  [15] kx^2 + ky^2
 constexpr int kKRec = 16;
 
 // Layout of the particles of all systems in the internal arrays (device
@@ -104,7 +104,7 @@ struct Workspace {
     double4 *kn64 = nullptr;    // per k: (nx, ny, nz, 0) as doubles
     void *sfpart = nullptr;     // structure-factor partials [tile][P_pad][4] (float or double)
     double *krec = nullptr;     // per-k records, kKRec doubles each (n_sys x P)
-    float4 *kf32 = nullptr;     // per k: (kx, ky, kz, 0), (cAr, cAi, cBr, cBi)
+    float4 *kf32 = nullptr;     // per k: (kx, ky, kz, kx^2 + ky^2), (cAr, cAi, cBr, cBi)
     double *fpart = nullptr;    // force-pass partials [ksplit][blocks * kBlock][4]
     // real space
     int *cell = nullptr, *slot = nullptr, *count = nullptr, *start = nullptr, *tmp = nullptr;
@@ -197,7 +197,7 @@ hipError_t launch_prep(rbe2d_ctx *h, const double *pos, const double *q, hipStre
 hipError_t launch_kcoef_sf(rbe2d_ctx *h, hipStream_t s);
 hipError_t launch_kforce(rbe2d_ctx *h, const double *pos, const double *q, double *F, double *dEdq,
                          uint32_t flags, bool accumulate, bool want_pot, bool add_real, const double *gE,
-                         hipStream_t s);
+                         hipStream_t s, double *var = nullptr);
 hipError_t launch_real(rbe2d_ctx *h, const double *pos, const double *q, bool want_dg, hipStream_t s);
 hipError_t launch_cells(rbe2d_ctx *h, const double *pos, const double *q, hipStream_t s);
 hipError_t launch_pairs(rbe2d_ctx *h, bool want_dg, hipStream_t s);

@@ -25,7 +25,7 @@ EXPORTS = ("rbe2d_create", "rbe2d_destroy", "rbe2d_query", "rbe2d_draw_kset", "r
            "rbe2d_energy_backward", "rbe2d_md_run", "rbe2d_profile_enable", "rbe2d_profile_read",
            "rbe2d_check", "rbe2d_last_error", "rbe2d_batch_create", "rbe2d_query_system",
            "rbe2d_batch_forces", "rbe2d_batch_md_run", "rbe2d_autotune", "rbe2d_short_forces",
-           "rbe2d_md_run_ex")
+           "rbe2d_md_run_ex", "rbe2d_suggest_params", "rbe2d_force_variance")
 PROF_SLOTS = ("prep", "sf_pass", "assemble", "cell_build", "real_pairs", "force_scatter", "energy",
               "integrator", "ksample", "short_range")
 
@@ -92,6 +92,9 @@ def lib():
         L.rbe2d_short_forces.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(MdParams), _vp]
         L.rbe2d_md_run_ex.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_double, ctypes.POINTER(MdParams),
                                       ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _vp]
+        L.rbe2d_suggest_params.argtypes = [ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                           ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.POINTER(Params)]
+        L.rbe2d_force_variance.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
         L.rbe2d_profile_enable.argtypes = [_vp, ctypes.c_int32]
         L.rbe2d_profile_read.argtypes = [_vp, _vp, _vp, ctypes.c_int32]
         L.rbe2d_check.argtypes = [_vp, _vp]
@@ -121,6 +124,18 @@ def draw_kset(params: Params, seed: int, stream_id: int = 0) -> np.ndarray:
     if st != RBE2D_OK:
         raise RBE2DError(st, lib().rbe2d_last_error(None).decode())
     return out
+
+
+def suggest_params(N, Lx, Ly, H, gamma_top, gamma_bot, tol, P=100, precision="fp64", n_max=None):
+    """Slab keyword arguments (alpha, r_c, M, Lz_ext, eps_lz and the geometry)
+    chosen by the library for a tolerance; see rbe2d_suggest_params."""
+    p = make_params(Lx, Ly, H, gamma_top, gamma_bot, 1.0, 1.0, P, 0, precision, N if n_max is None else n_max)
+    st = lib().rbe2d_suggest_params(int(N), float(Lx), float(Ly), float(H), float(gamma_top), float(gamma_bot),
+                                    float(tol), ctypes.byref(p))
+    if st != RBE2D_OK:
+        raise RBE2DError(st, lib().rbe2d_last_error(None).decode())
+    return dict(Lx=p.Lx, Ly=p.Ly, H=p.H, gamma_top=p.gamma_top, gamma_bot=p.gamma_bot, alpha=p.alpha, r_c=p.r_c,
+                P=p.P, M=p.M, Lz_ext=p.Lz_ext, eps_lz=p.eps_lz)
 
 
 def _stream():
@@ -267,6 +282,20 @@ class Slab:
             _dptr(F, torch.float64, (N, 3), "F"), float(dt), ctypes.byref(md), ctypes.c_uint64(seed),
             int(step0), int(n_steps), int(bool(use_graph)), _stream()))
 
+    def _variance(self, off, pos, q):
+        import torch
+        N = int(off[-1])
+        var = torch.empty(N, dtype=torch.float64, device=pos.device)
+        self._ok(lib().rbe2d_force_variance(
+            self._h, ctypes.c_void_p(off.ctypes.data), _dptr(pos, torch.float64, (N, 3), "pos"),
+            _dptr(q, torch.float64, (N,), "q"), _dptr(var, torch.float64, (N,), "var"), _stream()))
+        return var
+
+    def force_variance(self, pos, q):
+        """Per-particle estimate of the variance of the k-space force (Theorem 2.2)
+        from the current k-set."""
+        return self._variance(self._offsets_for(int(q.shape[0])), pos, q)
+
     def short_forces(self, pos, q, md, F=None, want_energy=False):
         """Adds the short-range forces of md (MdParams) to F (new zeros if None);
         with want_energy also returns {E_ion_ion, E_wall} (device (1, 2))."""
@@ -381,6 +410,9 @@ class BatchedSlab(Slab):
 
     def short_forces(self, offsets, pos, q, md, F=None, want_energy=False):
         return self._short(self._off(offsets), pos, q, F, want_energy, md)
+
+    def force_variance(self, offsets, pos, q):
+        return self._variance(self._off(offsets), pos, q)
 
     def md_run_ex(self, offsets, pos, vel, q, F, dt, md, seed, step0, n_steps, use_graph=False):
         self._md_ex(self._off(offsets), pos, vel, q, F, dt, md, seed, step0, n_steps, use_graph)

@@ -69,3 +69,28 @@ def _create(R, p):
     if st != 0:
         raise R.RBE2DError(st, R.lib().rbe2d_last_error(None).decode())
     R.lib().rbe2d_destroy(h)
+
+
+@pytest.mark.parametrize("args", [
+    (1_000_000, 800.0, 800.0, 40.0, 0.95, -0.95, 1e-5),
+    (10_000, 50.0, 50.0, 10.0, 0.9, 0.9, 1e-5),
+    (10, 10.0, 10.0, 5.0, 0.0, 0.0, 1e-5),
+    (500, 20.0, 20.0, 5.0, 0.0, 0.7, 1e-6),
+    (3000, 30.0, 30.0, 30.0, -1.0, 1.0, 1e-4),
+])
+def test_suggest_params_matches_oracle(R, orc, args):
+    """The library's host-side parameter selection against the oracle's."""
+    got = R.suggest_params(*args)
+    ref = orc.suggest_params(*args)
+    assert got["M"] == ref["M"]
+    for k, r in (("alpha", "alpha"), ("r_c", "r_c"), ("Lz_ext", "Lz")):
+        assert abs(got[k] - ref[r]) <= 1e-12 * abs(ref[r]), (k, got[k], ref[r])
+    assert got["eps_lz"] == args[-1]
+
+
+def test_suggest_params_rejects_bad_input(R):
+    for bad in ((0, 1.0, 1.0, 1.0, 0.0, 0.0, 1e-5), (10, 1.0, 1.0, 1.0, 0.0, 0.0, 1.5),
+                (10, 1.0, 1.0, 1.0, 1.2, 0.0, 1e-5), (10, -1.0, 1.0, 1.0, 0.0, 0.0, 1e-5)):
+        with pytest.raises(R.RBE2DError) as ei:
+            R.suggest_params(*bad)
+        assert ei.value.status == R.RBE2D_E_INVAL

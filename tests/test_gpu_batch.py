@@ -292,3 +292,33 @@ def test_autotune_batch_then_graph(torch, R, orc):
         runs.append([t.cpu().numpy() for t in (P2, V2, F2)])
     for x, y in zip(runs[0], runs[1]):
         assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("fp32", 1e-5)])
+def test_force_variance_matches_oracle(torch, R, orc, precision, tol):
+    """The per-particle variance estimate of the k-space force (Theorem 2.2)
+    against the oracle's estimate from the same batch."""
+    ws = [MIXED[0], MIXED[4], MIXED[1]]
+    pos, q, counts = batch_inputs(ws)
+    b = make_batch(R, ws, precision)
+    off = b.offsets(counts)
+    kset = b.draw_kset(13, 2)
+    b.set_kset(kset)
+    var = b.force_variance(off, to_dev(torch, pos), to_dev(torch, q)).cpu().numpy()
+    b.check()
+    for r, w in enumerate(ws):
+        if not w.N:
+            continue
+        ref = orc.force_variance_estimate(oracle_slab(orc, w, b.Lz_ext[r]), pos[off[r]:off[r + 1]],
+                                          q[off[r]:off[r + 1]], kset[r])
+        assert (ref > 0).all()
+        assert rel_rms(var[off[r]:off[r + 1]], ref) <= tol
+
+
+def test_force_variance_single_batch_of_one_k(torch, R):
+    w = MIXED[0]
+    pos, q = inputs.sample(w)
+    s = R.Slab(**w.slab_kwargs(P=1), precision="fp64", n_max=w.N)
+    s.set_kset(s.draw_kset(1, 0))
+    var = s.force_variance(to_dev(torch, pos), to_dev(torch, q)).cpu().numpy()
+    assert np.array_equal(var, np.zeros(w.N))
