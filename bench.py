@@ -72,6 +72,9 @@ def measured_traffic(kernel):
         return None
 
 
+SIDE_STREAM = ("prep", "sf_pass", "assemble")
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -348,7 +351,13 @@ def main():
 
     # per-kernel breakdown and the roofline of the dominant kernel
     kern = {k: {"ms_per_launch": (t / n if n else None), "launches": n} for k, (t, n) in prof.items()}
-    dom = max(prof, key=lambda k: prof[k][0])
+    # the k-space chain runs on a second stream, overlapped with the cell list
+    # and the pair kernel: its event durations include the time it shares the
+    # chip, so the dominant kernel is taken among the caller-stream kernels
+    for k in SIDE_STREAM:
+        if k in kern:
+            kern[k]["overlapped"] = True
+    dom = max((k for k in prof if k not in SIDE_STREAM), key=lambda k: prof[k][0])
     t_dom = prof[dom][0] / max(prof[dom][1], 1) * 1e-3
     NP = w.N * w.P
     pairs_real = expected_real_pairs(w)
@@ -365,7 +374,8 @@ def main():
         ach = work / t_dom / 1e12
         peak = VALU_LANE_SLOTS / 1e12
         roof = {"bound": "alu", "kernel": dom, "achieved": round(ach, 3), "peak": round(peak, 3),
-                "unit": "Tlane-slot/s", "frac": round(ach / peak, 4), "traffic": measured_traffic(dom)}
+                "unit": "Tlane-slot/s", "frac": round(ach / peak, 4), "traffic": measured_traffic(dom),
+                "concurrent_with": list(SIDE_STREAM) if dom == "real_pairs" else []}
     for k, slots, units in (("sf_pass", SLOTS_SF, NP), ("force_scatter", SLOTS_FORCE, NP),
                             ("real_pairs", SLOTS_REAL, pairs_real)):
         t, n = prof[k]

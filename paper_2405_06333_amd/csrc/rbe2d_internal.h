@@ -173,6 +173,10 @@ struct rbe2d_ctx {
     std::vector<void *> allocs;
     int32_t *kstage = nullptr;       // pinned staging of host k-set uploads
     hipEvent_t kev = nullptr;        // completion of the last upload from kstage
+    // the k-space chain runs on a second stream beside the real-space chain
+    // (default priority), forked from and joined back to the caller's stream
+    hipStream_t side = nullptr;
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
     bool kev_pending = false;
     // launch parameters: tuned for one particle layout by rbe2d_autotune, else
     // heuristic; force_* override both while the tuner times candidates
