@@ -72,7 +72,7 @@ def measured_traffic(kernel):
         return None
 
 
-SIDE_STREAM = ("prep", "sf_pass", "assemble")
+SIDE_STREAM = ("prep", "sf_pass", "assemble", "force_scatter")
 
 
 def parse():
@@ -351,9 +351,10 @@ def main():
 
     # per-kernel breakdown and the roofline of the dominant kernel
     kern = {k: {"ms_per_launch": (t / n if n else None), "launches": n} for k, (t, n) in prof.items()}
-    # the k-space chain runs on a second stream, overlapped with the cell list
-    # and the pair kernel: its event durations include the time it shares the
-    # chip, so the dominant kernel is taken among the caller-stream kernels
+    # the k-space chain (with its force scatter) runs on a second stream,
+    # overlapped with the cell list and the pair kernel: its event durations
+    # include the time it shares the chip, so the dominant kernel is taken
+    # among the caller-stream kernels
     for k in SIDE_STREAM:
         if k in kern:
             kern[k]["overlapped"] = True

@@ -324,9 +324,10 @@ rbe2d_status rbe2d_autotune(rbe2d_handle h, const int64_t *offsets, const double
  * class launched more than n times between reads keeps its first n).
  * Classes: 0 prep, 1 structure-factor pass, 2 per-k reduce/assemble,
  * 3 cell-list build, 4 real-space pairs, 5 force scatter, 6 energies,
- * 7 integrator, 8 k-sampler, 9 short-range forces.  Not to be used while a
- * graph is captured. */
-enum { RBE2D_PROF_SLOTS = 10 };
+ * 7 integrator, 8 k-sampler, 9 short-range forces, 10 real-space add (and
+ * the fused closing half kick of MD steps).  Not to be used while a graph is
+ * captured. */
+enum { RBE2D_PROF_SLOTS = 11 };
 rbe2d_status rbe2d_profile_enable(rbe2d_handle h, int32_t n_events);
 rbe2d_status rbe2d_profile_read(rbe2d_handle h, double *ms, int64_t *launches, int32_t n_slots);
 

@@ -496,6 +496,36 @@ rbe2d_status run_common(rbe2d_ctx *h, const double *pos, const double *q, uint32
     return RBE2D_OK;
 }
 
+// Forces of `parts` into F (added to F with `accumulate`).  With real space
+// and k-space/IBC both requested, the whole k-space chain including its force
+// scatter runs on the side stream (writing F) while the cell list and pair
+// kernel run on `s`; after the join one pass adds the real-space forces and,
+// when vel is set, applies the closing half kick v += dt/2 F of an MD step.
+rbe2d_status compute_forces(rbe2d_ctx *h, const double *pos, const double *q, double *F, uint32_t parts,
+                            bool accumulate, double *vel, double dt, hipStream_t s) {
+    const bool kside = (parts & (RBE2D_KSPACE | RBE2D_IBC)) != 0;
+    if (kside && (parts & RBE2D_REAL) && h->n_total > 0) {
+        hipStream_t ks = h->side;
+        RBE2D_TRY(h, hipEventRecord(h->fork_ev, s), "fork event");
+        RBE2D_TRY(h, hipStreamWaitEvent(ks, h->fork_ev, 0), "fork wait");
+        RBE2D_TRY(h, launch_prep(h, pos, q, ks), "prep launch");
+        if (parts & RBE2D_KSPACE) RBE2D_TRY(h, launch_kcoef_sf(h, ks), "structure-factor launch");
+        RBE2D_TRY(h, launch_kforce(h, pos, q, F, nullptr, parts & ~(uint32_t)RBE2D_REAL, accumulate, false, false,
+                                   nullptr, ks), "force launch");
+        RBE2D_TRY(h, launch_real(h, pos, q, false, s), "real-space launch");
+        RBE2D_TRY(h, hipEventRecord(h->join_ev, ks), "join event");
+        RBE2D_TRY(h, hipStreamWaitEvent(s, h->join_ev, 0), "join wait");
+        RBE2D_TRY(h, launch_add_real(h, F, vel, 0.5 * dt, s), "real-space add");
+        return RBE2D_OK;
+    }
+    rbe2d_status st = run_common(h, pos, q, parts, false, s);
+    if (st) return st;
+    RBE2D_TRY(h, launch_kforce(h, pos, q, F, nullptr, parts, accumulate, false, (parts & RBE2D_REAL) != 0, nullptr,
+                               s), "force launch");
+    if (vel) RBE2D_TRY(h, launch_md_kick(h, vel, F, dt, s), "md kick");
+    return RBE2D_OK;
+}
+
 rbe2d_status run_forces(rbe2d_ctx *h, const double *pos, const double *q, double *F, double *energy,
                         uint32_t flags, hipStream_t s) {
     if (flags & ~(uint32_t)(RBE2D_ALL | RBE2D_ACCUMULATE)) return fail(h, RBE2D_E_INVAL, "unknown flags");
@@ -503,10 +533,8 @@ rbe2d_status run_forces(rbe2d_ctx *h, const double *pos, const double *q, double
     if (st) return st;
     if (h->n_total > 0 && !F) return fail(h, RBE2D_E_INVAL, "F is NULL");
     const uint32_t parts = flags & RBE2D_ALL;
-    st = run_common(h, pos, q, parts, false, s);
+    st = compute_forces(h, pos, q, F, parts, (flags & RBE2D_ACCUMULATE) != 0, nullptr, 0.0, s);
     if (st) return st;
-    RBE2D_TRY(h, launch_kforce(h, pos, q, F, nullptr, parts, (flags & RBE2D_ACCUMULATE) != 0, false,
-                               (parts & RBE2D_REAL) != 0, nullptr, s), "force launch");
     if (energy) RBE2D_TRY(h, launch_energy(h, energy, parts, nullptr, nullptr, s), "energy launch");
     return RBE2D_OK;
 }
@@ -553,11 +581,15 @@ rbe2d_status md_step(rbe2d_ctx *h, double *pos, double *vel, const double *q, do
     else
         RBE2D_TRY(h, launch_md_kick_drift(h, pos, vel, F, dt, zlo, zhi_from_top, s), "md drift");
     RBE2D_TRY(h, launch_sample(h, seed, sbase, dev_step ? h->w.step : nullptr, s), "md sample");
-    rbe2d_status st = run_common(h, pos, q, RBE2D_ALL, false, s);
+    const bool shortr = mx && mx->short_on();
+    // the closing half kick is fused into the force pass unless short-range
+    // forces still have to be added
+    rbe2d_status st = compute_forces(h, pos, q, F, RBE2D_ALL, false, shortr ? nullptr : vel, dt, s);
     if (st) return st;
-    RBE2D_TRY(h, launch_kforce(h, pos, q, F, nullptr, RBE2D_ALL, false, false, true, nullptr, s), "md force");
-    if (mx && mx->short_on()) RBE2D_TRY(h, launch_short(h, *mx, F, nullptr, s), "md short-range");
-    RBE2D_TRY(h, launch_md_kick(h, vel, F, dt, s), "md kick");
+    if (shortr) {
+        RBE2D_TRY(h, launch_short(h, *mx, F, nullptr, s), "md short-range");
+        RBE2D_TRY(h, launch_md_kick(h, vel, F, dt, s), "md kick");
+    }
     if (dev_step) RBE2D_TRY(h, launch_step_inc(h, s), "md step counter");
     return RBE2D_OK;
 }

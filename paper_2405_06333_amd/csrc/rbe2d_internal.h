@@ -205,6 +205,7 @@ hipError_t launch_kforce(rbe2d_ctx *h, const double *pos, const double *q, doubl
 hipError_t launch_real(rbe2d_ctx *h, const double *pos, const double *q, bool want_dg, hipStream_t s);
 hipError_t launch_cells(rbe2d_ctx *h, const double *pos, const double *q, hipStream_t s);
 hipError_t launch_pairs(rbe2d_ctx *h, bool want_dg, hipStream_t s);
+hipError_t launch_add_real(rbe2d_ctx *h, double *F, double *vel, double half_dt, hipStream_t s);
 hipError_t launch_short(rbe2d_ctx *h, const MdExtra &mx, double *F, double *energy, hipStream_t s);
 hipError_t launch_md_kick_drift_langevin(rbe2d_ctx *h, double *pos, double *vel, const double *F, double dt,
                                          const MdExtra &mx, uint64_t seed, uint64_t stream_base,

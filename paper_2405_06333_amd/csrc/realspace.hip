@@ -679,6 +679,30 @@ hipError_t launch_pairs(rbe2d_ctx *h, bool want_dg, hipStream_t s) {
     return hipGetLastError();
 }
 
+// F += F_real (the pair kernel's per-particle output), and in MD steps the
+// closing half kick v += dt/2 F with the completed force
+__global__ __launch_bounds__(kBlock) void k_add_real(int64_t n, const double4 *freal, double *F, double *vel,
+                                                     double half_dt) {
+    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (g >= n) return;
+    const double4 fr = freal[g];
+    const double add[3] = {fr.x, fr.y, fr.z};
+    for (int c = 0; c < 3; c++) {
+        const double f = F[3 * g + c] + add[c];
+        F[3 * g + c] = f;
+        if (vel) vel[3 * g + c] = fma(half_dt, f, vel[3 * g + c]);
+    }
+}
+
+hipError_t launch_add_real(rbe2d_ctx *h, double *F, double *vel, double half_dt, hipStream_t s) {
+    if (h->n_total == 0) return hipSuccess;
+    prof_begin(h, 10, s);
+    hipLaunchKernelGGL(k_add_real, dim3((unsigned)((h->n_total + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                       h->n_total, h->w.freal, F, vel, half_dt);
+    prof_end(h, 10, s);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Short-range forces of the MD (purely repulsive shifted-truncated LJ between
 // ions and against the walls), on the cell list of the pair kernel.  One

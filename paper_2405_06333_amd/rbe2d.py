@@ -27,7 +27,7 @@ EXPORTS = ("rbe2d_create", "rbe2d_destroy", "rbe2d_query", "rbe2d_draw_kset", "r
            "rbe2d_batch_forces", "rbe2d_batch_md_run", "rbe2d_autotune", "rbe2d_short_forces",
            "rbe2d_md_run_ex", "rbe2d_suggest_params", "rbe2d_force_variance")
 PROF_SLOTS = ("prep", "sf_pass", "assemble", "cell_build", "real_pairs", "force_scatter", "energy",
-              "integrator", "ksample", "short_range")
+              "integrator", "ksample", "short_range", "add_real")
 
 
 class RBE2DError(RuntimeError):
