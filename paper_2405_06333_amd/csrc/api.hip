@@ -347,8 +347,10 @@ rbe2d_status create_handle(int n, const rbe2d_params *ps, bool batch, rbe2d_hand
     const int64_t nc = std::max<int64_t>(n_cap, 1);
     A(&w.cell, nc); A(&w.slot, nc); A(&w.tmp, nc);
     A(&w.count, cells); A(&w.start, cells + 1); A(&w.scanbuf, cells / 1024 + 2);
-    A(&w.sorted, h->cap_sorted); A(&w.sidx, h->cap_sorted); A(&w.scell, h->cap_sorted);
-    if (h->precision == RBE2D_PREC_FP32_PHASE) A(&w.src16, h->cap_sorted);
+    // source records get one wave of padding: the pair kernel reads the first
+    // record of an empty run, which may start at the end of the array
+    A(&w.sorted, h->cap_sorted + kWave); A(&w.sidx, h->cap_sorted); A(&w.scell, h->cap_sorted);
+    if (h->precision == RBE2D_PREC_FP32_PHASE) A(&w.src16, h->cap_sorted + kWave);
     A(&w.freal, nc); A(&w.dgreal, nc);
     A(&w.rpart, 3 * (h->cap_sorted / kWave));
     // the split is only used when there are too few targets to fill the chip

@@ -456,11 +456,12 @@ __global__ __launch_bounds__(kBlock) RBE2D_REAL_OCC void k_real(RealArgs a) {
                 // int32 wrap is the minimum image in x and y), one rounding
                 // each to FP32; exact FP64 geometry for pairs within `near`
                 const uint4 *p16 = a.src16 + jb;
+                const int lm = max(len - 1, 0);
                 for (int m0 = 0; m0 < maxlen; m0 += U) {
                     if (qu.full()) qu.drain(alpha, c2a);
                     uint4 sv[U];
 #pragma unroll
-                    for (int k = 0; k < U; k++) sv[k] = m0 + k < len ? p16[m0 + k] : make_uint4(0, 0, 0, 0);
+                    for (int k = 0; k < U; k++) sv[k] = p16[min(m0 + k, lm)];   // past the run: rejected below
 #pragma unroll
                     for (int k = 0; k < U; k++) {
                         const int m = m0 + k;
@@ -468,24 +469,28 @@ __global__ __launch_bounds__(kBlock) RBE2D_REAL_OCC void k_real(RealArgs a) {
                         float dy = (float)(int)(ytf - sv[k].y) * d.uy;
                         float dz = (float)(int)(tzf - sv[k].z) * d.uz;
                         const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                        const bool acc = m < len && r2 < d.rc2f && m != self;
+                        bool acc = m < len && r2 < d.rc2f;
                         if (acc && r2 < d.near2f) {
                             const double4 s64 = p[m];
                             double ex = xt - s64.x, ey = yt - s64.y;
                             ex -= d.Lx * rint(ex / d.Lx);
                             ey -= d.Ly * rint(ey / d.Ly);
-                            dx = (float)ex; dy = (float)ey; dz = (float)(tz - s64.z);
+                            const double ez = tz - s64.z;
+                            // zero displacement only for the target itself (direct family)
+                            acc = ex != 0.0 || ey != 0.0 || ez != 0.0;
+                            dx = (float)ex; dy = (float)ey; dz = (float)ez;
                         }
                         qu.push(acc, dx, dy, dz, __uint_as_float(sv[k].w));
                     }
                 }
                 return;
             }
+            const int lm = max(len - 1, 0);
             for (int m0 = 0; m0 < maxlen; m0 += U) {
                 if (qu.full()) qu.drain(alpha, c2a);
                 double4 sv[U];
 #pragma unroll
-                for (int k = 0; k < U; k++) sv[k] = m0 + k < len ? p[m0 + k] : make_double4(0, 0, 0, 0);
+                for (int k = 0; k < U; k++) sv[k] = p[min(m0 + k, lm)];   // past the run: rejected below
 #pragma unroll
                 for (int k = 0; k < U; k++) {
                     const int m = m0 + k;
