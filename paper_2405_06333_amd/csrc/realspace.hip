@@ -153,10 +153,14 @@ __global__ __launch_bounds__(kBlock) void k_cell_scatter(CellArgs a) {
 }
 
 // position within the cell = number of members with a smaller caller index;
-// sorted positions are padded per system to whole waves
+// sorted positions are padded per system to whole waves.  One thread per
+// slot j of the unordered cell lists (tmp): the particle it holds is
+// gathered, and its record is written within the same cell, so the stores of
+// a wave stay within a few neighbouring cells.
 __global__ __launch_bounds__(kBlock) void k_cell_rank(CellArgs a) {
-    const int g = blockIdx.x * kBlock + threadIdx.x;
-    if (g >= a.n_total) return;
+    const int j = blockIdx.x * kBlock + threadIdx.x;
+    if (j >= a.n_total) return;
+    const int g = a.tmp[j];
     const int r = find_sys(a.lay.off, a.n_sys, g);
     const SysDesc &d = a.sys[r];
     const int c = a.cell[g];
