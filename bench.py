@@ -124,6 +124,13 @@ def run_md(R, torch, w, precision, steps, warmup, profile, use_graph=False, auto
     slab.sample_kset(w.seed, 0)
     tuned = slab.autotune(P_, Q_) if autotune else None
     slab.forces(P_, Q_, out=F_)
+    err = None
+    if profile:
+        # stochastic error of the k-space force at this P (Theorem 2.2) on the
+        # starting configuration: rms of the per-particle variance estimate
+        var = slab.force_variance(P_, Q_)
+        err = {"kspace_force_sigma_rms": float(var.mean().sqrt().item()),
+               "total_force_rms": float((F_ * F_).sum(dim=1).mean().sqrt().item())}
     zlo, zhi = w.margin, w.H - w.margin
     step = 1
     slab.md_run(P_, V_, Q_, F_, w.dt, zlo, zhi, w.seed, step, warmup, use_graph=use_graph)
@@ -142,11 +149,7 @@ def run_md(R, torch, w, precision, steps, warmup, profile, use_graph=False, auto
     slab.check()
     finite = bool(torch.isfinite(F_).all().item() and torch.isfinite(P_).all().item())
     if profile:
-        # stochastic error of the k-space force at this P (Theorem 2.2), on the
-        # final configuration and k-set: rms of the per-particle estimate
-        var = slab.force_variance(P_, Q_)
-        tuned = {"launch_params": tuned, "kspace_force_sigma_rms": float(var.mean().sqrt().item()),
-                 "total_force_rms": float((F_ * F_).sum(dim=1).mean().sqrt().item())}
+        tuned = dict(err, launch_params=tuned)
     return (t1 - t0), prof, finite, tuned
 
 
