@@ -161,8 +161,12 @@ rbe2d_status rbe2d_energy(rbe2d_handle h, int64_t N, const double *pos, const do
 
 /* Adjoint of rbe2d_energy at the current k-set: given gE = dL/dE (device
  * scalar), writes dL/dr (device N x 3), dL/dq (device N) and
- * dL/dgamma (device 2: top, bot); any output may be NULL.  rho(k) is
- * recomputed, not stored.  dE/dq_i = phi_i, the electrostatic potential at
+ * dL/dgamma (device 2: top, bot); any output may be NULL.  Nothing of size
+ * N x P is stored: when the call directly follows rbe2d_energy on the same
+ * handle, pos, q and N (same pointers, contents unchanged), with no other
+ * call on the handle in between, the P per-k values (rho, A, B) and the
+ * per-particle real-space results that call left are reused; otherwise
+ * rho(k) and the real-space sums are recomputed.  dE/dq_i = phi_i, the electrostatic potential at
  * r_i of all other charges, all images (own images included) and the
  * k-space/IBC/self terms, taken literally (no neutralising background). */
 rbe2d_status rbe2d_energy_backward(rbe2d_handle h, int64_t N, const double *pos,

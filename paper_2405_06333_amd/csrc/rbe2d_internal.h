@@ -190,6 +190,15 @@ struct rbe2d_ctx {
     hipGraphExec_t md_exec = nullptr;
     hipGraph_t md_graph = nullptr;
     std::vector<uint64_t> md_key;    // arguments and layout the graph was captured for
+    // every call that changes the workspaces bumps `calls`; rbe2d_energy
+    // records the state it left, which rbe2d_energy_backward reuses when
+    // nothing ran in between on the same inputs
+    uint64_t calls = 0;
+    struct {
+        uint64_t at = ~0ull;
+        const double *pos = nullptr, *q = nullptr;
+        int64_t n = -1;
+    } fwd;
     rbe2d::Profiler prof;
     std::string err;
 };

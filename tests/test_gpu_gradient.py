@@ -181,3 +181,37 @@ def test_autograd_function(torch, R):
     G_bad = torch.tensor([w.gamma_top, 0.5], dtype=torch.float64, device="cuda", requires_grad=True)
     with pytest.raises(ValueError):
         Fn.apply(P_, Q_, G_bad, slab)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_backward_reuses_forward_state(torch, R, precision):
+    """A backward right after rbe2d_energy on the same inputs reuses what the
+    forward left; any other call in between, or other inputs, forces the
+    recompute.  Both give the same gradients."""
+    w = inputs.small_random(41, 900, L=15.0, H=5.0, gamma_top=0.8, gamma_bot=-0.6, alpha=0.8, r_c=4.5,
+                            P=40, M=5)
+    pos, q = inputs.sample(w)
+    pos2 = pos.copy()
+    pos2[:, 0] = np.mod(pos2[:, 0] + 0.37, w.Lx)
+    slab = gpu_slab(R, w, precision)
+    slab.set_kset(slab.draw_kset(6))
+    P_, Q_, P2 = to_dev(torch, pos), to_dev(torch, q), to_dev(torch, pos2)
+    g = torch.tensor(1.3, dtype=torch.float64, device="cuda")
+
+    def grads():
+        return [t.cpu().numpy() for t in slab.energy_backward(P_, Q_, g)]
+
+    fresh = grads()                                  # no forward before it
+    slab.energy(P_, Q_)
+    reused = grads()                                 # directly after the forward
+    slab.energy(P_, Q_)
+    slab.forces(P2, Q_)                              # another call in between
+    between = grads()
+    slab.energy(P2, Q_)
+    other = grads()                                  # forward on other positions
+    slab.check()
+    # equal up to the order of the kernels' atomic accumulations
+    tol = 1e-12 if precision == "fp64" else 1e-6
+    for res in (reused, between, other):
+        for a, b in zip(fresh, res):
+            assert rel_rms(b, a) <= tol
