@@ -11,6 +11,11 @@
 
 #include "rbe2d_internal.h"
 
+// cells per r_c along y of the pair kernel's cell grid
+#ifndef RBE2D_REACH_Y
+#define RBE2D_REACH_Y 6
+#endif
+
 using namespace rbe2d;
 
 namespace {
@@ -196,11 +201,14 @@ rbe2d_status setup_system(const rbe2d_params *pin, SysHost &sh) {
     if (p.precision == RBE2D_PREC_FP32_PHASE && bits > 20)
         return fail(nullptr, RBE2D_E_INVAL, "k-range too wide for FP32 phases (alpha L too large)");
 
-    // cell grid: cells >= r_c / reach in x, y and z (searched +-reach
-    // columns), coarsened if there would be too many cells
+    // cell grid: cells >= r_c / reach in x and z (searched +-reach columns
+    // and layers) and >= r_c / reach_y along y, where the pair kernel scans
+    // contiguous runs of cells (finer cells trim the runs' ends); coarsened
+    // if there would be too many cells
     d.reach = 2;
+    d.reach_y = RBE2D_REACH_Y;
     int ncx = std::max(1, (int)std::floor(d.reach * p.Lx / p.r_c));
-    int ncy = std::max(1, (int)std::floor(d.reach * p.Ly / p.r_c));
+    int ncy = std::max(1, (int)std::floor(d.reach_y * p.Ly / p.r_c));
     int ncz = std::max(1, (int)std::floor(d.reach * p.H / p.r_c));
     const int64_t cell_cap = std::max<int64_t>(2 * p.n_max, 4096);
     while ((int64_t)ncx * ncy * ncz > cell_cap && (ncx > 5 || ncy > 5 || ncz > 1)) {
@@ -216,13 +224,21 @@ rbe2d_status setup_system(const rbe2d_params *pin, SysHost &sh) {
     const double two32 = 4294967296.0;
     const double zspan = 2.0 * p.H + 4.0 * p.r_c;
     d.zoff = 0.5 * p.H + 2.0 * p.r_c;
-    d.fxs = two32 / p.Lx; d.fys = two32 / p.Ly; d.fzs = two32 / zspan;
-    d.ux = (float)(p.Lx / two32); d.uy = (float)(p.Ly / two32); d.uz = (float)(zspan / two32);
+    // candidates lie within r_c + hz of the target in z
+    d.iso = p.Lx == p.Ly && 2.0 * (p.r_c + d.hz) * (1.0 + 1e-6) < p.Lx;
+    d.fxs = two32 / p.Lx; d.fys = two32 / p.Ly; d.fzs = d.iso ? d.fxs : two32 / zspan;
+    d.ux = (float)(p.Lx / two32); d.uy = (float)(p.Ly / two32);
+    d.uz = d.iso ? d.ux : (float)(zspan / two32);
     d.rc2f = (float)(p.r_c * p.r_c);
     // below `near` the quantisation of the positions (one unit) would exceed
     // ~2^-22 of the distance: such pairs take exact FP64 displacements
-    const double near = std::max(std::max(p.Lx, p.Ly), zspan) / two32 * 4194304.0;
+    const double unit = d.iso ? p.Lx / two32 : std::max(std::max(p.Lx, p.Ly), zspan) / two32;
+    const double near = unit * 4194304.0;
     d.near2f = (float)(near * near);
+    d.ud = p.Lx / two32;
+    d.u2 = (float)(d.ud * d.ud);
+    d.rc2q = (float)(p.r_c * p.r_c * d.fxs * d.fxs);
+    d.near2q = (float)(near * near * d.fxs * d.fxs);
     return RBE2D_OK;
 }
 
@@ -313,6 +329,8 @@ rbe2d_status create_handle(int n, const rbe2d_params *ps, bool batch, rbe2d_hand
         return fail(nullptr, RBE2D_E_INVAL, "total particle or cell capacity exceeds 2^30");
     }
     h->precision = h->sys[0].p.precision;
+    h->iso = true;
+    for (int r = 0; r < n; r++) h->iso = h->iso && h->sys[r].d.iso;
     h->P = h->sys[0].p.P;
     h->P_pad = (h->P + kPPad - 1) / kPPad * kPPad;
     h->n_cap = n_cap;

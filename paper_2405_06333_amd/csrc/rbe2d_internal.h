@@ -54,13 +54,19 @@ struct SysDesc {
     double cfac;                               // 2 pi S pref / (V P)
     double scale_h;                            // 2^fh_bits (FP32 phase split)
     double hx, hy, hz, inv_hy, inv_hz;         // cell sizes
-    int ncx, ncy, ncz, reach, nfam, M, fh_bits, cbase;
+    int ncx, ncy, ncz, reach, reach_y, nfam, M, fh_bits, cbase;
     int nmax[3], cdf_off[3];                   // sampler tables in the shared CDF array
     // fixed-point source records of the FP32 pair kernel: x and y in units
     // of period / 2^32 (so an int32 difference is the minimum image), z + zoff
-    // in units of zspan / 2^32; pairs closer than `near` use FP64 geometry
+    // in units of zspan / 2^32; pairs closer than `near` use FP64 geometry.
+    // Isotropic frame (iso = 1): Lx = Ly and z takes the x unit too, which is
+    // exact for every candidate because |dz| < Lx / 2; the pair kernel then
+    // tests distances in units squared and scales only accepted pairs.
     double fxs, fys, fzs, zoff;                // scale factors 2^32 / (Lx, Ly, zspan)
     float ux, uy, uz, rc2f, near2f;            // units as floats, r_c^2, near^2
+    int iso;
+    float u2, rc2q, near2q;                    // iso: ux^2, r_c^2 / ux^2, near^2 / ux^2
+    double ud;                                 // iso: ux in FP64
 };
 
 // Per-k record written by the reduce/assemble kernel (FP64):
@@ -158,6 +164,7 @@ struct rbe2d_ctx {
     int64_t cap_particles = 0;       // padded k-space capacity (all systems)
     int64_t cap_sorted = 0;          // padded real-space capacity
     int total_cells = 0;
+    bool iso = false;                // every system has the isotropic fixed-point frame
     int64_t split_cap = 0;           // targets per split of the partial real-space outputs
     bool kset_valid = false;
     // current layout (host mirror); a layout is uploaded when it changes

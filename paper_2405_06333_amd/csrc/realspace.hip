@@ -240,28 +240,39 @@ __device__ __forceinline__ void pair_terms(double r2, double alpha, double c2a, 
 // FP32 kernel: a ring of Q entries per lane.  A round evaluates the oldest
 // entry of every lane that holds one; the FP32 sums of a drain (at most Q
 // pairs per lane) are folded into FP64.  Cheap routing (every result stays in
-// its lane) at the price of idle lanes in the rounds.
-template <int Q, int U>
+// its lane) at the price of idle lanes in the rounds.  The lane's read and
+// write positions are kept as byte offsets into the rings (slot-major, one
+// 16-byte entry per thread and slot).  ISO: entries hold displacements in
+// units of the isotropic fixed-point frame; r^2 and the force sums are
+// scaled when a pair is evaluated and when a drain is folded.
+template <int Q, int U, bool ISO>
 struct LaneRings {
     static constexpr int kRoundMin = RBE2D_ROUND_MIN;   // keep draining while this many lanes hold pairs
-    float4 (*ring)[kBlock];
-    int tid, head = 0, cnt = 0;
+    static constexpr int kSlot = kBlock * (int)sizeof(float4);
+    static constexpr int kMask = Q * kSlot - 1;         // Q * kSlot is a power of two
+    unsigned char *base;
+    int wofs, rofs, cnt = 0;
+    float u2;
+    double ud;
     float sx = 0, sy = 0, sz = 0, sp = 0;
     double gx = 0, gy = 0, gz = 0, gp = 0;
-    __device__ LaneRings(float4 (*r)[kBlock], int t) : ring(r), tid(t) {}
+    __device__ LaneRings(unsigned char *b, int t, float u2_, double ud_)
+        : base(b), wofs(t * (int)sizeof(float4)), rofs(t * (int)sizeof(float4)), u2(u2_), ud(ud_) {}
     __device__ void push(bool acc, float dx, float dy, float dz, float qs) {
         if (acc) {
-            ring[(head + cnt) & (Q - 1)][tid] = make_float4(dx, dy, dz, qs);
+            *reinterpret_cast<float4 *>(base + wofs) = make_float4(dx, dy, dz, qs);
+            wofs = (wofs + kSlot) & kMask;
             cnt++;
         }
     }
     __device__ bool full() const { return __ballot(cnt > Q - U) != 0; }
     __device__ void round(float alpha, float c2a) {
         if (cnt > 0) {
-            const float4 e = ring[head][tid];
-            head = (head + 1) & (Q - 1);
+            const float4 e = *reinterpret_cast<const float4 *>(base + rofs);
+            rofs = (rofs + kSlot) & kMask;
             cnt--;
-            const float r2 = e.x * e.x + e.y * e.y + e.z * e.z;
+            float r2 = e.x * e.x + e.y * e.y + e.z * e.z;
+            if (ISO) r2 *= u2;
             float ec, fs;
             pair_terms(r2, alpha, c2a, &ec, &fs);
             const float qf = e.w * fs;
@@ -269,7 +280,12 @@ struct LaneRings {
         }
     }
     __device__ void fold() {
-        gx += (double)sx; gy += (double)sy; gz += (double)sz; gp += (double)sp;
+        if (ISO) {
+            gx = fma((double)sx, ud, gx); gy = fma((double)sy, ud, gy); gz = fma((double)sz, ud, gz);
+        } else {
+            gx += (double)sx; gy += (double)sy; gz += (double)sz;
+        }
+        gp += (double)sp;
         sx = sy = sz = sp = 0;
     }
     // make room for U more pairs per lane
@@ -372,14 +388,19 @@ __device__ __forceinline__ int wave_min(int v) {
 // evaluates erfc/exp and the per-drain partial sums in FP32 and accumulates
 // the drains in FP64.  The order of every sum is fixed by the data, so the
 // results are bitwise reproducible.
-template <typename Queue> __device__ Queue make_queue(unsigned char *lds, int tid);
+template <typename Queue> __device__ Queue make_queue(unsigned char *lds, int tid, const SysDesc &d);
 template <>
-__device__ LaneRings<RBE2D_RING_Q, RBE2D_REAL_U32> make_queue<LaneRings<RBE2D_RING_Q, RBE2D_REAL_U32>>(
-    unsigned char *lds, int tid) {
-    return LaneRings<RBE2D_RING_Q, RBE2D_REAL_U32>(reinterpret_cast<float4(*)[kBlock]>(lds), tid);
+__device__ LaneRings<RBE2D_RING_Q, RBE2D_REAL_U32, false>
+make_queue<LaneRings<RBE2D_RING_Q, RBE2D_REAL_U32, false>>(unsigned char *lds, int tid, const SysDesc &d) {
+    return LaneRings<RBE2D_RING_Q, RBE2D_REAL_U32, false>(lds, tid, 1.0f, 1.0);
 }
 template <>
-__device__ WaveQueue<256, 2> make_queue<WaveQueue<256, 2>>(unsigned char *lds, int tid) {
+__device__ LaneRings<RBE2D_RING_Q, RBE2D_REAL_U32, true>
+make_queue<LaneRings<RBE2D_RING_Q, RBE2D_REAL_U32, true>>(unsigned char *lds, int tid, const SysDesc &d) {
+    return LaneRings<RBE2D_RING_Q, RBE2D_REAL_U32, true>(lds, tid, d.u2, d.ud);
+}
+template <>
+__device__ WaveQueue<256, 2> make_queue<WaveQueue<256, 2>>(unsigned char *lds, int tid, const SysDesc &) {
     constexpr int kQ = 256;
     const int wid = tid / kWave, lane = tid % kWave;
     double4 *ent = reinterpret_cast<double4 *>(lds) + wid * kQ;
@@ -388,14 +409,15 @@ __device__ WaveQueue<256, 2> make_queue<WaveQueue<256, 2>>(unsigned char *lds, i
     return WaveQueue<kQ, 2>(ent, own, acc, lane);
 }
 
-template <bool FP32, bool WANT_DG>
+template <bool FP32, bool WANT_DG, bool ISO>
 __global__ __launch_bounds__(kBlock) RBE2D_REAL_OCC void k_real(RealArgs a) {
+    static_assert(FP32 || !ISO, "the isotropic frame is a property of the fixed-point records");
     using T = typename RealTypes<FP32>::T;
     constexpr int U = RealTypes<FP32>::U;
     constexpr int NW = kBlock / kWave;
     constexpr int kRingQ = RBE2D_RING_Q;   // FP32: ring entries per lane
     constexpr int kWaveQ = 256;    // FP64: queue entries per wave
-    using Queue = typename std::conditional<FP32, LaneRings<kRingQ, U>, WaveQueue<kWaveQ, U>>::type;
+    using Queue = typename std::conditional<FP32, LaneRings<kRingQ, U, ISO>, WaveQueue<kWaveQ, U>>::type;
     constexpr size_t kLds = FP32 ? sizeof(float4) * kRingQ * kBlock
                                  : NW * (kWaveQ * (sizeof(double4) + 1) + 4 * kWave * sizeof(double));
     __shared__ __align__(16) unsigned char lds[kLds];
@@ -424,7 +446,7 @@ __global__ __launch_bounds__(kBlock) RBE2D_REAL_OCC void k_real(RealArgs a) {
     }
     const int cy = cid % d.ncy;
     const int cx = (cid / d.ncy) % d.ncx;
-    const bool allx = d.ncx < 2 * d.reach + 1, ally = d.ncy < 2 * d.reach + 1;
+    const bool allx = d.ncx < 2 * d.reach + 1, ally = d.ncy < 2 * d.reach_y + 1;
     const double yrel = me.y - cy * d.hy;           // y within the target's cell
     const double rcm2 = d.rc2 * (1.0 + 2e-9);       // culling bounds get a 1e-9 margin:
     const double rmarg = 1e-9 * d.rc;               // cells were assigned by division
@@ -447,7 +469,7 @@ __global__ __launch_bounds__(kBlock) RBE2D_REAL_OCC void k_real(RealArgs a) {
             lzhi = min(d.ncz - 1, (int)floor((tz + d.rc + rmarg) * d.inv_hz));
         }
         const int wzlo = wave_min(lzlo), wzhi = wave_max(lzhi);
-        Queue qu = make_queue<Queue>(lds, tid);
+        Queue qu = make_queue<Queue>(lds, tid, d);
         // scan one run of sources [jb, jb + len) for pairs within r_c.  The
         // trip count is the wave maximum, so drains always run with every
         // lane.  Loads are issued U at a time ahead of their use: the loop is
@@ -455,26 +477,32 @@ __global__ __launch_bounds__(kBlock) RBE2D_REAL_OCC void k_real(RealArgs a) {
         auto scan = [&](int jb, int len, double xt, double yt, int self) {
             const int maxlen = wave_max(len);
             const double4 *p = src + jb;
+            // U loads from min(m0, len - 1): past the run they stay within the
+            // padded arrays (jb + len - 1 + U - 1 < capacity + 64) and are rejected
+            const int lm = max(len - 1, 0);
             if constexpr (FP32) {
                 // fixed-point displacements: exact integer differences (the
                 // int32 wrap is the minimum image in x and y), one rounding
                 // each to FP32; exact FP64 geometry for pairs within `near`
                 const uint4 *p16 = a.src16 + jb;
-                const int lm = max(len - 1, 0);
+                const float rc2s = ISO ? d.rc2q : d.rc2f;
+                const float near2s = ISO ? d.near2q : d.near2f;
                 for (int m0 = 0; m0 < maxlen; m0 += U) {
                     if (qu.full()) qu.drain(alpha, c2a);
+                    const uint4 *pq = p16 + min(m0, lm);
                     uint4 sv[U];
 #pragma unroll
-                    for (int k = 0; k < U; k++) sv[k] = p16[min(m0 + k, lm)];   // past the run: rejected below
+                    for (int k = 0; k < U; k++) sv[k] = pq[k];
 #pragma unroll
                     for (int k = 0; k < U; k++) {
                         const int m = m0 + k;
-                        float dx = (float)(int)(xtf - sv[k].x) * d.ux;
-                        float dy = (float)(int)(ytf - sv[k].y) * d.uy;
-                        float dz = (float)(int)(tzf - sv[k].z) * d.uz;
+                        float dx = (float)(int)(xtf - sv[k].x);
+                        float dy = (float)(int)(ytf - sv[k].y);
+                        float dz = (float)(int)(tzf - sv[k].z);
+                        if (!ISO) { dx *= d.ux; dy *= d.uy; dz *= d.uz; }
                         const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                        bool acc = m < len && r2 < d.rc2f;
-                        if (acc && r2 < d.near2f) {
+                        bool acc = m < len && r2 < rc2s;
+                        if (acc && r2 < near2s) {
                             const double4 s64 = p[m];
                             double ex = xt - s64.x, ey = yt - s64.y;
                             ex -= d.Lx * rint(ex / d.Lx);
@@ -482,19 +510,20 @@ __global__ __launch_bounds__(kBlock) RBE2D_REAL_OCC void k_real(RealArgs a) {
                             const double ez = tz - s64.z;
                             // zero displacement only for the target itself (direct family)
                             acc = ex != 0.0 || ey != 0.0 || ez != 0.0;
-                            dx = (float)ex; dy = (float)ey; dz = (float)ez;
+                            if (ISO) { ex *= d.fxs; ey *= d.fxs; }
+                            dx = (float)ex; dy = (float)ey; dz = (float)(ISO ? ez * d.fxs : ez);
                         }
                         qu.push(acc, dx, dy, dz, __uint_as_float(sv[k].w));
                     }
                 }
                 return;
             }
-            const int lm = max(len - 1, 0);
             for (int m0 = 0; m0 < maxlen; m0 += U) {
                 if (qu.full()) qu.drain(alpha, c2a);
+                const double4 *pq = p + min(m0, lm);
                 double4 sv[U];
 #pragma unroll
-                for (int k = 0; k < U; k++) sv[k] = p[min(m0 + k, lm)];   // past the run: rejected below
+                for (int k = 0; k < U; k++) sv[k] = pq[k];
 #pragma unroll
                 for (int k = 0; k < U; k++) {
                     const int m = m0 + k;
@@ -532,8 +561,8 @@ __global__ __launch_bounds__(kBlock) RBE2D_REAL_OCC void k_real(RealArgs a) {
                         const double ye = sqrt(ye2) + rmarg;
                         int cylo = cy + (int)floor((yrel - ye) * d.inv_hy);
                         int cyhi = cy + (int)floor((yrel + ye) * d.inv_hy);
-                        cylo = max(cylo, cy - d.reach);
-                        cyhi = min(cyhi, cy + d.reach);
+                        cylo = max(cylo, cy - d.reach_y);
+                        cyhi = min(cyhi, cy + d.reach_y);
                         const int ya = max(cylo, 0), yb = min(cyhi, d.ncy - 1);
                         if (ya <= yb) { jb1 = start[row + ya]; len1 = start[row + yb + 1] - jb1; }
                         if (cylo < 0) {
@@ -672,12 +701,15 @@ hipError_t launch_pairs(rbe2d_ctx *h, bool want_dg, hipStream_t s) {
     const bool fp32 = h->precision == RBE2D_PREC_FP32_PHASE;
     const dim3 grid(nb8, r.nsplit);
     prof_begin(h, 4, s);
-    if (fp32) {
-        if (want_dg) hipLaunchKernelGGL((k_real<true, true>), grid, dim3(kBlock), 0, s, r);
-        else hipLaunchKernelGGL((k_real<true, false>), grid, dim3(kBlock), 0, s, r);
+    if (fp32 && h->iso) {
+        if (want_dg) hipLaunchKernelGGL((k_real<true, true, true>), grid, dim3(kBlock), 0, s, r);
+        else hipLaunchKernelGGL((k_real<true, false, true>), grid, dim3(kBlock), 0, s, r);
+    } else if (fp32) {
+        if (want_dg) hipLaunchKernelGGL((k_real<true, true, false>), grid, dim3(kBlock), 0, s, r);
+        else hipLaunchKernelGGL((k_real<true, false, false>), grid, dim3(kBlock), 0, s, r);
     } else {
-        if (want_dg) hipLaunchKernelGGL((k_real<false, true>), grid, dim3(kBlock), 0, s, r);
-        else hipLaunchKernelGGL((k_real<false, false>), grid, dim3(kBlock), 0, s, r);
+        if (want_dg) hipLaunchKernelGGL((k_real<false, true, false>), grid, dim3(kBlock), 0, s, r);
+        else hipLaunchKernelGGL((k_real<false, false, false>), grid, dim3(kBlock), 0, s, r);
     }
     if (r.nsplit > 1) {
         const int64_t n = std::max<int64_t>(h->n_total, h->n_swaves);

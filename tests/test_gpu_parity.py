@@ -116,6 +116,19 @@ def test_ragged_and_degenerate(torch, R, orc, precision, case):
     assert_parity(F, E, ref, TOL[precision])
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("box", [(14.0, 9.0, 5.0), (30.0, 30.0, 3.0), (16.0, 16.0, 8.0)],
+                         ids=["rect", "square-thin", "square-thick"])
+def test_box_shapes(torch, R, orc, precision, box):
+    """Rectangular and square boxes: the FP32 pair kernel has an isotropic
+    fixed-point frame for square boxes with room for the z range, and the
+    general frame otherwise."""
+    Lx, Ly, H = box
+    w = inputs.Workload(f"box{Lx:g}x{Ly:g}", 700, Lx, Ly, H, 0.8, -0.7, 1.0, 4.0, 40, 4, seed=17)
+    F, E, ref, _ = run_pair(torch, R, orc, w, precision)
+    assert_parity(F, E, ref, TOL[precision])
+
+
 def test_small_box_minimum_image(torch, R, orc):
     """Lx < 3 r_c: fewer than three cells per axis, minimum image per pair."""
     w = inputs.small_random(5, 200, L=7.0, H=3.0, gamma_top=0.3, gamma_bot=0.2, alpha=1.2, r_c=3.4,
