@@ -360,7 +360,7 @@ rbe2d_status create_handle(int n, const rbe2d_params *ps, bool batch, rbe2d_hand
     A(&sfp, (size_t)cap_blocks * h->P_pad * 4);
     w.sfpart = sfp;
     A(&w.krec, (size_t)n * h->P * kKRec);
-    A(&w.kf32, 2 * (size_t)n * h->P);
+    A(&w.kf32, 3 * (size_t)n * h->P);
     A(&w.fpart, (size_t)std::min<int64_t>(64 * cap_blocks * kBlock, 4096 * kBlock) * 4);
     const int64_t nc = std::max<int64_t>(n_cap, 1);
     A(&w.cell, nc); A(&w.slot, nc); A(&w.tmp, nc);

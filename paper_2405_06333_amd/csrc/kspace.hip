@@ -353,8 +353,12 @@ __global__ __launch_bounds__(64) void k_assemble(AssembleArgs a) {
     rec[7] = e; rec[8] = de[0]; rec[9] = de[1];
     rec[10] = nx; rec[11] = ny; rec[12] = nz;
     rec[13] = rr; rec[14] = ri; rec[15] = kx * kx + ky * ky;
-    a.kf32[2 * kg] = make_float4((float)kx, (float)ky, (float)kz, (float)(kx * kx + ky * ky));
-    a.kf32[2 * kg + 1] = make_float4((float)(c * Ar), (float)(c * Ai), (float)(c * Br), (float)(c * Bi));
+    a.kf32[3 * kg] = make_float4((float)kx, (float)ky, (float)kz, (float)(kx * kx + ky * ky));
+    a.kf32[3 * kg + 1] = make_float4((float)(c * Ar), (float)(c * Ai), (float)(c * Br), (float)(c * Bi));
+    // polar form for the force pass: Im(e^{-i ph} cA) = |cA| sin(arg cA - ph)
+    constexpr double inv2pi = 0.15915494309189535;
+    a.kf32[3 * kg + 2] = make_float4((float)(c * hypot(Ar, Ai)), (float)(atan2(Ai, Ar) * inv2pi),
+                                     (float)(c * hypot(Br, Bi)), (float)(atan2(Bi, Br) * inv2pi));
 }
 
 int choose_tile(int64_t N, int n_kchunks) {
@@ -479,7 +483,7 @@ __global__ __launch_bounds__(kBlock) void k_force32(ForceArgs a) {
     const float4 pa = a.p32[2 * ii];
     const float4 pb = a.p32[2 * ii + 1];
     const float4 *kn = a.kn32 + (int64_t)r * a.P_pad;
-    const float4 *kf = a.kf32 + 2 * (int64_t)r * a.P;
+    const float4 *kf = a.kf32 + 3 * (int64_t)r * a.P;
     const int l0 = blockIdx.y * a.k_per_split;
     const int l1 = min(a.P, l0 + a.k_per_split);
     double Fx = 0, Fy = 0, Fz = 0, Pt = 0;
@@ -489,25 +493,32 @@ __global__ __launch_bounds__(kBlock) void k_force32(ForceArgs a) {
             float fx = 0, fy = 0, fz = 0, pt = 0;
             for (int l = c0; l < c1; l++) {
                 const float4 n = kn[l];
-                const float4 kv = kf[2 * l];
-                const float4 ab = kf[2 * l + 1];
+                const float4 kv = kf[3 * l];
                 float pxy = fractf(fmaf(n.y, pa.z, n.x * pa.x));
                 pxy = fmaf(n.x, pa.y, pxy);
                 pxy = fmaf(n.y, pa.w, pxy);
                 const float pz = fmaf(n.z, pb.y, fractf(n.z * pb.x));
-                const float ph = pxy + pz, phh = pxy - pz;
-                const float c1f = cos_rev(ph), s1f = sin_rev(ph);
-                const float c2f = cos_rev(phh), s2f = sin_rev(phh);
-                const float X = fmaf(ab.y, c1f, -ab.x * s1f);   // Im(e^{-i ph} cA)
-                const float Y = fmaf(ab.w, c2f, -ab.z * s2f);   // Im(e^{-i phh} cB)
+                float X, Y;   // Im(e^{-i ph} cA), Im(e^{-i phh} cB)
+                if (MODE == 1) {
+                    // the potential needs the real parts too
+                    const float4 ab = kf[3 * l + 1];
+                    const float ph = pxy + pz, phh = pxy - pz;
+                    const float c1f = cos_rev(ph), s1f = sin_rev(ph);
+                    const float c2f = cos_rev(phh), s2f = sin_rev(phh);
+                    X = fmaf(ab.y, c1f, -ab.x * s1f);
+                    Y = fmaf(ab.w, c2f, -ab.z * s2f);
+                    pt = fmaf(ab.x, c1f, pt); pt = fmaf(ab.y, s1f, pt);
+                    pt = fmaf(ab.z, c2f, pt); pt = fmaf(ab.w, s2f, pt);
+                } else {
+                    // polar form: one transcendental per product
+                    const float4 pol = kf[3 * l + 2];
+                    X = pol.x * sin_rev((pol.y - pxy) - pz);
+                    Y = pol.z * sin_rev((pol.w - pxy) + pz);
+                }
                 const float sp = X + Y, sm = X - Y;
                 fx = fmaf(kv.x, sp, fx);
                 fy = fmaf(kv.y, sp, fy);
                 fz = fmaf(kv.z, sm, fz);
-                if (MODE == 1) {
-                    pt = fmaf(ab.x, c1f, pt); pt = fmaf(ab.y, s1f, pt);
-                    pt = fmaf(ab.z, c2f, pt); pt = fmaf(ab.w, s2f, pt);
-                }
                 if (MODE == 2) pt = fmaf(kv.w * sp, sp, fmaf(kv.z * sm, kv.z * sm, pt));
             }
             Fx += fx; Fy += fy; Fz += fz; Pt += pt;

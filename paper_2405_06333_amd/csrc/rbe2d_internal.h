@@ -110,7 +110,8 @@ struct Workspace {
     double4 *kn64 = nullptr;    // per k: (nx, ny, nz, 0) as doubles
     void *sfpart = nullptr;     // structure-factor partials [tile][P_pad][4] (float or double)
     double *krec = nullptr;     // per-k records, kKRec doubles each (n_sys x P)
-    float4 *kf32 = nullptr;     // per k: (kx, ky, kz, kx^2 + ky^2), (cAr, cAi, cBr, cBi)
+    float4 *kf32 = nullptr;     // per k: (kx, ky, kz, kx^2 + ky^2), (cAr, cAi, cBr, cBi),
+                                // (|cA|, arg cA / 2 pi, |cB|, arg cB / 2 pi)
     double *fpart = nullptr;    // force-pass partials [ksplit][blocks * kBlock][4]
     // real space
     int *cell = nullptr, *slot = nullptr, *count = nullptr, *start = nullptr, *tmp = nullptr;
