@@ -237,27 +237,48 @@ __device__ __forceinline__ void pair_terms(double r2, double alpha, double c2a, 
 // the sums of the queued pairs' force and potential terms in FP64.
 // ---------------------------------------------------------------------------
 
+// Per-target FP64 sums over all image families.  Each drain's sums are
+// added with the current family's weights: w for x, y and the potential,
+// w * zsign for z (the image height moves against the target's for odd
+// orders), dw / dgamma for the gamma derivatives of the potential; `scale`
+// converts force sums kept in other units.
+template <bool DG>
+struct TargetSums {
+    double fx = 0, fy = 0, fz = 0, phi = 0, dpt = 0, dpb = 0;
+    double wxy = 1, wz = 1, wp = 1, wt = 0, wb = 0;
+    __device__ void family(double w, double zsign, double dwt, double dwb, double scale) {
+        wxy = w * scale; wz = w * zsign * scale; wp = w; wt = dwt; wb = dwb;
+    }
+    __device__ void add(double sx, double sy, double sz, double sp) {
+        fx = fma(sx, wxy, fx); fy = fma(sy, wxy, fy); fz = fma(sz, wz, fz); phi = fma(sp, wp, phi);
+        if (DG) { dpt = fma(sp, wt, dpt); dpb = fma(sp, wb, dpb); }
+    }
+};
+
 // FP32 kernel: a ring of Q entries per lane.  A round evaluates the oldest
 // entry of every lane that holds one; the FP32 sums of a drain (at most Q
 // pairs per lane) are folded into FP64.  Cheap routing (every result stays in
 // its lane) at the price of idle lanes in the rounds.  The lane's read and
 // write positions are kept as byte offsets into the rings (slot-major, one
 // 16-byte entry per thread and slot).  ISO: entries hold displacements in
-// units of the isotropic fixed-point frame; r^2 and the force sums are
-// scaled when a pair is evaluated and when a drain is folded.
-template <int Q, int U, bool ISO>
-struct LaneRings {
+// units of the isotropic fixed-point frame; r^2 is scaled when a pair is
+// evaluated and the force sums when a drain is folded.
+template <int Q, int U, bool ISO, bool DG>
+struct LaneRings : TargetSums<DG> {
     static constexpr int kRoundMin = RBE2D_ROUND_MIN;   // keep draining while this many lanes hold pairs
     static constexpr int kSlot = kBlock * (int)sizeof(float4);
     static constexpr int kMask = Q * kSlot - 1;         // Q * kSlot is a power of two
     unsigned char *base;
     int wofs, rofs, cnt = 0;
     float u2;
-    double ud;
+    double unit;   // force-sum scale of the family weights
     float sx = 0, sy = 0, sz = 0, sp = 0;
-    double gx = 0, gy = 0, gz = 0, gp = 0;
-    __device__ LaneRings(unsigned char *b, int t, float u2_, double ud_)
-        : base(b), wofs(t * (int)sizeof(float4)), rofs(t * (int)sizeof(float4)), u2(u2_), ud(ud_) {}
+    __device__ LaneRings(unsigned char *b, int t, const SysDesc &d)
+        : base(b), wofs(t * (int)sizeof(float4)), rofs(t * (int)sizeof(float4)), u2(ISO ? d.u2 : 1.0f),
+          unit(ISO ? d.ud : 1.0) {}
+    __device__ void family(double w, double zsign, double dwt, double dwb) {
+        TargetSums<DG>::family(w, zsign, dwt, dwb, unit);
+    }
     __device__ void push(bool acc, float dx, float dy, float dz, float qs) {
         if (acc) {
             *reinterpret_cast<float4 *>(base + wofs) = make_float4(dx, dy, dz, qs);
@@ -280,12 +301,7 @@ struct LaneRings {
         }
     }
     __device__ void fold() {
-        if (ISO) {
-            gx = fma((double)sx, ud, gx); gy = fma((double)sy, ud, gy); gz = fma((double)sz, ud, gz);
-        } else {
-            gx += (double)sx; gy += (double)sy; gz += (double)sz;
-        }
-        gp += (double)sp;
+        this->add((double)sx, (double)sy, (double)sz, (double)sp);
         sx = sy = sz = sp = 0;
     }
     // make room for U more pairs per lane
@@ -305,15 +321,17 @@ struct LaneRings {
 // entries tagged with the target's lane), evaluated 64 entries at a time with
 // every lane busy; results go to per-target LDS accumulators by LDS atomic
 // adds.  Worth its routing cost where a pair evaluation is expensive.
-template <int QW, int U>
-struct WaveQueue {
+template <int QW, int U, bool DG>
+struct WaveQueue : TargetSums<DG> {
     double4 *ent;         // [QW] entries of this wave
     unsigned char *own;   // [QW] owning lane
     double *acc;          // [4][64] per-target sums
     int lane, qn = 0;     // qn: entries queued (wave-uniform)
-    double gx = 0, gy = 0, gz = 0, gp = 0;
     __device__ WaveQueue(double4 *e, unsigned char *o, double *a, int l) : ent(e), own(o), acc(a), lane(l) {
         for (int c = 0; c < 4; c++) acc[c * kWave + lane] = 0.0;
+    }
+    __device__ void family(double w, double zsign, double dwt, double dwb) {
+        TargetSums<DG>::family(w, zsign, dwt, dwb, 1.0);
     }
     __device__ void push(bool ok, double dx, double dy, double dz, double qs) {
         const uint64_t m = __ballot(ok);
@@ -345,7 +363,7 @@ struct WaveQueue {
     }
     __device__ void fold() {
         __builtin_amdgcn_wave_barrier();
-        gx += acc[lane]; gy += acc[kWave + lane]; gz += acc[2 * kWave + lane]; gp += acc[3 * kWave + lane];
+        this->add(acc[lane], acc[kWave + lane], acc[2 * kWave + lane], acc[3 * kWave + lane]);
         for (int c = 0; c < 4; c++) acc[c * kWave + lane] = 0.0;
     }
     __device__ void drain(double alpha, double c2a) {
@@ -388,25 +406,13 @@ __device__ __forceinline__ int wave_min(int v) {
 // evaluates erfc/exp and the per-drain partial sums in FP32 and accumulates
 // the drains in FP64.  The order of every sum is fixed by the data, so the
 // results are bitwise reproducible.
-template <typename Queue> __device__ Queue make_queue(unsigned char *lds, int tid, const SysDesc &d);
-template <>
-__device__ LaneRings<RBE2D_RING_Q, RBE2D_REAL_U32, false>
-make_queue<LaneRings<RBE2D_RING_Q, RBE2D_REAL_U32, false>>(unsigned char *lds, int tid, const SysDesc &d) {
-    return LaneRings<RBE2D_RING_Q, RBE2D_REAL_U32, false>(lds, tid, 1.0f, 1.0);
-}
-template <>
-__device__ LaneRings<RBE2D_RING_Q, RBE2D_REAL_U32, true>
-make_queue<LaneRings<RBE2D_RING_Q, RBE2D_REAL_U32, true>>(unsigned char *lds, int tid, const SysDesc &d) {
-    return LaneRings<RBE2D_RING_Q, RBE2D_REAL_U32, true>(lds, tid, d.u2, d.ud);
-}
-template <>
-__device__ WaveQueue<256, 2> make_queue<WaveQueue<256, 2>>(unsigned char *lds, int tid, const SysDesc &) {
-    constexpr int kQ = 256;
+template <int QW, int U, bool DG>
+__device__ WaveQueue<QW, U, DG> make_wave_queue(unsigned char *lds, int tid) {
     const int wid = tid / kWave, lane = tid % kWave;
-    double4 *ent = reinterpret_cast<double4 *>(lds) + wid * kQ;
-    double *acc = reinterpret_cast<double *>(lds + (kBlock / kWave) * kQ * sizeof(double4)) + wid * 4 * kWave;
-    unsigned char *own = lds + (kBlock / kWave) * (kQ * sizeof(double4) + 4 * kWave * sizeof(double)) + wid * kQ;
-    return WaveQueue<kQ, 2>(ent, own, acc, lane);
+    double4 *ent = reinterpret_cast<double4 *>(lds) + wid * QW;
+    double *acc = reinterpret_cast<double *>(lds + (kBlock / kWave) * QW * sizeof(double4)) + wid * 4 * kWave;
+    unsigned char *own = lds + (kBlock / kWave) * (QW * sizeof(double4) + 4 * kWave * sizeof(double)) + wid * QW;
+    return WaveQueue<QW, U, DG>(ent, own, acc, lane);
 }
 
 template <bool FP32, bool WANT_DG, bool ISO>
@@ -417,7 +423,8 @@ __global__ __launch_bounds__(kBlock) RBE2D_REAL_OCC void k_real(RealArgs a) {
     constexpr int NW = kBlock / kWave;
     constexpr int kRingQ = RBE2D_RING_Q;   // FP32: ring entries per lane
     constexpr int kWaveQ = 256;    // FP64: queue entries per wave
-    using Queue = typename std::conditional<FP32, LaneRings<kRingQ, U, ISO>, WaveQueue<kWaveQ, U>>::type;
+    using Queue = typename std::conditional<FP32, LaneRings<kRingQ, U, ISO, WANT_DG>,
+                                            WaveQueue<kWaveQ, U, WANT_DG>>::type;
     constexpr size_t kLds = FP32 ? sizeof(float4) * kRingQ * kBlock
                                  : NW * (kWaveQ * (sizeof(double4) + 1) + 4 * kWave * sizeof(double));
     __shared__ __align__(16) unsigned char lds[kLds];
@@ -452,7 +459,10 @@ __global__ __launch_bounds__(kBlock) RBE2D_REAL_OCC void k_real(RealArgs a) {
     const double rmarg = 1e-9 * d.rc;               // cells were assigned by division
     const T alpha = (T)d.alpha;
     const T c2a = (T)(1.1283791670955126 * d.alpha);
-    double fx = 0, fy = 0, fz = 0, phi = 0, dpt = 0, dpb = 0;
+    Queue qu = [&]() {
+        if constexpr (FP32) return Queue(lds, tid, d);
+        else return make_wave_queue<kWaveQ, U, WANT_DG>(lds, tid);
+    }();
     for (int f = 0; f <= d.nfam; f++) {
         double sz = 1.0, czs = 0.0, w = 1.0, zsign = 1.0, dwt = 0.0, dwb = 0.0;
         if (f > 0) {
@@ -469,7 +479,7 @@ __global__ __launch_bounds__(kBlock) RBE2D_REAL_OCC void k_real(RealArgs a) {
             lzhi = min(d.ncz - 1, (int)floor((tz + d.rc + rmarg) * d.inv_hz));
         }
         const int wzlo = wave_min(lzlo), wzhi = wave_max(lzhi);
-        Queue qu = make_queue<Queue>(lds, tid, d);
+        qu.family(w, zsign, dwt, dwb);
         // scan one run of sources [jb, jb + len) for pairs within r_c.  The
         // trip count is the wave maximum, so drains always run with every
         // lane.  Loads are issued U at a time ahead of their use: the loop is
@@ -505,8 +515,10 @@ __global__ __launch_bounds__(kBlock) RBE2D_REAL_OCC void k_real(RealArgs a) {
                         if (acc && r2 < near2s) {
                             const double4 s64 = p[m];
                             double ex = xt - s64.x, ey = yt - s64.y;
-                            ex -= d.Lx * rint(ex / d.Lx);
-                            ey -= d.Ly * rint(ey / d.Ly);
+                            // the true displacement is below `near`, far from half a
+                            // period, so rounding by the reciprocal finds the same image
+                            ex -= d.Lx * rint(ex * d.inv_Lx);
+                            ey -= d.Ly * rint(ey * d.inv_Ly);
                             const double ez = tz - s64.z;
                             // zero displacement only for the target itself (direct family)
                             acc = ex != 0.0 || ey != 0.0 || ez != 0.0;
@@ -529,8 +541,10 @@ __global__ __launch_bounds__(kBlock) RBE2D_REAL_OCC void k_real(RealArgs a) {
                     const int m = m0 + k;
                     double dx = xt - sv[k].x;
                     double dy = yt - sv[k].y;
-                    if (allx) dx -= d.Lx * rint(dx / d.Lx);
-                    if (ally) dy -= d.Ly * rint(dy / d.Ly);
+                    // the images differ only where |dx| is near half a period,
+                    // beyond r_c <= period / 2 either way
+                    if (allx) dx -= d.Lx * rint(dx * d.inv_Lx);
+                    if (ally) dy -= d.Ly * rint(dy * d.inv_Ly);
                     const double dz = tz - sv[k].z;
                     const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
                     qu.push(m < len && r2 < d.rc2 && m != self, (T)dx, (T)dy, (T)dz, (T)sv[k].w);
@@ -586,12 +600,8 @@ __global__ __launch_bounds__(kBlock) RBE2D_REAL_OCC void k_real(RealArgs a) {
             }
         }
         qu.flush(alpha, c2a);
-        fx = fma(w, qu.gx, fx);
-        fy = fma(w, qu.gy, fy);
-        fz = fma(w * zsign, qu.gz, fz);
-        phi = fma(w, qu.gp, phi);
-        if (WANT_DG) { dpt = fma(dwt, qu.gp, dpt); dpb = fma(dwb, qu.gp, dpb); }
     }
+    const double fx = qu.fx, fy = qu.fy, fz = qu.fz, phi = qu.phi, dpt = qu.dpt, dpb = qu.dpb;
     double qphi = 0.0, qdt = 0.0, qdb = 0.0;
     if (active) {
         const int i = a.sidx[t];
