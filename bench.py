@@ -42,7 +42,7 @@ SLOTS_REAL = 24    # per pair within r_c: d2 (5), cutoff (1), rsqrt (2), exp (2+
 # HBM traffic of the dominant kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE
 # (profiles/), valid only while the kernel sources are the ones it was taken on
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "real_pairs_large_md_traffic.txt")
-TRAFFIC_SOURCES = ("realspace.hip", "rbe2d_internal.h", "devmath.h", "erfcx_fit.h")
+TRAFFIC_SOURCES = ("realspace.hip", "rbe2d_internal.h", "devmath.h", "erfcx_fit.h", "api.hip")
 
 
 def kernel_source_hash():
