@@ -34,9 +34,10 @@ VALU_LANE_SLOTS = 256 * 64 * 2.4e9          # lane-instruction slots per second
 # algorithmic VALU lane-slots per (particle, k) pair; a transcendental
 # (v_sin/v_cos/v_exp/v_rsq/v_rcp) occupies 2 slots (half rate on gfx950)
 SLOTS_SF = 16      # k.r (3), khat.r (1), sin+cos of both (8), 4 accumulating FMAs
-SLOTS_FORCE = 21   # k.r (3), khat.r (1), sin+cos of both (8), 2 Im parts (4), X+-Y (2), 3 force FMAs
-SLOTS_REAL = 24    # per pair within r_c: d2 (5), cutoff (1), rsqrt (2), exp (2+1), erfc fit
-                   # (rcp 2 + 9 FMA), force factor (2); pairs outside r_c not counted
+SLOTS_FORCE = 16   # k.r (3), khat.r (1), angle offsets of the polar amplitudes (2), two sines (4),
+                   # |cA| sin (1), X +- |cB| sin (2), 3 force FMAs
+SLOTS_REAL = 22    # per pair within r_c: d2 (5), cutoff (1), rsqrt (2), exp (2+1), erfc fit
+                   # (rcp 2 + 7 FMA), force factor (2); pairs outside r_c not counted
 
 
 # HBM traffic of the dominant kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE
