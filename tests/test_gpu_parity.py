@@ -129,6 +129,41 @@ def test_box_shapes(torch, R, orc, precision, box):
     assert_parity(F, E, ref, TOL[precision])
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_close_pairs(torch, R, orc, precision):
+    """Pairs far closer than the FP32 kernel's fixed-point quantum allows
+    (its FP64 recompute), across the periodic boundaries, and ions next to
+    a wall (their own images at twice the distance)."""
+    L, H = 12.0, 5.0
+    rng = np.random.default_rng(23)
+    base = inputs.positions(rng, 200, L, L, H, 0.5)
+    pairs = []
+    for k, d in enumerate([1e-4, 1e-3, 1e-2, 0.1, 0.3, 0.6, 1.0]):
+        c = np.array([rng.uniform(1, L - 1), rng.uniform(1, L - 1), rng.uniform(1, H - 1)])
+        u = rng.normal(size=3)
+        u /= np.linalg.norm(u)
+        pairs += [c, c + d * u]
+    pairs += [[1e-4, 3.0, 2.0], [L - 2e-4, 3.0, 2.0001]]          # across x = 0
+    pairs += [[6.0, L - 5e-5, 2.5], [6.00003, 1e-5, 2.5]]        # across y = 0
+    pairs += [[4.0, 4.0, 1e-3], [8.0, 8.0, H - 2e-3]]            # at the walls
+    pos = np.concatenate([base, np.array(pairs)])
+    pos[:, :2] %= L
+    N = len(pos)
+    q = np.where(np.arange(N) % 2 == 0, 1.0, -1.0)
+    w = inputs.Workload("close", N, L, L, H, 0.7, -0.6, 1.0, 4.0, 30, 3, seed=23)
+    slab = gpu_slab(R, w, precision)
+    n = slab.draw_kset(23)
+    slab.set_kset(n)
+    F, E = slab.forces(to_dev(torch, pos), to_dev(torch, q), want_energy=True)
+    slab.check()
+    ref = orc.evaluate(oracle_slab(orc, w, slab.Lz_ext), pos, q, n)
+    assert_parity(F.cpu().numpy(), E.cpu().numpy(), ref, TOL[precision])
+    # every particle to the same bar, not only the rms (the closest pairs dominate it)
+    Fg = F.cpu().numpy()
+    rel = np.linalg.norm(Fg - ref.F, axis=1) / np.linalg.norm(ref.F, axis=1)
+    assert rel.max() <= 10 * TOL[precision], rel.max()
+
+
 def test_small_box_minimum_image(torch, R, orc):
     """Lx < 3 r_c: fewer than three cells per axis, minimum image per pair."""
     w = inputs.small_random(5, 200, L=7.0, H=3.0, gamma_top=0.3, gamma_bot=0.2, alpha=1.2, r_c=3.4,
