@@ -40,6 +40,29 @@ __device__ __forceinline__ void sincos_rev64(double r, double *s_out, double *c_
     *c_out = ((qi + 1) & 2) ? -c0 : c0;
 }
 
+// sin of 2 pi r alone: r is reduced to the nearest half turn (exact, as
+// above), then the Taylor polynomial of sin to t^23 on |t| <= pi/2, whose
+// truncation error is below 1e-20; an odd half turn flips the sign.
+__device__ __forceinline__ double sin_rev64(double r) {
+    const double kd = rint(2.0 * r);
+    const double f = fma(-0.5, kd, r);
+    const double t = f * (2.0 * kPi);
+    const double t2 = t * t;
+    double p = -1.0 / 25852016738884976640000.0;  // -1/23!
+    p = fma(p, t2, 1.0 / 51090942171709440000.0);  // 1/21!
+    p = fma(p, t2, -1.0 / 121645100408832000.0);   // -1/19!
+    p = fma(p, t2, 1.0 / 355687428096000.0);       // 1/17!
+    p = fma(p, t2, -1.0 / 1307674368000.0);        // -1/15!
+    p = fma(p, t2, 1.0 / 6227020800.0);            // 1/13!
+    p = fma(p, t2, -1.0 / 39916800.0);             // -1/11!
+    p = fma(p, t2, 1.0 / 362880.0);                // 1/9!
+    p = fma(p, t2, -1.0 / 5040.0);                 // -1/7!
+    p = fma(p, t2, 1.0 / 120.0);                   // 1/5!
+    p = fma(p, t2, -1.0 / 6.0);                    // -1/3!
+    const double s = fma(t * t2, p, t);
+    return (((long long)kd) & 1) ? -s : s;
+}
+
 __device__ __forceinline__ float fractf(float x) { return __builtin_amdgcn_fractf(x); }
 __device__ __forceinline__ float sin_rev(float x) { return __builtin_amdgcn_sinf(x); }
 __device__ __forceinline__ float cos_rev(float x) { return __builtin_amdgcn_cosf(x); }

@@ -353,12 +353,13 @@ __global__ __launch_bounds__(64) void k_assemble(AssembleArgs a) {
     rec[7] = e; rec[8] = de[0]; rec[9] = de[1];
     rec[10] = nx; rec[11] = ny; rec[12] = nz;
     rec[13] = rr; rec[14] = ri; rec[15] = kx * kx + ky * ky;
+    // polar form for the force passes: Im(e^{-i ph} cA) = |cA| sin(arg cA - ph)
+    constexpr double inv2pi = 0.15915494309189535;
+    rec[16] = c * hypot(Ar, Ai); rec[17] = atan2(Ai, Ar) * inv2pi;
+    rec[18] = c * hypot(Br, Bi); rec[19] = atan2(Bi, Br) * inv2pi;
     a.kf32[3 * kg] = make_float4((float)kx, (float)ky, (float)kz, (float)(kx * kx + ky * ky));
     a.kf32[3 * kg + 1] = make_float4((float)(c * Ar), (float)(c * Ai), (float)(c * Br), (float)(c * Bi));
-    // polar form for the force pass: Im(e^{-i ph} cA) = |cA| sin(arg cA - ph)
-    constexpr double inv2pi = 0.15915494309189535;
-    a.kf32[3 * kg + 2] = make_float4((float)(c * hypot(Ar, Ai)), (float)(atan2(Ai, Ar) * inv2pi),
-                                     (float)(c * hypot(Br, Bi)), (float)(atan2(Bi, Br) * inv2pi));
+    a.kf32[3 * kg + 2] = make_float4((float)rec[16], (float)rec[17], (float)rec[18], (float)rec[19]);
 }
 
 int choose_tile(int64_t N, int n_kchunks) {
@@ -552,19 +553,25 @@ __global__ __launch_bounds__(kBlock) void k_force64(ForceArgs a) {
             const double *rec = kr + (int64_t)l * kKRec;
             const double pxy = fma(n.y, p.y, n.x * p.x);
             const double pz = n.z * p.z;
-            double c1, s1, c2, s2;
-            sincos_rev64(pxy + pz, &s1, &c1);
-            sincos_rev64(pxy - pz, &s2, &c2);
-            const double X = fma(rec[4], c1, -rec[3] * s1);
-            const double Y = fma(rec[6], c2, -rec[5] * s2);
+            double X, Y;   // Im(e^{-i ph} cA), Im(e^{-i phh} cB)
+            if (MODE == 1) {
+                // the potential needs the real parts too
+                double c1, s1, c2, s2;
+                sincos_rev64(pxy + pz, &s1, &c1);
+                sincos_rev64(pxy - pz, &s2, &c2);
+                X = fma(rec[4], c1, -rec[3] * s1);
+                Y = fma(rec[6], c2, -rec[5] * s2);
+                pt = fma(rec[3], c1, pt); pt = fma(rec[4], s1, pt);
+                pt = fma(rec[5], c2, pt); pt = fma(rec[6], s2, pt);
+            } else {
+                // polar form: one sine per product
+                X = rec[16] * sin_rev64((rec[17] - pxy) - pz);
+                Y = rec[18] * sin_rev64((rec[19] - pxy) + pz);
+            }
             const double sp = X + Y, sm = X - Y;
             fx = fma(rec[0], sp, fx);
             fy = fma(rec[1], sp, fy);
             fz = fma(rec[2], sm, fz);
-            if (MODE == 1) {
-                pt = fma(rec[3], c1, pt); pt = fma(rec[4], s1, pt);
-                pt = fma(rec[5], c2, pt); pt = fma(rec[6], s2, pt);
-            }
             if (MODE == 2) pt = fma(rec[15] * sp, sp, fma(rec[2] * sm, rec[2] * sm, pt));
         }
     }

@@ -74,7 +74,8 @@ struct SysDesc {
 //   [0..2] kx, ky, kz      [3..6] c*A (re, im), c*B (re, im)
 //   [7] e_l = c Re(rho conj(rho^M))   [8..9] d e_l / d gamma_{top,bot}
 //   [10..12] nx, ny, nz (as doubles)  [13..14] rho (re, im)  [15] kx^2 + ky^2
-constexpr int kKRec = 16;
+//   [16..19] polar form |cA|, arg cA / 2 pi, |cB|, arg cB / 2 pi
+constexpr int kKRec = 20;
 
 // Layout of the particles of all systems in the internal arrays (device
 // copies, n_sys + 1 entries each, prefix form: entry r is the start of
