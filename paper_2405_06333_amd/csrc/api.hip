@@ -284,6 +284,7 @@ void free_all(rbe2d_ctx *h) {
     if (h->lay_ev) (void)hipEventDestroy(h->lay_ev);
     if (h->fork_ev) (void)hipEventDestroy(h->fork_ev);
     if (h->join_ev) (void)hipEventDestroy(h->join_ev);
+    if (h->tail_ev) (void)hipEventDestroy(h->tail_ev);
     if (h->side) (void)hipStreamDestroy(h->side);
 }
 
@@ -403,6 +404,7 @@ rbe2d_status create_handle(int n, const rbe2d_params *ps, bool batch, rbe2d_hand
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&h->join_ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->tail_ev, hipEventDisableTiming);
     if (e != hipSuccess) {
         const bool oom = e == hipErrorOutOfMemory;
         free_all(h);
@@ -616,12 +618,105 @@ rbe2d_status md_step(rbe2d_ctx *h, double *pos, double *vel, const double *q, do
     return RBE2D_OK;
 }
 
+// Force evaluation and closing kick of one plain velocity-Verlet step at
+// the current positions (whose k-set is drawn).  The k-space chain runs on
+// the side stream, real space on s.  After the forces, either the closing
+// half kick (last step of the run) or the closing and next opening half
+// kicks with the next drift in one pass.  Meanwhile the side stream draws
+// the next step's k-set (device step counter: incremented there first).
+// The next step's fork orders that draw before the next k-space chain; a
+// captured step joins it back explicitly (join_tail).
+rbe2d_status vv_unit(rbe2d_ctx *h, double *pos, double *vel, const double *q, double *F, double dt, double zlo,
+                     double zhi_from_top, uint64_t seed, int64_t step, bool dev_step, bool last, bool join_tail,
+                     hipStream_t s) {
+    hipStream_t ks = h->side;
+    RBE2D_TRY(h, hipEventRecord(h->fork_ev, s), "fork event");
+    RBE2D_TRY(h, hipStreamWaitEvent(ks, h->fork_ev, 0), "fork wait");
+    RBE2D_TRY(h, launch_prep(h, pos, q, ks), "prep launch");
+    RBE2D_TRY(h, launch_kcoef_sf(h, ks), "structure-factor launch");
+    RBE2D_TRY(h, launch_kforce(h, pos, q, F, nullptr, RBE2D_KSPACE | RBE2D_IBC, false, false, false, nullptr, ks),
+              "force launch");
+    RBE2D_TRY(h, launch_real(h, pos, q, false, s), "real-space launch");
+    RBE2D_TRY(h, hipEventRecord(h->join_ev, ks), "join event");
+    RBE2D_TRY(h, hipStreamWaitEvent(s, h->join_ev, 0), "join wait");
+    if (!last) {
+        if (dev_step) RBE2D_TRY(h, launch_step_inc(h, ks), "md step counter");
+        RBE2D_TRY(h, launch_sample(h, seed, (uint64_t)(step + 1) * (uint64_t)h->n_sys, dev_step ? h->w.step : nullptr,
+                                   ks), "md sample");
+        RBE2D_TRY(h, launch_md_leapfrog(h, pos, vel, F, dt, zlo, zhi_from_top, s), "md leapfrog");
+    } else {
+        RBE2D_TRY(h, launch_add_real(h, F, vel, 0.5 * dt, s), "real-space add");
+    }
+    if (join_tail) {
+        RBE2D_TRY(h, hipEventRecord(h->tail_ev, ks), "tail event");
+        RBE2D_TRY(h, hipStreamWaitEvent(s, h->tail_ev, 0), "tail wait");
+    }
+    return RBE2D_OK;
+}
+
+// plain velocity Verlet (no thermostat, no short-range forces) over n steps:
+// the opening kick and drift with the caller's F and the first k-draw, then
+// n force evaluations chained by fused kicks; with use_graph the middle ones
+// are replays of one captured unit
+rbe2d_status vv_run(rbe2d_ctx *h, double *pos, double *vel, const double *q, double *F, double dt, double zlo,
+                    double zhi_from_top, uint64_t seed, int64_t step0, int32_t n_steps, bool use_graph,
+                    hipStream_t s) {
+    RBE2D_TRY(h, launch_md_kick_drift(h, pos, vel, F, dt, zlo, zhi_from_top, s), "md drift");
+    RBE2D_TRY(h, launch_sample(h, seed, (uint64_t)step0 * (uint64_t)h->n_sys, nullptr, s), "md sample");
+    int32_t it = 0;
+    if (use_graph) {
+        auto bits = [](double x) { uint64_t u; std::memcpy(&u, &x, 8); return u; };
+        std::vector<uint64_t> key = {1, (uint64_t)(uintptr_t)pos, (uint64_t)(uintptr_t)vel, (uint64_t)(uintptr_t)q,
+                                     (uint64_t)(uintptr_t)F, bits(dt), bits(zlo), bits(zhi_from_top), seed,
+                                     (uint64_t)h->per};
+        key.insert(key.end(), h->lay_host.begin(), h->lay_host.end());
+        if (!h->md_exec || key != h->md_key) {
+            free_graph(h);
+            hipStream_t cs;
+            RBE2D_TRY(h, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "capture stream");
+            const int prof_n = h->prof.n;
+            h->prof.n = 0;   // no profiling events inside the graph
+            hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+            rbe2d_status st = RBE2D_OK;
+            if (e == hipSuccess) {
+                st = vv_unit(h, pos, vel, q, F, dt, zlo, zhi_from_top, seed, 0, true, false, true, cs);
+                hipGraph_t g = nullptr;
+                const hipError_t e2 = hipStreamEndCapture(cs, &g);
+                if (st == RBE2D_OK && e2 != hipSuccess) st = hipfail(h, e2, "end capture");
+                if (st == RBE2D_OK) {
+                    h->md_graph = g;
+                    const hipError_t e3 = hipGraphInstantiate(&h->md_exec, g, nullptr, nullptr, 0);
+                    if (e3 != hipSuccess) st = hipfail(h, e3, "graph instantiate");
+                } else if (g) {
+                    (void)hipGraphDestroy(g);
+                }
+            } else {
+                st = hipfail(h, e, "begin capture");
+            }
+            h->prof.n = prof_n;
+            (void)hipStreamDestroy(cs);
+            if (st) { free_graph(h); return st; }
+            h->md_key = key;
+        }
+        RBE2D_TRY(h, launch_set_step(h, step0, s), "md step counter");
+        for (; it < n_steps - 1; it++) RBE2D_TRY(h, hipGraphLaunch(h->md_exec, s), "graph launch");
+    }
+    for (; it < n_steps; it++) {
+        rbe2d_status st = vv_unit(h, pos, vel, q, F, dt, zlo, zhi_from_top, seed, step0 + it, false,
+                                  it == n_steps - 1, false, s);
+        if (st) return st;
+    }
+    return RBE2D_OK;
+}
+
 // n_steps MD steps, eager or as replays of one captured step
 rbe2d_status md_run(rbe2d_ctx *h, double *pos, double *vel, const double *q, double *F, double dt, double zlo,
                     double zhi_from_top, uint64_t seed, int64_t step0, int32_t n_steps, bool use_graph,
                     const MdExtra *mx, hipStream_t s) {
     if (n_steps <= 0) return RBE2D_OK;
     h->kset_valid = true;
+    if (!mx && h->n_total > 0)
+        return vv_run(h, pos, vel, q, F, dt, zlo, zhi_from_top, seed, step0, n_steps, use_graph, s);
     if (!use_graph) {
         for (int32_t it = 0; it < n_steps; it++) {
             rbe2d_status st = md_step(h, pos, vel, q, F, dt, zlo, zhi_from_top, seed, step0 + it, false, mx, s);

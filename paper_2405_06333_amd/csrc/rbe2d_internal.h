@@ -186,7 +186,7 @@ struct rbe2d_ctx {
     // the k-space chain runs on a second stream beside the real-space chain
     // (default priority), forked from and joined back to the caller's stream
     hipStream_t side = nullptr;
-    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr, tail_ev = nullptr;
     bool kev_pending = false;
     // launch parameters: tuned for one particle layout by rbe2d_autotune, else
     // heuristic; force_* override both while the tuner times candidates
@@ -236,6 +236,8 @@ hipError_t launch_sample(rbe2d_ctx *h, uint64_t seed, uint64_t stream_id, const 
 hipError_t launch_md_kick_drift(rbe2d_ctx *h, double *pos, double *vel, const double *F, double dt,
                                 double zlo, double zhi_from_top, hipStream_t s);
 hipError_t launch_md_kick(rbe2d_ctx *h, double *vel, const double *F, double dt, hipStream_t s);
+hipError_t launch_md_leapfrog(rbe2d_ctx *h, double *pos, double *vel, const double *F, double dt, double zlo,
+                              double zhi_from_top, hipStream_t s);
 hipError_t launch_set_step(rbe2d_ctx *h, long long value, hipStream_t s);
 hipError_t launch_step_inc(rbe2d_ctx *h, hipStream_t s);
 hipError_t launch_fill(void *p, int64_t nbytes_multiple_of_4, hipStream_t s);

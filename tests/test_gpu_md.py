@@ -154,3 +154,31 @@ def test_thermostat_reaches_target_temperature(torch, R):
         temps.append(float((V_ ** 2).mean().item()))
     s.check()
     assert abs(np.mean(temps) - kT) < 0.05 * kT, temps
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_velocity_verlet_steps_match_oracle(torch, R, orc, use_graph):
+    """Four plain velocity-Verlet steps (md_run: chained half kicks, the next
+    k-set drawn beside the force pass) against the oracle's step with no
+    friction, fed with the same k-sets."""
+    w = inputs.small_random(51, 400, L=11.0, H=6.0, gamma_top=0.6, gamma_bot=-0.4, alpha=0.9, r_c=4.0, P=40,
+                            M=4, margin=0.5)
+    pos, q = inputs.sample(w)
+    s = R.Slab(**w.slab_kwargs(), precision="fp64", n_max=w.N)
+    o = oracle_slab(orc, w, s.Lz_ext)
+    seed, dt, step0, zlo, zhi = 13, 2e-3, 3, 0.3, w.H - 0.3
+    vel = np.random.default_rng(6).normal(0.0, 2.0, pos.shape)
+    n0 = s.draw_kset(seed, 1)
+    F0 = orc.evaluate(o, pos, q, n0).F
+    P_, V_, Q_, F_ = to_dev(torch, pos), to_dev(torch, vel), to_dev(torch, q), to_dev(torch, F0)
+    s.md_run(P_, V_, Q_, F_, dt, zlo, zhi, seed, step0, 4, use_graph=use_graph)
+    s.check()
+    p, v, F = pos, vel, F0
+    for st in range(step0, step0 + 4):
+        n = orc.draw_kset(o, seed, st)
+        p, v, F = orc.baoab_step(p, v, F, dt, 0.0, 0.0, np.zeros_like(p), w.Lx, w.Ly, zlo, zhi,
+                                 lambda x: orc.evaluate(o, x, q, n).F)
+    assert np.abs(P_.cpu().numpy() - p).max() <= 1e-11
+    assert rel_rms(V_.cpu().numpy(), v) <= 1e-11
+    assert rel_rms(F_.cpu().numpy(), F) <= 1e-9
+    assert np.array_equal(s.get_kset(), orc.draw_kset(o, seed, step0 + 3))
