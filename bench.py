@@ -74,6 +74,7 @@ def measured_traffic(kernel):
 
 
 SIDE_STREAM = ("prep", "sf_pass", "assemble", "force_scatter")
+BREAKDOWN_STEPS = 5   # profiled steps for the per-kernel breakdown, before the timed ones
 
 
 def parse():
@@ -138,20 +139,43 @@ def run_md(R, torch, w, precision, steps, warmup, profile, use_graph=False, auto
     step += warmup
     torch.cuda.synchronize()
     slab.check()
+    prof = None
     if profile:
+        # per-kernel breakdown: a short run with every kernel class bracketed
+        # by events (outside the timed region: the events of all classes add
+        # tens of microseconds per step); then the timed run brackets only
+        # the dominant caller-stream kernel
+        nb = min(steps, BREAKDOWN_STEPS)
+        slab.profile_enable(nb + 4)
+        slab.profile_read()
+        slab.md_run(P_, V_, Q_, F_, w.dt, zlo, zhi, w.seed, step, nb, use_graph=use_graph)
+        step += nb
+        breakdown = slab.profile_read()
+        dom = dominant_kernel(breakdown)
         slab.profile_enable(steps + 4)
+        slab.profile_classes([dom])
         slab.profile_read()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     slab.md_run(P_, V_, Q_, F_, w.dt, zlo, zhi, w.seed, step, steps, use_graph=use_graph)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    prof = slab.profile_read() if profile else None
+    if profile:
+        prof = {"breakdown": breakdown, "dominant": dom, "timed": slab.profile_read()[dom]}
+        slab.profile_enable(0)
     slab.check()
     finite = bool(torch.isfinite(F_).all().item() and torch.isfinite(P_).all().item())
     if profile:
         tuned = dict(err, launch_params=tuned)
     return (t1 - t0), prof, finite, tuned
+
+
+def dominant_kernel(prof):
+    """The k-space chain (with its force scatter) runs on a second stream,
+    overlapped with the cell list and the pair kernel: its event durations
+    include the time it shares the chip, so the dominant kernel is taken
+    among the caller-stream kernels."""
+    return max((k for k in prof if k not in SIDE_STREAM), key=lambda k: prof[k][0])
 
 
 def timed(torch, fn, steps):
@@ -353,17 +377,17 @@ def main():
     ms_step = secs * 1e3 / a.steps
     value = w.N * a.steps / secs
 
-    # per-kernel breakdown and the roofline of the dominant kernel
-    kern = {k: {"ms_per_launch": (t / n if n else None), "launches": n} for k, (t, n) in prof.items()}
-    # the k-space chain (with its force scatter) runs on a second stream,
-    # overlapped with the cell list and the pair kernel: its event durations
-    # include the time it shares the chip, so the dominant kernel is taken
-    # among the caller-stream kernels
+    # per-kernel breakdown (separate profiled steps) and the roofline of the
+    # dominant kernel (its events inside the timed region)
+    bd = prof["breakdown"]
+    kern = {k: {"ms_per_launch": (t / n if n else None), "launches": n} for k, (t, n) in bd.items()}
     for k in SIDE_STREAM:
         if k in kern:
             kern[k]["overlapped"] = True
-    dom = max((k for k in prof if k not in SIDE_STREAM), key=lambda k: prof[k][0])
-    t_dom = prof[dom][0] / max(prof[dom][1], 1) * 1e-3
+    dom = prof["dominant"]
+    t_dom = prof["timed"][0] / max(prof["timed"][1], 1) * 1e-3
+    kern[dom]["ms_per_launch_timed"] = t_dom * 1e3
+    kern[dom]["launches_timed"] = prof["timed"][1]
     NP = w.N * w.P
     pairs_real = expected_real_pairs(w)
     if dom == "sf_pass":
@@ -383,10 +407,10 @@ def main():
                 "concurrent_with": list(SIDE_STREAM) if dom == "real_pairs" else []}
     for k, slots, units in (("sf_pass", SLOTS_SF, NP), ("force_scatter", SLOTS_FORCE, NP),
                             ("real_pairs", SLOTS_REAL, pairs_real)):
-        t, n = prof[k]
+        t, n = bd[k]
         if n:
             kern[k]["valu_frac"] = round(slots * units / (t / n * 1e-3) / VALU_LANE_SLOTS, 4)
-    t, n = prof["real_pairs"]
+    t, n = bd["real_pairs"]
     if n:   # algorithmic HBM bytes of the pair kernel: read (x, y, z, q) + index, write F and phi
         kern["real_pairs"]["hbm_GBs"] = round(w.N * (32 + 4 + 32) / (t / n * 1e-3) / 1e9, 1)
 

@@ -335,6 +335,12 @@ enum { RBE2D_PROF_SLOTS = 11 };
 rbe2d_status rbe2d_profile_enable(rbe2d_handle h, int32_t n_events);
 rbe2d_status rbe2d_profile_read(rbe2d_handle h, double *ms, int64_t *launches, int32_t n_slots);
 
+/* Restricts the timing to the classes whose bit is set in class_mask (bit
+ * i = class i above); rbe2d_profile_enable selects all classes.  Each timed
+ * launch adds two event records to its stream, so timing one class perturbs
+ * the timed work least.  Errors: RBE2D_E_INVAL (NULL handle). */
+rbe2d_status rbe2d_profile_classes(rbe2d_handle h, uint32_t class_mask);
+
 /* Synchronises `stream` and reports asynchronous errors: RBE2D_E_RANGE if a
  * call since the last check saw z outside (0, H), RBE2D_E_HIP for a failed
  * kernel.  Clears the device error word. */

@@ -1173,6 +1173,13 @@ rbe2d_status rbe2d_profile_enable(rbe2d_handle h, int32_t n_events) {
             for (int i = 0; i < n_events; i++) RBE2D_TRY(h, hipEventCreate(&p.ev[sl][b][i]), "profile event");
         }
     p.n = n_events;
+    p.mask = ~0u;
+    return RBE2D_OK;
+}
+
+rbe2d_status rbe2d_profile_classes(rbe2d_handle h, uint32_t class_mask) {
+    if (!h) return fail(nullptr, RBE2D_E_INVAL, "handle is NULL");
+    h->prof.mask = class_mask;
     return RBE2D_OK;
 }
 

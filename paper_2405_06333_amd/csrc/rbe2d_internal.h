@@ -91,6 +91,7 @@ struct Layout {
 // HIP-event timing of kernel classes (rbe2d_profile_enable / _read)
 struct Profiler {
     int n = 0;                               // event pairs per class
+    uint32_t mask = ~0u;                     // classes timed
     std::vector<hipEvent_t> ev[RBE2D_PROF_SLOTS][2];
     int used[RBE2D_PROF_SLOTS] = {};
 };
@@ -248,11 +249,13 @@ int choose_ksplit(int64_t n_blocks, int P);
 // bracket a launch of kernel class `slot` with profiling events (no-op when off)
 inline void prof_begin(rbe2d_ctx *h, int slot, hipStream_t s) {
     Profiler &p = h->prof;
-    if (p.n > 0 && p.used[slot] < p.n) (void)hipEventRecord(p.ev[slot][0][p.used[slot]], s);
+    if (p.n > 0 && ((p.mask >> slot) & 1u) && p.used[slot] < p.n)
+        (void)hipEventRecord(p.ev[slot][0][p.used[slot]], s);
 }
 inline void prof_end(rbe2d_ctx *h, int slot, hipStream_t s) {
     Profiler &p = h->prof;
-    if (p.n > 0 && p.used[slot] < p.n) (void)hipEventRecord(p.ev[slot][1][p.used[slot]++], s);
+    if (p.n > 0 && ((p.mask >> slot) & 1u) && p.used[slot] < p.n)
+        (void)hipEventRecord(p.ev[slot][1][p.used[slot]++], s);
 }
 
 // Largest r in [0, n) with a[r] <= x, for a nondecreasing prefix array a[0..n].

@@ -25,7 +25,7 @@ EXPORTS = ("rbe2d_create", "rbe2d_destroy", "rbe2d_query", "rbe2d_draw_kset", "r
            "rbe2d_energy_backward", "rbe2d_md_run", "rbe2d_profile_enable", "rbe2d_profile_read",
            "rbe2d_check", "rbe2d_last_error", "rbe2d_batch_create", "rbe2d_query_system",
            "rbe2d_batch_forces", "rbe2d_batch_md_run", "rbe2d_autotune", "rbe2d_short_forces",
-           "rbe2d_md_run_ex", "rbe2d_suggest_params", "rbe2d_force_variance")
+           "rbe2d_md_run_ex", "rbe2d_suggest_params", "rbe2d_force_variance", "rbe2d_profile_classes")
 PROF_SLOTS = ("prep", "sf_pass", "assemble", "cell_build", "real_pairs", "force_scatter", "energy",
               "integrator", "ksample", "short_range", "add_real")
 
@@ -322,6 +322,13 @@ class Slab:
 
     def profile_enable(self, n_events):
         self._ok(lib().rbe2d_profile_enable(self._h, int(n_events)))
+
+    def profile_classes(self, names):
+        """Time only the named kernel classes (PROF_SLOTS) from now on."""
+        mask = 0
+        for n in names:
+            mask |= 1 << PROF_SLOTS.index(n)
+        self._ok(lib().rbe2d_profile_classes(self._h, ctypes.c_uint32(mask)))
 
     def profile_read(self):
         """{kernel class: (total ms, launches)} since the last read."""
