@@ -218,7 +218,7 @@ rbe2d_status setup_system(const rbe2d_params *pin, SysHost &sh) {
     d.ncx = ncx; d.ncy = ncy; d.ncz = ncz;
     d.hx = p.Lx / ncx; d.hy = p.Ly / ncy; d.hz = p.H / ncz;
     d.inv_hy = 1.0 / d.hy; d.inv_hz = 1.0 / d.hz;
-    d.inv_Lx = 1.0 / p.Lx; d.inv_Ly = 1.0 / p.Ly;
+    d.inv_Lx = 1.0 / p.Lx; d.inv_Ly = 1.0 / p.Ly; d.inv_Lz = 1.0 / d.Lz;
     // fixed-point frame of the FP32 pair kernel.  z (and every transformed
     // target height within r_c of the slab) lies in [-zoff, zspan - zoff);
     // the span exceeds twice any candidate |dz| <= r_c + hz <= r_c + H.

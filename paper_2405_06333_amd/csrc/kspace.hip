@@ -37,7 +37,7 @@ struct PrepArgs {
 
 template <bool FP32>
 __global__ __launch_bounds__(kBlock) void k_prep(PrepArgs a) {
-    __shared__ double sh[kBlock / 64];
+    __shared__ double sh[3][kBlock / 64];
     const int b = blockIdx.x;
     const int r = find_sys(a.lay.bbase, a.n_sys, b);
     const SysDesc &d = a.sys[r];
@@ -51,27 +51,33 @@ __global__ __launch_bounds__(kBlock) void k_prep(PrepArgs a) {
         const double x = a.pos[3 * g], y = a.pos[3 * g + 1], z = a.pos[3 * g + 2];
         qi = a.q[g];
         if (!(z > 0.0 && z < d.H)) atomicOr(a.err, 1);
-        fx = x / d.Lx; fx -= floor(fx);
-        fy = y / d.Ly; fy -= floor(fy);
-        fz = z / d.Lz;
+        fx = x * d.inv_Lx; fx -= floor(fx);
+        fy = y * d.inv_Ly; fy -= floor(fy);
+        fz = z * d.inv_Lz;
         sqz = qi * z; sq = qi; sq2 = qi * qi;
     }
     if (FP32) {
-        const double hx = rint(fx * d.scale_h) / d.scale_h;
-        const double hy = rint(fy * d.scale_h) / d.scale_h;
-        const double hz = rint(fz * d.scale_h) / d.scale_h;
+        // scale_h = 2^fh_bits: the split is exact
+        const double hx = ldexp(rint(fx * d.scale_h), -d.fh_bits);
+        const double hy = ldexp(rint(fy * d.scale_h), -d.fh_bits);
+        const double hz = ldexp(rint(fz * d.scale_h), -d.fh_bits);
         a.p32[2 * ii] = make_float4((float)hx, (float)(fx - hx), (float)hy, (float)(fy - hy));
         a.p32[2 * ii + 1] = make_float4((float)hz, (float)(fz - hz), (float)qi, 0.0f);
     } else {
         a.p64[ii] = make_double4(fx, fy, fz, qi);
     }
-    const double t0 = block_sum(sqz, sh);
-    const double t1 = block_sum(sq, sh);
-    const double t2 = block_sum(sq2, sh);
-    if (threadIdx.x == 0) {
-        a.bpart[4 * b] = t0;
-        a.bpart[4 * b + 1] = t1;
-        a.bpart[4 * b + 2] = t2;
+    // block sums of q z, q, q^2 (one barrier for the three)
+    sqz = wave_sum(sqz);
+    sq = wave_sum(sq);
+    sq2 = wave_sum(sq2);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) { sh[0][wid] = sqz; sh[1][wid] = sq; sh[2][wid] = sq2; }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        double t = 0.0;
+        for (int k = 0; k < kBlock / 64; k++) t += sh[threadIdx.x][k];
+        a.bpart[4 * b + threadIdx.x] = t;
+    } else if (threadIdx.x == 3) {
         a.bpart[4 * b + 3] = 0.0;
     }
 }
@@ -110,7 +116,13 @@ __global__ __launch_bounds__(kBlock) void k_scalars(ScalArgs a) {
     }
 }
 
+__global__ void k_ktable(const int32_t *kset, int n_sys, int P, int P_pad, float4 *kn32, double4 *kn64);
+
 hipError_t launch_prep(rbe2d_ctx *h, const double *pos, const double *q, hipStream_t s) {
+    // the k-vector table needs only the k-set: first, off the particles' path
+    const int nk = h->n_sys * h->P_pad;
+    hipLaunchKernelGGL(k_ktable, dim3((nk + 63) / 64), dim3(64), 0, s, h->w.kset, h->n_sys, h->P, h->P_pad,
+                       h->w.kn32, h->w.kn64);
     PrepArgs a;
     a.pos = pos; a.q = q; a.sys = h->w.sys; a.lay = h->w.lay; a.n_sys = h->n_sys;
     a.p32 = h->w.p32; a.p64 = h->w.p64; a.bpart = h->w.bpart; a.err = h->w.err;
@@ -376,9 +388,6 @@ int choose_tile(int64_t N, int n_kchunks) {
 
 hipError_t launch_kcoef_sf(rbe2d_ctx *h, hipStream_t s) {
     const bool fp32 = h->precision == RBE2D_PREC_FP32_PHASE;
-    const int nk = h->n_sys * h->P_pad;
-    hipLaunchKernelGGL(k_ktable, dim3((nk + 63) / 64), dim3(64), 0, s, h->w.kset, h->n_sys, h->P,
-                       h->P_pad, h->w.kn32, h->w.kn64);
     prof_begin(h, 1, s);
     if (h->n_tiles > 0) {
         const int tiles8 = (h->n_tiles + 7) / 8 * 8;
