@@ -393,19 +393,16 @@ __device__ __forceinline__ int wave_min(int v) {
 // each z-layer within r_c and each x-column, the sources lie in one
 // contiguous run of cells along y (two runs where the range wraps around the
 // periodic y boundary), culled to the y-extent the sphere of radius r_c
-// allows in that layer and column.  Pairs within r_c are appended to a
-// queue shared by the wave in LDS (compacted with a ballot prefix, tagged
-// with the target's lane) and evaluated 64 at a time, one per lane, so the
-// erfc/exp work runs with every lane busy whatever the spread of accepted
-// pairs over the targets; the results go to per-target LDS accumulators by
-// LDS atomic adds, which the owning lane folds into FP64 after each drain.  The FP64 variant reads 32-byte FP64 source records.  The FP32
-// variant reads 16-byte fixed-point records: a displacement is an exact
-// integer difference rounded once to FP32, so its error is one position
-// quantum (period / 2^32); pairs so close that this would matter (the closest
-// pairs dominate the force) are recomputed from the FP64 records.  It
-// evaluates erfc/exp and the per-drain partial sums in FP32 and accumulates
-// the drains in FP64.  The order of every sum is fixed by the data, so the
-// results are bitwise reproducible.
+// allows in that layer and column.  Pairs within r_c are queued and their
+// erfc/exp terms evaluated later in rounds (LaneRings for FP32, WaveQueue
+// for FP64, above).  The FP64 variant reads 32-byte FP64 source records.
+// The FP32 variant reads 16-byte fixed-point records: a displacement is an
+// exact integer difference rounded once to FP32, so its error is one
+// position quantum (period / 2^32); pairs so close that this would matter
+// (the closest pairs dominate the force) are recomputed from the FP64
+// records.  It evaluates erfc/exp and the per-drain partial sums in FP32 and
+// accumulates the drains in FP64.  The order of every sum is fixed by the
+// data, so the results are bitwise reproducible.
 template <int QW, int U, bool DG>
 __device__ WaveQueue<QW, U, DG> make_wave_queue(unsigned char *lds, int tid) {
     const int wid = tid / kWave, lane = tid % kWave;
