@@ -587,3 +587,22 @@ def test_force_variance_estimate_is_unbiased(orc, gammas, M):
     # and the per-k terms add up to the oracle's k-space force
     _, F, *_ = orc.kspace(sl, pos, q, n, c)
     assert np.abs(Fs[-1] - F).max() < 1e-12 * np.abs(F).max()
+
+
+@pytest.mark.parametrize("gammas,M", [((0.0, 0.0), 0), ((0.8, -0.6), 4)])
+def test_force_variance_is_flat_in_Lz(orc, gammas, M):
+    """Theorem 2.2: with alpha fixed, the force variance does not grow with
+    the extended height once L_z is past the image layers (S and V both scale
+    with L_z, and the k_z sum becomes an integral; the k_z = 0 plane leaves an
+    O(1/L_z) remainder: 0.55 % between L_z = 12 H and 48 H here).  A wrong power of V or S
+    would change it by factors of 2 and 4."""
+    rng = np.random.default_rng(0)
+    N = 24
+    pos = np.column_stack([rng.uniform(0, 8, N), rng.uniform(0, 8, N), rng.uniform(0.3, 3.7, N)])
+    q = np.where(np.arange(N) < N // 2, 1.0, -1.0)
+    v = {}
+    for Lz in (48.0, 96.0, 192.0):
+        sl = orc.Slab(Lx=8, Ly=8, H=4, g_top=gammas[0], g_bot=gammas[1], alpha=0.8, rc=3.5, M=M, P=10, Lz=Lz)
+        v[Lz] = orc.force_variance_exact(sl, pos, q, 10)
+    for Lz in (48.0, 96.0):
+        assert np.abs(v[Lz] / v[192.0] - 1).max() < 1e-2, (Lz, np.abs(v[Lz] / v[192.0] - 1).max())
