@@ -222,12 +222,24 @@ __device__ __forceinline__ void pair_terms(float r2, float alpha, float c2a, flo
     *ec = v;
     *fs = fmaf(c2a, e, v) * (rinv * rinv);
 }
-__device__ __forceinline__ void pair_terms(double r2, double alpha, double c2a, double *ec, double *fs) {
+// FP64: erfc(x) = exp(-x^2) erfcx(x) with the fitted erfcx (relative error
+// below 2e-13), sharing the exponential of the force term; for x beyond the
+// fitted range erfc(x) < 1.2e-29 and the term is dropped.
+// The coefficients are read from LDS (`coef`, a copy of rbe2d_erfcx64_a): as
+// FP64 literals they would hold 32 registers for the whole kernel.
+__device__ __forceinline__ void pair_terms(double r2, double alpha, double c2a, double *ec, double *fs,
+                                           const double *coef) {
     const double d = sqrt(r2);
+    const double rinv2 = 1.0 / r2;
     const double e = exp(-alpha * alpha * r2);
-    const double v = erfc(alpha * d) / d;
+    const double x = alpha * d;
+    const double t = 1.0 / fma(RBE2D_ERFCX64_P, x, 1.0);
+    double p = coef[RBE2D_ERFCX64_DEG - 1];
+#pragma unroll
+    for (int k = RBE2D_ERFCX64_DEG - 2; k >= 0; k--) p = fma(p, t, coef[k]);
+    const double v = x < RBE2D_ERFCX_XMAX ? e * (p * t) * (d * rinv2) : 0.0;
     *ec = v;
-    *fs = fma(c2a, e, v) / r2;
+    *fs = fma(c2a, e, v) * rinv2;
 }
 
 // ---------------------------------------------------------------------------
@@ -326,8 +338,10 @@ struct WaveQueue : TargetSums<DG> {
     double4 *ent;         // [QW] entries of this wave
     unsigned char *own;   // [QW] owning lane
     double *acc;          // [4][64] per-target sums
+    const double *coef;   // erfcx fit coefficients (LDS)
     int lane, qn = 0;     // qn: entries queued (wave-uniform)
-    __device__ WaveQueue(double4 *e, unsigned char *o, double *a, int l) : ent(e), own(o), acc(a), lane(l) {
+    __device__ WaveQueue(double4 *e, unsigned char *o, double *a, const double *c, int l)
+        : ent(e), own(o), acc(a), coef(c), lane(l) {
         for (int c = 0; c < 4; c++) acc[c * kWave + lane] = 0.0;
     }
     __device__ void family(double w, double zsign, double dwt, double dwb) {
@@ -352,7 +366,7 @@ struct WaveQueue : TargetSums<DG> {
             const int o = own[base + lane];
             const double r2 = e.x * e.x + e.y * e.y + e.z * e.z;
             double ec, fs;
-            pair_terms(r2, alpha, c2a, &ec, &fs);
+            pair_terms(r2, alpha, c2a, &ec, &fs, coef);
             const double qf = e.w * fs;
             atomicAdd(&acc[o], qf * e.x);
             atomicAdd(&acc[kWave + o], qf * e.y);
@@ -404,12 +418,12 @@ __device__ __forceinline__ int wave_min(int v) {
 // accumulates the drains in FP64.  The order of every sum is fixed by the
 // data, so the results are bitwise reproducible.
 template <int QW, int U, bool DG>
-__device__ WaveQueue<QW, U, DG> make_wave_queue(unsigned char *lds, int tid) {
+__device__ WaveQueue<QW, U, DG> make_wave_queue(unsigned char *lds, int tid, const double *coef) {
     const int wid = tid / kWave, lane = tid % kWave;
     double4 *ent = reinterpret_cast<double4 *>(lds) + wid * QW;
     double *acc = reinterpret_cast<double *>(lds + (kBlock / kWave) * QW * sizeof(double4)) + wid * 4 * kWave;
     unsigned char *own = lds + (kBlock / kWave) * (QW * sizeof(double4) + 4 * kWave * sizeof(double)) + wid * QW;
-    return WaveQueue<QW, U, DG>(ent, own, acc, lane);
+    return WaveQueue<QW, U, DG>(ent, own, acc, coef, lane);
 }
 
 template <bool FP32, bool WANT_DG, bool ISO>
@@ -425,6 +439,11 @@ __global__ __launch_bounds__(kBlock) RBE2D_REAL_OCC void k_real(RealArgs a) {
     constexpr size_t kLds = FP32 ? sizeof(float4) * kRingQ * kBlock
                                  : NW * (kWaveQ * (sizeof(double4) + 1) + 4 * kWave * sizeof(double));
     __shared__ __align__(16) unsigned char lds[kLds];
+    __shared__ double coef64[FP32 ? 1 : RBE2D_ERFCX64_DEG];
+    if (!FP32) {
+        if (threadIdx.x < RBE2D_ERFCX64_DEG) coef64[threadIdx.x] = rbe2d_erfcx64_a[threadIdx.x];
+        __syncthreads();
+    }
     const double4 *src = a.src;
     const int tid = threadIdx.x;
     // Blocks are dealt round-robin to the 8 XCDs: give each XCD a contiguous
@@ -458,7 +477,7 @@ __global__ __launch_bounds__(kBlock) RBE2D_REAL_OCC void k_real(RealArgs a) {
     const T c2a = (T)(1.1283791670955126 * d.alpha);
     Queue qu = [&]() {
         if constexpr (FP32) return Queue(lds, tid, d);
-        else return make_wave_queue<kWaveQ, U, WANT_DG>(lds, tid);
+        else return make_wave_queue<kWaveQ, U, WANT_DG>(lds, tid, coef64);
     }();
     for (int f = 0; f <= d.nfam; f++) {
         double sz = 1.0, czs = 0.0, w = 1.0, zsign = 1.0, dwt = 0.0, dwb = 0.0;
