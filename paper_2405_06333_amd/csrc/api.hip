@@ -619,20 +619,21 @@ rbe2d_status md_step(rbe2d_ctx *h, double *pos, double *vel, const double *q, do
 }
 
 // Force evaluation and closing kick of one plain velocity-Verlet step at
-// the current positions (whose k-set is drawn).  The k-space chain runs on
-// the side stream, real space on s.  After the forces, either the closing
-// half kick (last step of the run) or the closing and next opening half
-// kicks with the next drift in one pass.  Meanwhile the side stream draws
-// the next step's k-set (device step counter: incremented there first).
-// The next step's fork orders that draw before the next k-space chain; a
-// captured step joins it back explicitly (join_tail).
+// the current positions (whose k-set is drawn and whose k-space particle
+// records the preceding MD pass wrote).  The k-space chain runs on the side
+// stream, real space on s.  After the forces, either the closing half kick
+// (last step of the run) or one pass with the closing and next opening half
+// kicks, the next drift and the next records.  Meanwhile the side stream
+// draws the next step's k-set (device step counter: incremented there
+// first).  The next step's fork orders that draw before the next k-space
+// chain; a captured step joins it back explicitly (join_tail).
 rbe2d_status vv_unit(rbe2d_ctx *h, double *pos, double *vel, const double *q, double *F, double dt, double zlo,
                      double zhi_from_top, uint64_t seed, int64_t step, bool dev_step, bool last, bool join_tail,
                      hipStream_t s) {
     hipStream_t ks = h->side;
     RBE2D_TRY(h, hipEventRecord(h->fork_ev, s), "fork event");
     RBE2D_TRY(h, hipStreamWaitEvent(ks, h->fork_ev, 0), "fork wait");
-    RBE2D_TRY(h, launch_prep(h, pos, q, ks), "prep launch");
+    RBE2D_TRY(h, launch_ktable_scalars(h, ks), "k-table launch");
     RBE2D_TRY(h, launch_kcoef_sf(h, ks), "structure-factor launch");
     RBE2D_TRY(h, launch_kforce(h, pos, q, F, nullptr, RBE2D_KSPACE | RBE2D_IBC, false, false, false, nullptr, ks),
               "force launch");
@@ -643,7 +644,7 @@ rbe2d_status vv_unit(rbe2d_ctx *h, double *pos, double *vel, const double *q, do
         if (dev_step) RBE2D_TRY(h, launch_step_inc(h, ks), "md step counter");
         RBE2D_TRY(h, launch_sample(h, seed, (uint64_t)(step + 1) * (uint64_t)h->n_sys, dev_step ? h->w.step : nullptr,
                                    ks), "md sample");
-        RBE2D_TRY(h, launch_md_leapfrog(h, pos, vel, F, dt, zlo, zhi_from_top, s), "md leapfrog");
+        RBE2D_TRY(h, launch_prep_md(h, pos, vel, F, q, dt, zlo, zhi_from_top, true, s), "md leapfrog");
     } else {
         RBE2D_TRY(h, launch_add_real(h, F, vel, 0.5 * dt, s), "real-space add");
     }
@@ -661,7 +662,7 @@ rbe2d_status vv_unit(rbe2d_ctx *h, double *pos, double *vel, const double *q, do
 rbe2d_status vv_run(rbe2d_ctx *h, double *pos, double *vel, const double *q, double *F, double dt, double zlo,
                     double zhi_from_top, uint64_t seed, int64_t step0, int32_t n_steps, bool use_graph,
                     hipStream_t s) {
-    RBE2D_TRY(h, launch_md_kick_drift(h, pos, vel, F, dt, zlo, zhi_from_top, s), "md drift");
+    RBE2D_TRY(h, launch_prep_md(h, pos, vel, F, q, dt, zlo, zhi_from_top, false, s), "md drift");
     RBE2D_TRY(h, launch_sample(h, seed, (uint64_t)step0 * (uint64_t)h->n_sys, nullptr, s), "md sample");
     int32_t it = 0;
     if (use_graph) {

@@ -63,6 +63,24 @@ __device__ __forceinline__ double sin_rev64(double r) {
     return (((long long)kd) & 1) ? -s : s;
 }
 
+// x += dt v, then x, y wrapped into the box and z folded into [zlo, zhi]:
+// every crossing of a wall is a specular reflection (v_z flips)
+__device__ __forceinline__ void drift_fold(const SysDesc &d, double dt, double zlo, double zhi_from_top, double v[3],
+                                           double r[3]) {
+    for (int c = 0; c < 3; c++) r[c] = fma(dt, v[c], r[c]);
+    r[0] -= d.Lx * floor(r[0] / d.Lx);
+    r[1] -= d.Ly * floor(r[1] / d.Ly);
+    const double zhi = d.H - zhi_from_top;
+    const double W = zhi - zlo;
+    const double u = r[2] - zlo;
+    const double m = floor(u / W);
+    const double rem = u - m * W;
+    const bool odd = fmod(fabs(m), 2.0) == 1.0;
+    r[2] = odd ? zhi - rem : zlo + rem;
+    if (odd) v[2] = -v[2];
+    r[2] = fmin(fmax(r[2], zlo), zhi);
+}
+
 __device__ __forceinline__ float fractf(float x) { return __builtin_amdgcn_fractf(x); }
 __device__ __forceinline__ float sin_rev(float x) { return __builtin_amdgcn_sinf(x); }
 __device__ __forceinline__ float cos_rev(float x) { return __builtin_amdgcn_cosf(x); }

@@ -33,9 +33,18 @@ struct PrepArgs {
     double4 *p64;
     double *bpart;
     int *err;
+    // MD update first (MD > 0): positions and velocities are updated in place
+    double *pos_md, *vel;
+    const double *F;
+    const double4 *freal;       // MD == 2: the pair kernel's part of the force
+    double dt, zlo, zhi_from_top;
 };
 
-template <bool FP32>
+// MD: 0 none; 1 opening half kick with F and drift; 2 closing half kick and
+// the next opening half kick, both with F + freal (the same force, the same
+// roundings as two separate kicks), and drift.  Then the k-space particle
+// records of the (new) positions and the block sums of the IBC.
+template <bool FP32, int MD>
 __global__ __launch_bounds__(kBlock) void k_prep(PrepArgs a) {
     __shared__ double sh[3][kBlock / 64];
     const int b = blockIdx.x;
@@ -48,7 +57,28 @@ __global__ __launch_bounds__(kBlock) void k_prep(PrepArgs a) {
     double fx = 0, fy = 0, fz = 0, qi = 0;
     if (iloc < Nr) {
         const int64_t g = (int64_t)a.lay.off[r] + iloc;      // caller index
-        const double x = a.pos[3 * g], y = a.pos[3 * g + 1], z = a.pos[3 * g + 2];
+        double x, y, z;
+        if (MD > 0) {
+            double v[3], rr[3], add[3] = {0.0, 0.0, 0.0};
+            if (MD == 2) {
+                const double4 fr = a.freal[g];
+                add[0] = fr.x; add[1] = fr.y; add[2] = fr.z;
+            }
+            for (int c = 0; c < 3; c++) {
+                const double f = MD == 2 ? a.F[3 * g + c] + add[c] : a.F[3 * g + c];
+                v[c] = fma(0.5 * a.dt, f, a.vel[3 * g + c]);
+                if (MD == 2) v[c] = fma(0.5 * a.dt, f, v[c]);
+                rr[c] = a.pos_md[3 * g + c];
+            }
+            drift_fold(d, a.dt, a.zlo, a.zhi_from_top, v, rr);
+            for (int c = 0; c < 3; c++) {
+                a.vel[3 * g + c] = v[c];
+                a.pos_md[3 * g + c] = rr[c];
+            }
+            x = rr[0]; y = rr[1]; z = rr[2];
+        } else {
+            x = a.pos[3 * g]; y = a.pos[3 * g + 1]; z = a.pos[3 * g + 2];
+        }
         qi = a.q[g];
         if (!(z > 0.0 && z < d.H)) atomicOr(a.err, 1);
         fx = x * d.inv_Lx; fx -= floor(fx);
@@ -118,24 +148,60 @@ __global__ __launch_bounds__(kBlock) void k_scalars(ScalArgs a) {
 
 __global__ void k_ktable(const int32_t *kset, int n_sys, int P, int P_pad, float4 *kn32, double4 *kn64);
 
-hipError_t launch_prep(rbe2d_ctx *h, const double *pos, const double *q, hipStream_t s) {
-    // the k-vector table needs only the k-set: first, off the particles' path
+static PrepArgs prep_args(rbe2d_ctx *h, const double *pos, const double *q) {
+    PrepArgs a{};
+    a.pos = pos; a.q = q; a.sys = h->w.sys; a.lay = h->w.lay; a.n_sys = h->n_sys;
+    a.p32 = h->w.p32; a.p64 = h->w.p64; a.bpart = h->w.bpart; a.err = h->w.err;
+    return a;
+}
+
+static void launch_ktable(rbe2d_ctx *h, hipStream_t s) {
     const int nk = h->n_sys * h->P_pad;
     hipLaunchKernelGGL(k_ktable, dim3((nk + 63) / 64), dim3(64), 0, s, h->w.kset, h->n_sys, h->P, h->P_pad,
                        h->w.kn32, h->w.kn64);
-    PrepArgs a;
-    a.pos = pos; a.q = q; a.sys = h->w.sys; a.lay = h->w.lay; a.n_sys = h->n_sys;
-    a.p32 = h->w.p32; a.p64 = h->w.p64; a.bpart = h->w.bpart; a.err = h->w.err;
-    prof_begin(h, 0, s);
-    if (h->n_blocks > 0) {
-        if (h->precision == RBE2D_PREC_FP32_PHASE)
-            hipLaunchKernelGGL(k_prep<true>, dim3(h->n_blocks), dim3(kBlock), 0, s, a);
-        else
-            hipLaunchKernelGGL(k_prep<false>, dim3(h->n_blocks), dim3(kBlock), 0, s, a);
-    }
+}
+
+static void launch_scalars(rbe2d_ctx *h, hipStream_t s) {
     ScalArgs b;
     b.bpart = h->w.bpart; b.sys = h->w.sys; b.lay = h->w.lay; b.scal = h->w.scal;
     hipLaunchKernelGGL(k_scalars, dim3(h->n_sys), dim3(kBlock), 0, s, b);
+}
+
+template <int MD>
+static void launch_prep_kernel(rbe2d_ctx *h, const PrepArgs &a, hipStream_t s) {
+    if (h->n_blocks <= 0) return;
+    if (h->precision == RBE2D_PREC_FP32_PHASE)
+        hipLaunchKernelGGL((k_prep<true, MD>), dim3(h->n_blocks), dim3(kBlock), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_prep<false, MD>), dim3(h->n_blocks), dim3(kBlock), 0, s, a);
+}
+
+hipError_t launch_prep(rbe2d_ctx *h, const double *pos, const double *q, hipStream_t s) {
+    // the k-vector table needs only the k-set: first, off the particles' path
+    launch_ktable(h, s);
+    prof_begin(h, 0, s);
+    launch_prep_kernel<0>(h, prep_args(h, pos, q), s);
+    launch_scalars(h, s);
+    prof_end(h, 0, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_prep_md(rbe2d_ctx *h, double *pos, double *vel, const double *F, const double *q, double dt,
+                          double zlo, double zhi_from_top, bool with_real, hipStream_t s) {
+    PrepArgs a = prep_args(h, pos, q);
+    a.pos_md = pos; a.vel = vel; a.F = F; a.freal = h->w.freal;
+    a.dt = dt; a.zlo = zlo; a.zhi_from_top = zhi_from_top;
+    prof_begin(h, 7, s);
+    if (with_real) launch_prep_kernel<2>(h, a, s);
+    else launch_prep_kernel<1>(h, a, s);
+    prof_end(h, 7, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_ktable_scalars(rbe2d_ctx *h, hipStream_t s) {
+    launch_ktable(h, s);
+    prof_begin(h, 0, s);
+    launch_scalars(h, s);
     prof_end(h, 0, s);
     return hipGetLastError();
 }

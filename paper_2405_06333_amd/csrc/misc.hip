@@ -154,24 +154,6 @@ hipError_t launch_step_inc(rbe2d_ctx *h, hipStream_t s) {
 // zlo and H - zhi_from_top of each system
 // ---------------------------------------------------------------------------
 
-// x += dt v, then x, y wrapped into the box and z folded into [zlo, zhi]:
-// every crossing of a wall is a specular reflection (v_z flips)
-__device__ __forceinline__ void drift_fold(const SysDesc &d, double dt, double zlo, double zhi_from_top, double v[3],
-                                           double r[3]) {
-    for (int c = 0; c < 3; c++) r[c] = fma(dt, v[c], r[c]);
-    r[0] -= d.Lx * floor(r[0] / d.Lx);
-    r[1] -= d.Ly * floor(r[1] / d.Ly);
-    const double zhi = d.H - zhi_from_top;
-    const double W = zhi - zlo;
-    const double u = r[2] - zlo;
-    const double m = floor(u / W);
-    const double rem = u - m * W;
-    const bool odd = fmod(fabs(m), 2.0) == 1.0;
-    r[2] = odd ? zhi - rem : zlo + rem;
-    if (odd) v[2] = -v[2];
-    r[2] = fmin(fmax(r[2], zlo), zhi);
-}
-
 __global__ __launch_bounds__(kBlock) void k_kick_drift(const SysDesc *sys, Layout lay, int n_sys, int n_total,
                                                        double *pos, double *vel, const double *F, double dt,
                                                        double zlo, double zhi_from_top) {
@@ -182,34 +164,6 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(const SysDesc *sys, Layou
     double v[3], r[3];
     for (int c = 0; c < 3; c++) {
         v[c] = fma(0.5 * dt, F[3 * i + c], vel[3 * i + c]);
-        r[c] = pos[3 * i + c];
-    }
-    drift_fold(d, dt, zlo, zhi_from_top, v, r);
-    for (int c = 0; c < 3; c++) {
-        vel[3 * i + c] = v[c];
-        pos[3 * i + c] = r[c];
-    }
-}
-
-// Between two velocity-Verlet steps: the closing half kick of one step and
-// the opening half kick of the next use the same force, F (k-space, IBC)
-// plus the pair kernel's real-space part, and are followed by the next
-// drift.  The same roundings as the separate half kicks; F is not stored
-// (the next force pass overwrites it).
-__global__ __launch_bounds__(kBlock) void k_leapfrog(const SysDesc *sys, Layout lay, int n_sys, int n_total,
-                                                     double *pos, double *vel, const double *F,
-                                                     const double4 *freal, double dt, double zlo,
-                                                     double zhi_from_top) {
-    const int g = blockIdx.x * kBlock + threadIdx.x;
-    if (g >= n_total) return;
-    const SysDesc &d = sys[find_sys(lay.off, n_sys, g)];
-    const int64_t i = g;
-    const double4 fr = freal[i];
-    const double add[3] = {fr.x, fr.y, fr.z};
-    double v[3], r[3];
-    for (int c = 0; c < 3; c++) {
-        const double f = F[3 * i + c] + add[c];
-        v[c] = fma(0.5 * dt, f, fma(0.5 * dt, f, vel[3 * i + c]));
         r[c] = pos[3 * i + c];
     }
     drift_fold(d, dt, zlo, zhi_from_top, v, r);
@@ -288,17 +242,6 @@ hipError_t launch_md_kick_drift(rbe2d_ctx *h, double *pos, double *vel, const do
     prof_begin(h, 7, s);
     hipLaunchKernelGGL(k_kick_drift, dim3((unsigned)((h->n_total + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
                        h->w.sys, h->w.lay, h->n_sys, (int)h->n_total, pos, vel, F, dt, zlo, zhi_from_top);
-    prof_end(h, 7, s);
-    return hipGetLastError();
-}
-
-hipError_t launch_md_leapfrog(rbe2d_ctx *h, double *pos, double *vel, const double *F, double dt, double zlo,
-                              double zhi_from_top, hipStream_t s) {
-    if (h->n_total == 0) return hipSuccess;
-    prof_begin(h, 7, s);
-    hipLaunchKernelGGL(k_leapfrog, dim3((unsigned)((h->n_total + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
-                       h->w.sys, h->w.lay, h->n_sys, (int)h->n_total, pos, vel, F, h->w.freal, dt, zlo,
-                       zhi_from_top);
     prof_end(h, 7, s);
     return hipGetLastError();
 }

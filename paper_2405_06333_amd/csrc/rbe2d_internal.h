@@ -237,8 +237,14 @@ hipError_t launch_sample(rbe2d_ctx *h, uint64_t seed, uint64_t stream_id, const 
 hipError_t launch_md_kick_drift(rbe2d_ctx *h, double *pos, double *vel, const double *F, double dt,
                                 double zlo, double zhi_from_top, hipStream_t s);
 hipError_t launch_md_kick(rbe2d_ctx *h, double *vel, const double *F, double dt, hipStream_t s);
-hipError_t launch_md_leapfrog(rbe2d_ctx *h, double *pos, double *vel, const double *F, double dt, double zlo,
-                              double zhi_from_top, hipStream_t s);
+// MD update fused with the k-space particle preparation (the side stream
+// then runs only launch_ktable_scalars): the opening half kick and drift
+// with F (with_real false), or, between two velocity-Verlet steps, the
+// closing and next opening half kicks with F plus the real-space part and
+// the drift (with_real true)
+hipError_t launch_prep_md(rbe2d_ctx *h, double *pos, double *vel, const double *F, const double *q, double dt,
+                          double zlo, double zhi_from_top, bool with_real, hipStream_t s);
+hipError_t launch_ktable_scalars(rbe2d_ctx *h, hipStream_t s);
 hipError_t launch_set_step(rbe2d_ctx *h, long long value, hipStream_t s);
 hipError_t launch_step_inc(rbe2d_ctx *h, hipStream_t s);
 hipError_t launch_fill(void *p, int64_t nbytes_multiple_of_4, hipStream_t s);
