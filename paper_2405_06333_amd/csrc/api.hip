@@ -599,11 +599,11 @@ rbe2d_status md_step(rbe2d_ctx *h, double *pos, double *vel, const double *q, do
                      double zlo, double zhi_from_top, uint64_t seed, int64_t step, bool dev_step,
                      const MdExtra *mx, hipStream_t s) {
     const uint64_t sbase = (uint64_t)step * (uint64_t)h->n_sys;
+    // (without mx this runs only for an empty layout: plain velocity Verlet
+    // with particles takes vv_run)
     if (mx)
         RBE2D_TRY(h, launch_md_kick_drift_langevin(h, pos, vel, F, dt, *mx, seed, sbase,
                                                    dev_step ? h->w.step : nullptr, s), "md drift");
-    else
-        RBE2D_TRY(h, launch_md_kick_drift(h, pos, vel, F, dt, zlo, zhi_from_top, s), "md drift");
     RBE2D_TRY(h, launch_sample(h, seed, sbase, dev_step ? h->w.step : nullptr, s), "md sample");
     const bool shortr = mx && mx->short_on();
     // the closing half kick is fused into the force pass unless short-range

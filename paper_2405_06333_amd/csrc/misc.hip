@@ -150,28 +150,10 @@ hipError_t launch_step_inc(rbe2d_ctx *h, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// velocity Verlet with unit masses; x, y periodic, z reflected at the walls
-// zlo and H - zhi_from_top of each system
+// integrators with unit masses; x, y periodic, z reflected at the walls.
+// The plain velocity-Verlet update is fused into the k-space preparation
+// (k_prep with MD > 0); the Langevin one and the half kick are here.
 // ---------------------------------------------------------------------------
-
-__global__ __launch_bounds__(kBlock) void k_kick_drift(const SysDesc *sys, Layout lay, int n_sys, int n_total,
-                                                       double *pos, double *vel, const double *F, double dt,
-                                                       double zlo, double zhi_from_top) {
-    const int g = blockIdx.x * kBlock + threadIdx.x;
-    if (g >= n_total) return;
-    const SysDesc &d = sys[find_sys(lay.off, n_sys, g)];
-    const int64_t i = g;
-    double v[3], r[3];
-    for (int c = 0; c < 3; c++) {
-        v[c] = fma(0.5 * dt, F[3 * i + c], vel[3 * i + c]);
-        r[c] = pos[3 * i + c];
-    }
-    drift_fold(d, dt, zlo, zhi_from_top, v, r);
-    for (int c = 0; c < 3; c++) {
-        vel[3 * i + c] = v[c];
-        pos[3 * i + c] = r[c];
-    }
-}
 
 // BAOAB up to the force evaluation (Langevin equation, unit masses):
 // v += dt/2 F; r += dt/2 v; v = c1 v + c2 xi; r += dt/2 v; wrap / reflect.
@@ -234,16 +216,6 @@ __global__ __launch_bounds__(kBlock) void k_kick(int64_t n3, double *vel, const 
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n3) return;
     vel[i] = fma(0.5 * dt, F[i], vel[i]);
-}
-
-hipError_t launch_md_kick_drift(rbe2d_ctx *h, double *pos, double *vel, const double *F, double dt,
-                                double zlo, double zhi_from_top, hipStream_t s) {
-    if (h->n_total == 0) return hipSuccess;
-    prof_begin(h, 7, s);
-    hipLaunchKernelGGL(k_kick_drift, dim3((unsigned)((h->n_total + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
-                       h->w.sys, h->w.lay, h->n_sys, (int)h->n_total, pos, vel, F, dt, zlo, zhi_from_top);
-    prof_end(h, 7, s);
-    return hipGetLastError();
 }
 
 hipError_t launch_md_kick(rbe2d_ctx *h, double *vel, const double *F, double dt, hipStream_t s) {

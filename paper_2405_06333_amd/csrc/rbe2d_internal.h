@@ -234,8 +234,6 @@ hipError_t launch_energy(rbe2d_ctx *h, double *energy, uint32_t flags, const dou
                          hipStream_t s);
 hipError_t launch_sample(rbe2d_ctx *h, uint64_t seed, uint64_t stream_id, const long long *dev_step,
                          hipStream_t s);
-hipError_t launch_md_kick_drift(rbe2d_ctx *h, double *pos, double *vel, const double *F, double dt,
-                                double zlo, double zhi_from_top, hipStream_t s);
 hipError_t launch_md_kick(rbe2d_ctx *h, double *vel, const double *F, double dt, hipStream_t s);
 // MD update fused with the k-space particle preparation (the side stream
 // then runs only launch_ktable_scalars): the opening half kick and drift
