@@ -28,6 +28,9 @@
 #ifndef RBE2D_ROUND_MIN
 #define RBE2D_ROUND_MIN 40    // keep draining while this many lanes hold pairs
 #endif
+#ifndef RBE2D_REAL_CHUNKS
+#define RBE2D_REAL_CHUNKS 8   // contiguous target chunks per XCD
+#endif
 #ifdef RBE2D_REAL_WAVES_PER_EU  // occupancy hint for the pair kernel (register budget)
 #define RBE2D_REAL_OCC __attribute__((amdgpu_waves_per_eu(RBE2D_REAL_WAVES_PER_EU, 8)))
 #else
@@ -192,7 +195,7 @@ struct RealArgs {
     const Family *fam;          // kMaxFamilies per system
     Layout lay;
     int n_sys, n_waves;         // n_waves: padded real-space waves of all systems
-    int nblocks;                // logical blocks (the grid is rounded up to a multiple of 8)
+    int nblocks;                // logical blocks (the grid is rounded up to 8 * RBE2D_REAL_CHUNKS chunks)
     double4 *freal;
     double2 *dgreal;
     double *rpart;              // per wave
@@ -209,18 +212,33 @@ template <bool FP32> struct RealTypes;
 template <> struct RealTypes<true> { using T = float; using V4 = float4; static constexpr int U = RBE2D_REAL_U32; };
 template <> struct RealTypes<false> { using T = double; using V4 = double4; static constexpr int U = 2; };
 
-// erfc(alpha d)/d (ec) and the radial force factor fs = [erfc(a d)/d + 2a/sqrt(pi) e^{-a^2 d^2}]/d^2
-__device__ __forceinline__ void pair_terms(float r2, float alpha, float c2a, float *ec, float *fs) {
+// Constants of the FP32 pair terms in the units of the displacements: with
+// displacements in units u (r = u rq), ec and fs below come out as u erfc(a r)/r
+// and u^3 [erfc(a r)/r + 2a/sqrt(pi) e^{-a^2 r^2}]/r^2; the sums are rescaled
+// by 1/u and 1/u^2 when they are folded into FP64.
+struct PairConst32 {
+    float ce;    // -a^2 u^2 log2(e): exp(-a^2 r^2) = 2^(ce rq^2)
+    float cpx;   // p a u: the fit's argument p a r = cpx rq
+    float c2a;   // 2a/sqrt(pi) u
+    double fscale, pscale;   // 1/u^2 (forces), 1/u (potential)
+    __device__ PairConst32(double alpha, double u)
+        : ce((float)(-alpha * alpha * u * u * 1.4426950408889634)), cpx((float)(RBE2D_ERFCX_P * alpha * u)),
+          c2a((float)(1.1283791670955126 * alpha * u)), fscale(1.0 / (u * u)), pscale(1.0 / u) {}
+};
+
+// erfc(a r)/r (ec) and the radial force factor fs = [erfc(a r)/r + 2a/sqrt(pi)
+// e^{-a^2 r^2}]/r^2 from rq^2, both in the units of PairConst32; erfc(x) =
+// e^{-x^2} t P7(t), t = 1/(1 + p x), the fitted erfcx.
+__device__ __forceinline__ void pair_terms(float r2, const PairConst32 &c, float *ec, float *fs) {
     const float rinv = __builtin_amdgcn_rsqf(r2);
-    const float x = alpha * r2 * rinv;
-    const float e = __builtin_amdgcn_exp2f(-(alpha * alpha * 1.4426950408889634f) * r2);
-    const float t = __builtin_amdgcn_rcpf(fmaf(RBE2D_ERFCX_P, x, 1.0f));
+    const float e = __builtin_amdgcn_exp2f(c.ce * r2);
+    const float t = __builtin_amdgcn_rcpf(fmaf(c.cpx, r2 * rinv, 1.0f));
     float p = rbe2d_erfcx_a[RBE2D_ERFCX_DEG - 1];
 #pragma unroll
     for (int k = RBE2D_ERFCX_DEG - 2; k >= 0; k--) p = fmaf(p, t, rbe2d_erfcx_a[k]);
     const float v = e * p * t * rinv;
     *ec = v;
-    *fs = fmaf(c2a, e, v) * (rinv * rinv);
+    *fs = fmaf(c.c2a, e, v) * (rinv * rinv);
 }
 // FP64: erfc(x) = exp(-x^2) erfcx(x) with the fitted erfcx (relative error
 // below 2e-13), sharing the exponential of the force term; for x beyond the
@@ -258,8 +276,9 @@ template <bool DG>
 struct TargetSums {
     double fx = 0, fy = 0, fz = 0, phi = 0, dpt = 0, dpb = 0;
     double wxy = 1, wz = 1, wp = 1, wt = 0, wb = 0;
-    __device__ void family(double w, double zsign, double dwt, double dwb, double scale) {
-        wxy = w * scale; wz = w * zsign * scale; wp = w; wt = dwt; wb = dwb;
+    // fscale, pscale: unit conversions of the force and potential sums
+    __device__ void family(double w, double zsign, double dwt, double dwb, double fscale, double pscale) {
+        wxy = w * fscale; wz = w * zsign * fscale; wp = w * pscale; wt = dwt * pscale; wb = dwb * pscale;
     }
     __device__ void add(double sx, double sy, double sz, double sp) {
         fx = fma(sx, wxy, fx); fy = fma(sy, wxy, fy); fz = fma(sz, wz, fz); phi = fma(sp, wp, phi);
@@ -271,43 +290,39 @@ struct TargetSums {
 // entry of every lane that holds one; the FP32 sums of a drain (at most Q
 // pairs per lane) are folded into FP64.  Cheap routing (every result stays in
 // its lane) at the price of idle lanes in the rounds.  The lane's read and
-// write positions are kept as byte offsets into the rings (slot-major, one
-// 16-byte entry per thread and slot).  ISO: entries hold displacements in
-// units of the isotropic fixed-point frame; r^2 is scaled when a pair is
-// evaluated and the force sums when a drain is folded.
+// write positions are byte counters into the slot-major rings (one 16-byte
+// entry per thread and slot), masked only to form an address; their
+// difference is the fill.  ISO: entries hold displacements in units of the
+// isotropic fixed-point frame and the pair terms are evaluated in those units.
 template <int Q, int U, bool ISO, bool DG>
 struct LaneRings : TargetSums<DG> {
     static constexpr int kRoundMin = RBE2D_ROUND_MIN;   // keep draining while this many lanes hold pairs
-    static constexpr int kSlot = kBlock * (int)sizeof(float4);
-    static constexpr int kMask = Q * kSlot - 1;         // Q * kSlot is a power of two
+    static constexpr uint32_t kSlot = kBlock * (uint32_t)sizeof(float4);
+    static constexpr uint32_t kMask = Q * kSlot - 1;    // Q * kSlot is a power of two
+    static constexpr uint32_t kRoom = (Q - U) * kSlot;  // fill beyond which U more pushes may not fit
     unsigned char *base;
-    int wofs, rofs, cnt = 0;
-    float u2;
-    double unit;   // force-sum scale of the family weights
+    uint32_t wpos, rpos;   // unsigned: the counters may wrap, their difference stays exact
+    PairConst32 pc;
     float sx = 0, sy = 0, sz = 0, sp = 0;
     __device__ LaneRings(unsigned char *b, int t, const SysDesc &d)
-        : base(b), wofs(t * (int)sizeof(float4)), rofs(t * (int)sizeof(float4)), u2(ISO ? d.u2 : 1.0f),
-          unit(ISO ? d.ud : 1.0) {}
+        : base(b), wpos((uint32_t)t * (uint32_t)sizeof(float4)), rpos(wpos), pc(d.alpha, ISO ? d.ud : 1.0) {}
     __device__ void family(double w, double zsign, double dwt, double dwb) {
-        TargetSums<DG>::family(w, zsign, dwt, dwb, unit);
+        TargetSums<DG>::family(w, zsign, dwt, dwb, pc.fscale, pc.pscale);
     }
     __device__ void push(bool acc, float dx, float dy, float dz, float qs) {
         if (acc) {
-            *reinterpret_cast<float4 *>(base + wofs) = make_float4(dx, dy, dz, qs);
-            wofs = (wofs + kSlot) & kMask;
-            cnt++;
+            *reinterpret_cast<float4 *>(base + (wpos & kMask)) = make_float4(dx, dy, dz, qs);
+            wpos += kSlot;
         }
     }
-    __device__ bool full() const { return __ballot(cnt > Q - U) != 0; }
-    __device__ void round(float alpha, float c2a) {
-        if (cnt > 0) {
-            const float4 e = *reinterpret_cast<const float4 *>(base + rofs);
-            rofs = (rofs + kSlot) & kMask;
-            cnt--;
-            float r2 = e.x * e.x + e.y * e.y + e.z * e.z;
-            if (ISO) r2 *= u2;
+    __device__ bool full() const { return __ballot(wpos - rpos > kRoom) != 0; }
+    __device__ void round() {
+        if (wpos != rpos) {
+            const float4 e = *reinterpret_cast<const float4 *>(base + (rpos & kMask));
+            rpos += kSlot;
+            const float r2 = e.x * e.x + e.y * e.y + e.z * e.z;
             float ec, fs;
-            pair_terms(r2, alpha, c2a, &ec, &fs);
+            pair_terms(r2, pc, &ec, &fs);
             const float qf = e.w * fs;
             sx += qf * e.x; sy += qf * e.y; sz += qf * e.z; sp += e.w * ec;
         }
@@ -317,14 +332,14 @@ struct LaneRings : TargetSums<DG> {
         sx = sy = sz = sp = 0;
     }
     // make room for U more pairs per lane
-    __device__ void drain(float alpha, float c2a) {
+    __device__ void drain() {
         do {
-            round(alpha, c2a);
-        } while (__ballot(cnt > Q - U) != 0 || __popcll(__ballot(cnt > 0)) >= kRoundMin);
+            round();
+        } while (__ballot(wpos - rpos > kRoom) != 0 || __popcll(__ballot(wpos != rpos)) >= kRoundMin);
         fold();
     }
-    __device__ void flush(float alpha, float c2a) {
-        while (__ballot(cnt > 0) != 0) round(alpha, c2a);
+    __device__ void flush() {
+        while (__ballot(wpos != rpos) != 0) round();
         fold();
     }
 };
@@ -339,13 +354,14 @@ struct WaveQueue : TargetSums<DG> {
     unsigned char *own;   // [QW] owning lane
     double *acc;          // [4][64] per-target sums
     const double *coef;   // erfcx fit coefficients (LDS)
+    double alpha, c2a;    // a and 2a/sqrt(pi)
     int lane, qn = 0;     // qn: entries queued (wave-uniform)
-    __device__ WaveQueue(double4 *e, unsigned char *o, double *a, const double *c, int l)
-        : ent(e), own(o), acc(a), coef(c), lane(l) {
+    __device__ WaveQueue(double4 *e, unsigned char *o, double *a, const double *c, double al, int l)
+        : ent(e), own(o), acc(a), coef(c), alpha(al), c2a(1.1283791670955126 * al), lane(l) {
         for (int c = 0; c < 4; c++) acc[c * kWave + lane] = 0.0;
     }
     __device__ void family(double w, double zsign, double dwt, double dwb) {
-        TargetSums<DG>::family(w, zsign, dwt, dwb, 1.0);
+        TargetSums<DG>::family(w, zsign, dwt, dwb, 1.0, 1.0);
     }
     __device__ void push(bool ok, double dx, double dy, double dz, double qs) {
         const uint64_t m = __ballot(ok);
@@ -358,7 +374,7 @@ struct WaveQueue : TargetSums<DG> {
     }
     __device__ bool full() const { return qn > QW - U * kWave; }
     // evaluate the top n <= 64 entries, one per lane
-    __device__ void round(int n, double alpha, double c2a) {
+    __device__ void round(int n) {
         __builtin_amdgcn_wave_barrier();   // entries were written by other lanes of the wave
         const int base = qn - n;
         if (lane < n) {
@@ -380,12 +396,12 @@ struct WaveQueue : TargetSums<DG> {
         this->add(acc[lane], acc[kWave + lane], acc[2 * kWave + lane], acc[3 * kWave + lane]);
         for (int c = 0; c < 4; c++) acc[c * kWave + lane] = 0.0;
     }
-    __device__ void drain(double alpha, double c2a) {
-        while (qn >= kWave) round(kWave, alpha, c2a);
+    __device__ void drain() {
+        while (qn >= kWave) round(kWave);
         fold();
     }
-    __device__ void flush(double alpha, double c2a) {
-        while (qn > 0) round(min(qn, kWave), alpha, c2a);
+    __device__ void flush() {
+        while (qn > 0) round(min(qn, kWave));
         fold();
     }
 };
@@ -418,12 +434,12 @@ __device__ __forceinline__ int wave_min(int v) {
 // accumulates the drains in FP64.  The order of every sum is fixed by the
 // data, so the results are bitwise reproducible.
 template <int QW, int U, bool DG>
-__device__ WaveQueue<QW, U, DG> make_wave_queue(unsigned char *lds, int tid, const double *coef) {
+__device__ WaveQueue<QW, U, DG> make_wave_queue(unsigned char *lds, int tid, const double *coef, double alpha) {
     const int wid = tid / kWave, lane = tid % kWave;
     double4 *ent = reinterpret_cast<double4 *>(lds) + wid * QW;
     double *acc = reinterpret_cast<double *>(lds + (kBlock / kWave) * QW * sizeof(double4)) + wid * 4 * kWave;
     unsigned char *own = lds + (kBlock / kWave) * (QW * sizeof(double4) + 4 * kWave * sizeof(double)) + wid * QW;
-    return WaveQueue<QW, U, DG>(ent, own, acc, coef, lane);
+    return WaveQueue<QW, U, DG>(ent, own, acc, coef, alpha, lane);
 }
 
 template <bool FP32, bool WANT_DG, bool ISO>
@@ -446,10 +462,14 @@ __global__ __launch_bounds__(kBlock) RBE2D_REAL_OCC void k_real(RealArgs a) {
     }
     const double4 *src = a.src;
     const int tid = threadIdx.x;
-    // Blocks are dealt round-robin to the 8 XCDs: give each XCD a contiguous
-    // range of targets, so neighbouring cells share that XCD's L2.
-    const int per_xcd = (int)(gridDim.x >> 3);
-    const int lb = (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
+    // Blocks are dealt round-robin to the 8 XCDs.  Each XCD runs C contiguous
+    // chunks of targets (chunk k of XCD x is chunk 8k + x of the range), so
+    // neighbouring cells share that XCD's L2, and the targets near the walls
+    // (cell order is z-slowest; they search extra image families) are shared
+    // by all XCDs instead of loading the first and last ones.
+    const int cs = (int)(gridDim.x >> 3) / RBE2D_REAL_CHUNKS;   // blocks per chunk
+    const int j = (int)(blockIdx.x >> 3);
+    const int lb = ((j / cs) * 8 + (int)(blockIdx.x & 7)) * cs + j % cs;
     if (lb >= a.nblocks) return;
     const int t = lb * kBlock + tid;
     // the system of this wave (system ranges are padded to whole waves)
@@ -473,11 +493,9 @@ __global__ __launch_bounds__(kBlock) RBE2D_REAL_OCC void k_real(RealArgs a) {
     const double yrel = me.y - cy * d.hy;           // y within the target's cell
     const double rcm2 = d.rc2 * (1.0 + 2e-9);       // culling bounds get a 1e-9 margin:
     const double rmarg = 1e-9 * d.rc;               // cells were assigned by division
-    const T alpha = (T)d.alpha;
-    const T c2a = (T)(1.1283791670955126 * d.alpha);
     Queue qu = [&]() {
         if constexpr (FP32) return Queue(lds, tid, d);
-        else return make_wave_queue<kWaveQ, U, WANT_DG>(lds, tid, coef64);
+        else return make_wave_queue<kWaveQ, U, WANT_DG>(lds, tid, coef64, d.alpha);
     }();
     for (int f = 0; f <= d.nfam; f++) {
         double sz = 1.0, czs = 0.0, w = 1.0, zsign = 1.0, dwt = 0.0, dwb = 0.0;
@@ -514,7 +532,7 @@ __global__ __launch_bounds__(kBlock) RBE2D_REAL_OCC void k_real(RealArgs a) {
                 const float rc2s = ISO ? d.rc2q : d.rc2f;
                 const float near2s = ISO ? d.near2q : d.near2f;
                 for (int m0 = 0; m0 < maxlen; m0 += U) {
-                    if (qu.full()) qu.drain(alpha, c2a);
+                    if (qu.full()) qu.drain();
                     const uint4 *pq = p16 + min(m0, lm);
                     uint4 sv[U];
 #pragma unroll
@@ -547,7 +565,7 @@ __global__ __launch_bounds__(kBlock) RBE2D_REAL_OCC void k_real(RealArgs a) {
                 return;
             }
             for (int m0 = 0; m0 < maxlen; m0 += U) {
-                if (qu.full()) qu.drain(alpha, c2a);
+                if (qu.full()) qu.drain();
                 const double4 *pq = p + min(m0, lm);
                 double4 sv[U];
 #pragma unroll
@@ -615,7 +633,7 @@ __global__ __launch_bounds__(kBlock) RBE2D_REAL_OCC void k_real(RealArgs a) {
                 if (__ballot(len2 > 0) != 0) scan(jb2, len2, xt, me.y - sy2, self2);
             }
         }
-        qu.flush(alpha, c2a);
+        qu.flush();
     }
     const double fx = qu.fx, fy = qu.fy, fz = qu.fz, phi = qu.phi, dpt = qu.dpt, dpb = qu.dpb;
     double qphi = 0.0, qdt = 0.0, qdb = 0.0;
@@ -723,9 +741,10 @@ hipError_t launch_pairs(rbe2d_ctx *h, bool want_dg, hipStream_t s) {
     }
     const int nbs = (h->n_swaves * kWave + kBlock - 1) / kBlock;
     r.nblocks = nbs;
-    const int nb8 = (nbs + 7) / 8 * 8;
+    const int nch = 8 * RBE2D_REAL_CHUNKS;
+    const int nbc = (nbs + nch - 1) / nch * nch;
     const bool fp32 = h->precision == RBE2D_PREC_FP32_PHASE;
-    const dim3 grid(nb8, r.nsplit);
+    const dim3 grid(nbc, r.nsplit);
     prof_begin(h, 4, s);
     if (fp32 && h->iso) {
         if (want_dg) hipLaunchKernelGGL((k_real<true, true, true>), grid, dim3(kBlock), 0, s, r);
