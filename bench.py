@@ -178,6 +178,33 @@ def dominant_kernel(prof):
     return max((k for k in prof if k not in SIDE_STREAM), key=lambda k: prof[k][0])
 
 
+def run_parts(R, torch, w, precision, calls):
+    """Each half of the force call alone on the same configuration: k-space
+    (with IBC) and real space (cell list and pairs), every kernel class timed
+    by HIP events.  Standalone durations of the structure-factor pass, the
+    force scatter and the pair kernel (in the MD step they share the chip)."""
+    from paper_2405_06333_amd import inputs
+    pos, q = inputs.sample(w)
+    P_ = torch.as_tensor(pos, device="cuda")
+    Q_ = torch.as_tensor(q, device="cuda")
+    slab = R.Slab(**w.slab_kwargs(), precision=precision, n_max=w.N)
+    slab.sample_kset(w.seed, 0)
+    out = {}
+    for name, flags in (("kspace", R.KSPACE | R.IBC), ("real", R.REAL)):
+        for _ in range(2):
+            slab.forces(P_, Q_, flags=flags)
+        torch.cuda.synchronize()
+        slab.profile_enable(calls + 4)
+        slab.profile_read()
+        for _ in range(calls):
+            slab.forces(P_, Q_, flags=flags)
+        torch.cuda.synchronize()
+        out[name] = slab.profile_read()
+        slab.profile_enable(0)
+    slab.check()
+    return out
+
+
 def timed(torch, fn, steps):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -419,8 +446,20 @@ def main():
         s64, _, _, _ = run_md(R, torch, w, "fp64", a.fp64_steps, 1, profile=False, autotune=not a.no_autotune)
         fp64 = {"value": w.N * a.fp64_steps / s64, "unit": "particle-steps/s", "steps": a.fp64_steps}
 
-    graph = batch = grad = langevin = None
+    graph = batch = grad = langevin = parts = None
     if a.side_steps > 0:
+        alone = run_parts(R, torch, w, a.precision, a.side_steps)
+        parts = {"calls": a.side_steps, "unit": "ms per launch"}
+        for half, k, slots, units in (("kspace", "sf_pass", SLOTS_SF, NP), ("kspace", "force_scatter", SLOTS_FORCE, NP),
+                                      ("real", "real_pairs", SLOTS_REAL, pairs_real),
+                                      ("real", "cell_build", None, None)):
+            t, n = alone[half].get(k, (0.0, 0))
+            if not n:
+                continue
+            ms = t / n
+            parts[k] = {"ms": round(ms, 4)}
+            if slots:
+                parts[k]["valu_frac"] = round(slots * units / (ms * 1e-3) / VALU_LANE_SLOTS, 4)
         sg, _, _, _ = run_md(R, torch, w, a.precision, a.side_steps, 1, profile=False, use_graph=True,
                              autotune=not a.no_autotune)
         graph = {"value": w.N * a.side_steps / sg, "unit": "particle-steps/s", "steps": a.side_steps}
@@ -458,6 +497,7 @@ def main():
                                 "P": w.P, "estimator": "sample variance of the per-k force terms (Theorem 2.2)"}
                                if tuned else None),
         "kernels": kern,
+        "kernels_alone": parts,
         "finite": finite,
     }
     print(json.dumps(out), flush=True)

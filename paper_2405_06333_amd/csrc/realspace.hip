@@ -286,6 +286,11 @@ struct TargetSums {
     }
 };
 
+// popcount of a wave mask as two 32-bit halves (scalar instructions only)
+__device__ __forceinline__ int busy_lanes(uint64_t m) {
+    return __builtin_popcount((uint32_t)m) + __builtin_popcount((uint32_t)(m >> 32));
+}
+
 // FP32 kernel: a ring of Q entries per lane.  A round evaluates the oldest
 // entry of every lane that holds one; the FP32 sums of a drain (at most Q
 // pairs per lane) are folded into FP64.  Cheap routing (every result stays in
@@ -311,13 +316,15 @@ struct LaneRings : TargetSums<DG> {
     }
     __device__ void push(bool acc, float dx, float dy, float dz, float qs) {
         if (acc) {
-            *reinterpret_cast<float4 *>(base + (wpos & kMask)) = make_float4(dx, dy, dz, qs);
+            const uint32_t at = wpos & kMask;
             wpos += kSlot;
+            *reinterpret_cast<float4 *>(base + at) = make_float4(dx, dy, dz, qs);
         }
     }
     __device__ bool full() const { return __ballot(wpos - rpos > kRoom) != 0; }
-    __device__ void round() {
-        if (wpos != rpos) {
+    // one round: evaluate the oldest entry of every lane with fill f > 0
+    __device__ void round(uint32_t f) {
+        if (f != 0) {
             const float4 e = *reinterpret_cast<const float4 *>(base + (rpos & kMask));
             rpos += kSlot;
             const float r2 = e.x * e.x + e.y * e.y + e.z * e.z;
@@ -331,15 +338,22 @@ struct LaneRings : TargetSums<DG> {
         this->add((double)sx, (double)sy, (double)sz, (double)sp);
         sx = sy = sz = sp = 0;
     }
-    // make room for U more pairs per lane
+    // make room for U more pairs per lane: rounds while a lane could
+    // overflow or while enough lanes hold pairs
     __device__ void drain() {
+        uint32_t f = wpos - rpos;
         do {
-            round();
-        } while (__ballot(wpos - rpos > kRoom) != 0 || __popcll(__ballot(wpos != rpos)) >= kRoundMin);
+            round(f);
+            f = wpos - rpos;
+        } while (__ballot(f > kRoom) != 0 || busy_lanes(__ballot(f != 0)) >= kRoundMin);
         fold();
     }
     __device__ void flush() {
-        while (__ballot(wpos != rpos) != 0) round();
+        uint32_t f = wpos - rpos;
+        while (__ballot(f != 0) != 0) {
+            round(f);
+            f = wpos - rpos;
+        }
         fold();
     }
 };
