@@ -17,10 +17,12 @@
 #include "rbe2d_internal.h"
 
 // Compile-time parameters of the FP32 pair kernel (measured best on the
-// 1e6-ion slab: 16-entry rings halve the occupancy, 2 loads in flight leave
-// latency exposed, the drain threshold hardly matters).
+// 1e6-ion slab: 16-entry rings halve the occupancy, batches of 2 loads leave
+// latency exposed, the drain threshold hardly matters; the double-buffered
+// batches need the register cap below, at 3 waves per SIMD the kernel is
+// 18 % slower).
 #ifndef RBE2D_REAL_U32
-#define RBE2D_REAL_U32 4      // source loads in flight per lane
+#define RBE2D_REAL_U32 4      // source loads per batch (two batches in flight per lane)
 #endif
 #ifndef RBE2D_RING_Q
 #define RBE2D_RING_Q 8        // ring entries per lane (a power of two)
@@ -31,10 +33,8 @@
 #ifndef RBE2D_REAL_CHUNKS
 #define RBE2D_REAL_CHUNKS 8   // contiguous target chunks per XCD
 #endif
-#ifdef RBE2D_REAL_WAVES_PER_EU  // occupancy hint for the pair kernel (register budget)
-#define RBE2D_REAL_OCC __attribute__((amdgpu_waves_per_eu(RBE2D_REAL_WAVES_PER_EU, 8)))
-#else
-#define RBE2D_REAL_OCC
+#ifndef RBE2D_REAL_WAVES32
+#define RBE2D_REAL_WAVES32 4  // FP32 pair kernel: waves per SIMD its register budget must allow
 #endif
 
 namespace rbe2d {
@@ -212,6 +212,17 @@ template <bool FP32> struct RealTypes;
 template <> struct RealTypes<true> { using T = float; using V4 = float4; static constexpr int U = RBE2D_REAL_U32; };
 template <> struct RealTypes<false> { using T = double; using V4 = double4; static constexpr int U = 2; };
 
+// Wave-uniform values computed by vector instructions, moved to scalar
+// registers (the compiler keeps them in vector registers otherwise).
+__device__ __forceinline__ float uniform(float v) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ double uniform(double v) {
+    const int2 h = make_int2(__builtin_amdgcn_readfirstlane(__double2loint(v)),
+                             __builtin_amdgcn_readfirstlane(__double2hiint(v)));
+    return __hiloint2double(h.y, h.x);
+}
+
 // Constants of the FP32 pair terms in the units of the displacements: with
 // displacements in units u (r = u rq), ec and fs below come out as u erfc(a r)/r
 // and u^3 [erfc(a r)/r + 2a/sqrt(pi) e^{-a^2 r^2}]/r^2; the sums are rescaled
@@ -222,8 +233,9 @@ struct PairConst32 {
     float c2a;   // 2a/sqrt(pi) u
     double fscale, pscale;   // 1/u^2 (forces), 1/u (potential)
     __device__ PairConst32(double alpha, double u)
-        : ce((float)(-alpha * alpha * u * u * 1.4426950408889634)), cpx((float)(RBE2D_ERFCX_P * alpha * u)),
-          c2a((float)(1.1283791670955126 * alpha * u)), fscale(1.0 / (u * u)), pscale(1.0 / u) {}
+        : ce(uniform((float)(-alpha * alpha * u * u * 1.4426950408889634))),
+          cpx(uniform((float)(RBE2D_ERFCX_P * alpha * u))), c2a(uniform((float)(1.1283791670955126 * alpha * u))),
+          fscale(uniform(1.0 / (u * u))), pscale(uniform(1.0 / u)) {}
 };
 
 // erfc(a r)/r (ec) and the radial force factor fs = [erfc(a r)/r + 2a/sqrt(pi)
@@ -278,7 +290,8 @@ struct TargetSums {
     double wxy = 1, wz = 1, wp = 1, wt = 0, wb = 0;
     // fscale, pscale: unit conversions of the force and potential sums
     __device__ void family(double w, double zsign, double dwt, double dwb, double fscale, double pscale) {
-        wxy = w * fscale; wz = w * zsign * fscale; wp = w * pscale; wt = dwt * pscale; wb = dwb * pscale;
+        wxy = uniform(w * fscale); wz = uniform(w * zsign * fscale); wp = uniform(w * pscale);
+        if (DG) { wt = uniform(dwt * pscale); wb = uniform(dwb * pscale); }
     }
     __device__ void add(double sx, double sy, double sz, double sp) {
         fx = fma(sx, wxy, fx); fy = fma(sy, wxy, fy); fz = fma(sz, wz, fz); phi = fma(sp, wp, phi);
@@ -457,7 +470,8 @@ __device__ WaveQueue<QW, U, DG> make_wave_queue(unsigned char *lds, int tid, con
 }
 
 template <bool FP32, bool WANT_DG, bool ISO>
-__global__ __launch_bounds__(kBlock) RBE2D_REAL_OCC void k_real(RealArgs a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(FP32 ? RBE2D_REAL_WAVES32 : 1, 8)))
+void k_real(RealArgs a) {
     static_assert(FP32 || !ISO, "the isotropic frame is a property of the fixed-point records");
     using T = typename RealTypes<FP32>::T;
     constexpr int U = RealTypes<FP32>::U;
@@ -545,12 +559,19 @@ __global__ __launch_bounds__(kBlock) RBE2D_REAL_OCC void k_real(RealArgs a) {
                 const uint4 *p16 = a.src16 + jb;
                 const float rc2s = ISO ? d.rc2q : d.rc2f;
                 const float near2s = ISO ? d.near2q : d.near2f;
-                for (int m0 = 0; m0 < maxlen; m0 += U) {
-                    if (qu.full()) qu.drain();
-                    const uint4 *pq = p16 + min(m0, lm);
-                    uint4 sv[U];
+                // double-buffered: the next U records are in flight while
+                // these are tested (and while a drain runs)
+                uint4 sv[U];
 #pragma unroll
-                    for (int k = 0; k < U; k++) sv[k] = pq[k];
+                for (int k = 0; k < U; k++) sv[k] = p16[k];
+                for (int m0 = 0; m0 < maxlen; m0 += U) {
+                    uint4 nx[U];
+                    if (m0 + U < maxlen) {
+                        const uint4 *pq = p16 + min(m0 + U, lm);
+#pragma unroll
+                        for (int k = 0; k < U; k++) nx[k] = pq[k];
+                    }
+                    if (qu.full()) qu.drain();
 #pragma unroll
                     for (int k = 0; k < U; k++) {
                         const int m = m0 + k;
@@ -575,6 +596,8 @@ __global__ __launch_bounds__(kBlock) RBE2D_REAL_OCC void k_real(RealArgs a) {
                         }
                         qu.push(acc, dx, dy, dz, __uint_as_float(sv[k].w));
                     }
+#pragma unroll
+                    for (int k = 0; k < U; k++) sv[k] = nx[k];
                 }
                 return;
             }
