@@ -10,6 +10,7 @@
 // l -- so every image family is another cell search around the transformed
 // target, done only when that point lies within r_c of the slab.
 #include <algorithm>
+#include <climits>
 #include <type_traits>
 
 #include "devmath.h"
@@ -18,9 +19,10 @@
 
 // Compile-time parameters of the FP32 pair kernel (measured best on the
 // 1e6-ion slab: 16-entry rings halve the occupancy, batches of 2 loads leave
-// latency exposed, the drain threshold hardly matters; the double-buffered
-// batches need the register cap below, at 3 waves per SIMD the kernel is
-// 18 % slower).
+// latency exposed, the drain threshold hardly matters).  Register cap: the
+// double-buffered scan needs 131 VGPRs uncapped (3 waves per SIMD, 18 %
+// slower); capped at 5 waves (96 VGPRs, a few spills; the rings then fill
+// the 160 KB of LDS) the MD step is 4 % faster than at 4 waves.
 #ifndef RBE2D_REAL_U32
 #define RBE2D_REAL_U32 4      // source loads per batch (two batches in flight per lane)
 #endif
@@ -34,7 +36,7 @@
 #define RBE2D_REAL_CHUNKS 8   // contiguous target chunks per XCD
 #endif
 #ifndef RBE2D_REAL_WAVES32
-#define RBE2D_REAL_WAVES32 4  // FP32 pair kernel: waves per SIMD its register budget must allow
+#define RBE2D_REAL_WAVES32 5  // FP32 pair kernel: waves per SIMD its register budget must allow
 #endif
 
 namespace rbe2d {
@@ -433,16 +435,25 @@ struct WaveQueue : TargetSums<DG> {
     }
 };
 
-__device__ __forceinline__ int wave_max(int v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
-    return v;
+// Wave-wide max / min of an int with DPP lane moves (no LDS round trips):
+// within quads, within rows of 16 (half-mirror, mirror), then row 3 takes
+// rows 0-2 by the row broadcasts; the result is read from lane 63 into a
+// scalar register.  Every lane of the wave must be active.
+template <bool MAX>
+__device__ __forceinline__ int wave_reduce(int v) {
+    // lanes outside the row mask see the identity of the operation
+    constexpr int id = MAX ? INT_MIN : INT_MAX;
+    auto op = [](int x, int y) { return MAX ? max(x, y) : min(x, y); };
+    v = op(v, __builtin_amdgcn_update_dpp(id, v, 0xb1, 0xf, 0xf, false));    // quad_perm [1,0,3,2]
+    v = op(v, __builtin_amdgcn_update_dpp(id, v, 0x4e, 0xf, 0xf, false));    // quad_perm [2,3,0,1]
+    v = op(v, __builtin_amdgcn_update_dpp(id, v, 0x141, 0xf, 0xf, false));   // row_half_mirror
+    v = op(v, __builtin_amdgcn_update_dpp(id, v, 0x140, 0xf, 0xf, false));   // row_mirror
+    v = op(v, __builtin_amdgcn_update_dpp(id, v, 0x142, 0xa, 0xf, false));   // row_bcast:15 -> rows 1, 3
+    v = op(v, __builtin_amdgcn_update_dpp(id, v, 0x143, 0xc, 0xf, false));   // row_bcast:31 -> rows 2, 3
+    return __builtin_amdgcn_readlane(v, 63);
 }
-__device__ __forceinline__ int wave_min(int v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
-    return v;
-}
+__device__ __forceinline__ int wave_max(int v) { return wave_reduce<true>(v); }
+__device__ __forceinline__ int wave_min(int v) { return wave_reduce<false>(v); }
 
 // One thread per target, targets in cell order (z-layer slowest, then x,
 // then y), so the lanes of a wave share a z-layer and see neighbour rows of
@@ -518,9 +529,16 @@ void k_real(RealArgs a) {
     const int cy = cid % d.ncy;
     const int cx = (cid / d.ncy) % d.ncx;
     const bool allx = d.ncx < 2 * d.reach + 1, ally = d.ncy < 2 * d.reach_y + 1;
-    const double yrel = me.y - cy * d.hy;           // y within the target's cell
-    const double rcm2 = d.rc2 * (1.0 + 2e-9);       // culling bounds get a 1e-9 margin:
-    const double rmarg = 1e-9 * d.rc;               // cells were assigned by division
+    // Culling bounds are computed in FP32 with margins that cover its
+    // rounding (and the division that assigned the cells): 1e-4 r_c^2 on the
+    // squared y-extent, 1e-5 r_c on the extent.  They only decide which cells
+    // are scanned; every candidate is then tested against r_c.
+    const float yrel = (float)(me.y - cy * d.hy);   // y within the target's cell
+    const float xrel = (float)me.x;                 // x within the target's cell
+    const float hxf = (float)d.hx, inv_hyf = (float)d.inv_hy;
+    const float rcm2 = (float)(d.rc2 * (1.0 + 1e-4));
+    const float rmarg = (float)(1e-5 * d.rc);
+    const double rmarg64 = 1e-9 * d.rc;             // layer range (cells assigned by division)
     Queue qu = [&]() {
         if constexpr (FP32) return Queue(lds, tid, d);
         else return make_wave_queue<kWaveQ, U, WANT_DG>(lds, tid, coef64, d.alpha);
@@ -537,8 +555,8 @@ void k_real(RealArgs a) {
         const uint32_t tzf = fam_on ? to_fixed(tz + d.zoff, d.fzs) : 0u;
         int lzlo = d.ncz, lzhi = -1;
         if (fam_on) {
-            lzlo = max(0, (int)floor((tz - d.rc - rmarg) * d.inv_hz));
-            lzhi = min(d.ncz - 1, (int)floor((tz + d.rc + rmarg) * d.inv_hz));
+            lzlo = max(0, (int)floor((tz - d.rc - rmarg64) * d.inv_hz));
+            lzhi = min(d.ncz - 1, (int)floor((tz + d.rc + rmarg64) * d.inv_hz));
         }
         const int wzlo = wave_min(lzlo), wzhi = wave_max(lzhi);
         qu.family(w, zsign, dwt, dwb);
@@ -625,27 +643,27 @@ void k_real(RealArgs a) {
         const int xlo = allx ? 0 : -d.reach, xhi = allx ? d.ncx - 1 : d.reach;
         for (int lz = wzlo; lz <= wzhi; lz++) {
             const bool lay_on = lz >= lzlo && lz <= lzhi;
-            const double dzmin = fmax(0.0, fmax(lz * d.hz - tz, tz - (lz + 1) * d.hz));
+            const float dzmin = (float)fmax(0.0, fmax(lz * d.hz - tz, tz - (lz + 1) * d.hz));
             for (int ox = xlo + (int)blockIdx.y; ox <= xhi; ox += a.nsplit) {
                 const int dxc = allx ? ox - cx : ox;       // column offset in cells
                 int cxx = allx ? ox : cx + ox;
                 if (!allx) cxx += cxx < 0 ? d.ncx : (cxx >= d.ncx ? -d.ncx : 0);
-                double dxmin = 0;
-                if (!allx) dxmin = dxc > 0 ? dxc * d.hx - me.x : (dxc < 0 ? me.x - (dxc + 1) * d.hx : 0.0);
+                float dxmin = 0.0f;
+                if (!allx) dxmin = dxc > 0 ? dxc * hxf - xrel : (dxc < 0 ? xrel - (dxc + 1) * hxf : 0.0f);
                 const double xt = me.x - dxc * d.hx;
-                const double ye2 = rcm2 - dxmin * dxmin - dzmin * dzmin;
+                const float ye2 = rcm2 - dxmin * dxmin - dzmin * dzmin;
                 // up to two runs of cells along y: [ya, yb] unshifted, the wrapped one shifted by sy2
                 int jb1 = 0, len1 = 0, jb2 = 0, len2 = 0;
                 double sy2 = 0.0;
-                if (lay_on && ye2 > 0.0) {
+                if (lay_on && ye2 > 0.0f) {
                     const int row = (lz * d.ncx + cxx) * d.ncy;
                     if (ally) {
                         jb1 = start[row];
                         len1 = start[row + d.ncy] - jb1;
                     } else {
-                        const double ye = sqrt(ye2) + rmarg;
-                        int cylo = cy + (int)floor((yrel - ye) * d.inv_hy);
-                        int cyhi = cy + (int)floor((yrel + ye) * d.inv_hy);
+                        const float ye = __builtin_amdgcn_sqrtf(ye2) + rmarg;
+                        int cylo = cy + (int)floorf((yrel - ye) * inv_hyf);
+                        int cyhi = cy + (int)floorf((yrel + ye) * inv_hyf);
                         cylo = max(cylo, cy - d.reach_y);
                         cyhi = min(cyhi, cy + d.reach_y);
                         const int ya = max(cylo, 0), yb = min(cyhi, d.ncy - 1);
