@@ -619,9 +619,10 @@ rbe2d_status md_step(rbe2d_ctx *h, double *pos, double *vel, const double *q, do
 }
 
 // Force evaluation and closing kick of one plain velocity-Verlet step at
-// the current positions (whose k-set is drawn and whose k-space particle
-// records the preceding MD pass wrote).  The k-space chain runs on the side
-// stream, real space on s.  After the forces, either the closing half kick
+// the current positions (whose k-set is drawn, with its k-vector table, and
+// whose k-space particle records and IBC block sums the preceding MD pass
+// wrote).  The k-space chain (structure factors, assembly with the IBC
+// scalars, force scatter) runs on the side stream, real space on s.  After the forces, either the closing half kick
 // (last step of the run) or one pass with the closing and next opening half
 // kicks, the next drift and the next records.  Meanwhile the side stream
 // draws the next step's k-set (device step counter: incremented there
@@ -633,8 +634,7 @@ rbe2d_status vv_unit(rbe2d_ctx *h, double *pos, double *vel, const double *q, do
     hipStream_t ks = h->side;
     RBE2D_TRY(h, hipEventRecord(h->fork_ev, s), "fork event");
     RBE2D_TRY(h, hipStreamWaitEvent(ks, h->fork_ev, 0), "fork wait");
-    RBE2D_TRY(h, launch_ktable_scalars(h, ks), "k-table launch");
-    RBE2D_TRY(h, launch_kcoef_sf(h, ks), "structure-factor launch");
+    RBE2D_TRY(h, launch_kcoef_sf(h, ks, true), "structure-factor launch");
     RBE2D_TRY(h, launch_kforce(h, pos, q, F, nullptr, RBE2D_KSPACE | RBE2D_IBC, false, false, false, nullptr, ks),
               "force launch");
     RBE2D_TRY(h, launch_real(h, pos, q, false, s), "real-space launch");
@@ -644,6 +644,7 @@ rbe2d_status vv_unit(rbe2d_ctx *h, double *pos, double *vel, const double *q, do
         if (dev_step) RBE2D_TRY(h, launch_step_inc(h, ks), "md step counter");
         RBE2D_TRY(h, launch_sample(h, seed, (uint64_t)(step + 1) * (uint64_t)h->n_sys, dev_step ? h->w.step : nullptr,
                                    ks), "md sample");
+        launch_ktable(h, ks);
         RBE2D_TRY(h, launch_prep_md(h, pos, vel, F, q, dt, zlo, zhi_from_top, true, s), "md leapfrog");
     } else {
         RBE2D_TRY(h, launch_add_real(h, F, vel, 0.5 * dt, s), "real-space add");
@@ -664,6 +665,7 @@ rbe2d_status vv_run(rbe2d_ctx *h, double *pos, double *vel, const double *q, dou
                     hipStream_t s) {
     RBE2D_TRY(h, launch_prep_md(h, pos, vel, F, q, dt, zlo, zhi_from_top, false, s), "md drift");
     RBE2D_TRY(h, launch_sample(h, seed, (uint64_t)step0 * (uint64_t)h->n_sys, nullptr, s), "md sample");
+    launch_ktable(h, s);
     int32_t it = 0;
     if (use_graph) {
         auto bits = [](double x) { uint64_t u; std::memcpy(&u, &x, 8); return u; };

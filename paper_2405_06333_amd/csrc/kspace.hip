@@ -122,22 +122,22 @@ struct ScalArgs {
     double *scal;
 };
 
-__global__ __launch_bounds__(kBlock) void k_scalars(ScalArgs a) {
-    __shared__ double sh[kBlock / 64];
-    const int r = blockIdx.x;
+// IBC scalars of system r from the prep pass's block sums, by one wave
+// (fixed summation order: the same in both launches that use it)
+__device__ void ibc_scalars(const ScalArgs &a, int r, int lane) {
     const SysDesc &d = a.sys[r];
     double v[3] = {0, 0, 0};
-    for (int b = a.lay.bbase[r] + threadIdx.x; b < a.lay.bbase[r + 1]; b += kBlock)
+    for (int b = a.lay.bbase[r] + lane; b < a.lay.bbase[r + 1]; b += 64)
         for (int c = 0; c < 3; c++) v[c] += a.bpart[4 * b + c];
-    const double s0 = block_sum(v[0], sh), s1 = block_sum(v[1], sh), s2 = block_sum(v[2], sh);
-    if (threadIdx.x == 0) {
-        const double mu = s0, Q = s1;
+    for (int c = 0; c < 3; c++) v[c] = wave_sum(v[c]);
+    if (lane == 0) {
+        const double mu = v[0], Q = v[1];
         const double muM = d.g1 * mu + d.cgam * Q;
         const double tv = 2.0 * kPi / d.V * d.pref;
         double *o = a.scal + 8 * r;
         o[0] = mu;
         o[1] = Q;
-        o[2] = s2;
+        o[2] = v[2];
         o[3] = muM;
         o[4] = -tv * (muM + d.g1 * mu);
         o[5] = tv * mu * d.cgam;
@@ -145,6 +145,8 @@ __global__ __launch_bounds__(kBlock) void k_scalars(ScalArgs a) {
         o[7] = d.dg1b * mu + d.dcgb * Q;
     }
 }
+
+__global__ __launch_bounds__(64) void k_scalars(ScalArgs a) { ibc_scalars(a, blockIdx.x, threadIdx.x); }
 
 __global__ void k_ktable(const int32_t *kset, int n_sys, int P, int P_pad, float4 *kn32, double4 *kn64);
 
@@ -155,16 +157,20 @@ static PrepArgs prep_args(rbe2d_ctx *h, const double *pos, const double *q) {
     return a;
 }
 
-static void launch_ktable(rbe2d_ctx *h, hipStream_t s) {
+void launch_ktable(rbe2d_ctx *h, hipStream_t s) {
     const int nk = h->n_sys * h->P_pad;
     hipLaunchKernelGGL(k_ktable, dim3((nk + 63) / 64), dim3(64), 0, s, h->w.kset, h->n_sys, h->P, h->P_pad,
                        h->w.kn32, h->w.kn64);
 }
 
-static void launch_scalars(rbe2d_ctx *h, hipStream_t s) {
+static ScalArgs scal_args(rbe2d_ctx *h) {
     ScalArgs b;
     b.bpart = h->w.bpart; b.sys = h->w.sys; b.lay = h->w.lay; b.scal = h->w.scal;
-    hipLaunchKernelGGL(k_scalars, dim3(h->n_sys), dim3(kBlock), 0, s, b);
+    return b;
+}
+
+static void launch_scalars(rbe2d_ctx *h, hipStream_t s) {
+    hipLaunchKernelGGL(k_scalars, dim3(h->n_sys), dim3(64), 0, s, scal_args(h));
 }
 
 template <int MD>
@@ -195,14 +201,6 @@ hipError_t launch_prep_md(rbe2d_ctx *h, double *pos, double *vel, const double *
     if (with_real) launch_prep_kernel<2>(h, a, s);
     else launch_prep_kernel<1>(h, a, s);
     prof_end(h, 7, s);
-    return hipGetLastError();
-}
-
-hipError_t launch_ktable_scalars(rbe2d_ctx *h, hipStream_t s) {
-    launch_ktable(h, s);
-    prof_begin(h, 0, s);
-    launch_scalars(h, s);
-    prof_end(h, 0, s);
     return hipGetLastError();
 }
 
@@ -348,6 +346,8 @@ struct AssembleArgs {
     const ImgTable *img;
     double *krec;
     float4 *kf32;
+    int n_sys, with_scalars;   // with_scalars: n_sys more blocks compute the IBC scalars
+    ScalArgs sc;
 };
 
 __device__ __forceinline__ double dmono(int e_self, double g_self, int e_other, double g_other) {
@@ -360,6 +360,10 @@ __device__ __forceinline__ double dmono(int e_self, double g_self, int e_other, 
 }
 
 __global__ __launch_bounds__(64) void k_assemble(AssembleArgs a) {
+    if ((int)blockIdx.x >= a.n_sys * a.P) {
+        ibc_scalars(a.sc, blockIdx.x - a.n_sys * a.P, threadIdx.x);
+        return;
+    }
     const int r = blockIdx.x / a.P, l = blockIdx.x - r * a.P;
     const SysDesc &d = a.sys[r];
     const ImgTable &it = a.img[r];
@@ -452,7 +456,7 @@ int choose_tile(int64_t N, int n_kchunks) {
     return per;
 }
 
-hipError_t launch_kcoef_sf(rbe2d_ctx *h, hipStream_t s) {
+hipError_t launch_kcoef_sf(rbe2d_ctx *h, hipStream_t s, bool with_scalars) {
     const bool fp32 = h->precision == RBE2D_PREC_FP32_PHASE;
     prof_begin(h, 1, s);
     if (h->n_tiles > 0) {
@@ -472,8 +476,9 @@ hipError_t launch_kcoef_sf(rbe2d_ctx *h, hipStream_t s) {
     a.part = h->w.sfpart; a.fp32_part = fp32; a.P = h->P; a.P_pad = h->P_pad;
     a.tbase = h->w.lay.tbase; a.kset = h->w.kset; a.sys = h->w.sys; a.img = h->w.img;
     a.krec = h->w.krec; a.kf32 = h->w.kf32;
+    a.n_sys = h->n_sys; a.with_scalars = with_scalars; a.sc = scal_args(h);
     prof_begin(h, 2, s);
-    hipLaunchKernelGGL(k_assemble, dim3(h->n_sys * h->P), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(k_assemble, dim3(h->n_sys * h->P + (with_scalars ? h->n_sys : 0)), dim3(64), 0, s, a);
     prof_end(h, 2, s);
     return hipGetLastError();
 }

@@ -218,7 +218,11 @@ namespace rbe2d {
 
 // kernel launchers (return hipSuccess or the launch error); all systems at once
 hipError_t launch_prep(rbe2d_ctx *h, const double *pos, const double *q, hipStream_t s);
-hipError_t launch_kcoef_sf(rbe2d_ctx *h, hipStream_t s);
+// structure factors and per-k assembly; with_scalars: the assembly launch
+// also computes the IBC scalars (otherwise the prep launch does)
+hipError_t launch_kcoef_sf(rbe2d_ctx *h, hipStream_t s, bool with_scalars = false);
+// k-vector tables of the current k-set (kn32, kn64)
+void launch_ktable(rbe2d_ctx *h, hipStream_t s);
 hipError_t launch_kforce(rbe2d_ctx *h, const double *pos, const double *q, double *F, double *dEdq,
                          uint32_t flags, bool accumulate, bool want_pot, bool add_real, const double *gE,
                          hipStream_t s, double *var = nullptr);
@@ -235,14 +239,14 @@ hipError_t launch_energy(rbe2d_ctx *h, double *energy, uint32_t flags, const dou
 hipError_t launch_sample(rbe2d_ctx *h, uint64_t seed, uint64_t stream_id, const long long *dev_step,
                          hipStream_t s);
 hipError_t launch_md_kick(rbe2d_ctx *h, double *vel, const double *F, double dt, hipStream_t s);
-// MD update fused with the k-space particle preparation (the side stream
-// then runs only launch_ktable_scalars): the opening half kick and drift
+// MD update fused with the k-space particle preparation (the k-vector table
+// follows each k-draw and the IBC scalars come with the assembly, so the
+// side stream starts with the structure factors): the opening half kick and drift
 // with F (with_real false), or, between two velocity-Verlet steps, the
 // closing and next opening half kicks with F plus the real-space part and
 // the drift (with_real true)
 hipError_t launch_prep_md(rbe2d_ctx *h, double *pos, double *vel, const double *F, const double *q, double dt,
                           double zlo, double zhi_from_top, bool with_real, hipStream_t s);
-hipError_t launch_ktable_scalars(rbe2d_ctx *h, hipStream_t s);
 hipError_t launch_set_step(rbe2d_ctx *h, long long value, hipStream_t s);
 hipError_t launch_step_inc(rbe2d_ctx *h, hipStream_t s);
 hipError_t launch_fill(void *p, int64_t nbytes_multiple_of_4, hipStream_t s);
