@@ -20,9 +20,9 @@
 // Compile-time parameters of the FP32 pair kernel (measured best on the
 // 1e6-ion slab: 16-entry rings halve the occupancy, batches of 2 loads leave
 // latency exposed, the drain threshold hardly matters).  Register cap: the
-// double-buffered scan needs 131 VGPRs uncapped (3 waves per SIMD, 18 %
-// slower); capped at 5 waves (96 VGPRs, a few spills; the rings then fill
-// the 160 KB of LDS) the MD step is 4 % faster than at 4 waves.
+// double-buffered scan of paired columns fits 4 waves per SIMD without
+// spills (122 VGPRs); at 5 waves it spills and is 5 % slower, uncapped at 3
+// waves slower still.
 #ifndef RBE2D_REAL_U32
 #define RBE2D_REAL_U32 4      // source loads per batch (two batches in flight per lane)
 #endif
@@ -36,7 +36,7 @@
 #define RBE2D_REAL_CHUNKS 8   // contiguous target chunks per XCD
 #endif
 #ifndef RBE2D_REAL_WAVES32
-#define RBE2D_REAL_WAVES32 5  // FP32 pair kernel: waves per SIMD its register budget must allow
+#define RBE2D_REAL_WAVES32 4  // FP32 pair kernel: waves per SIMD its register budget must allow
 #endif
 
 namespace rbe2d {
@@ -560,36 +560,45 @@ void k_real(RealArgs a) {
         }
         const int wzlo = wave_min(lzlo), wzhi = wave_max(lzhi);
         qu.family(w, zsign, dwt, dwb);
-        // scan one run of sources [jb, jb + len) for pairs within r_c.  The
-        // trip count is the wave maximum, so drains always run with every
-        // lane.  Loads are issued U at a time ahead of their use: the loop is
-        // bound by the latency of these gathers, not by their arithmetic.
-        auto scan = [&](int jb, int len, double xt, double yt, int self) {
-            const int maxlen = wave_max(len);
-            const double4 *p = src + jb;
-            // U loads from min(m0, len - 1): past the run they stay within the
-            // padded arrays (jb + len - 1 + U - 1 < capacity + 64) and are rejected
-            const int lm = max(len - 1, 0);
+        // FP32: scan run A [jbA, jbA + lenA), then run B, for pairs within
+        // r_c.  Each lane walks its two runs as one sequence: A's batches of U
+        // (the last one padded), then B's.  The trip count is the wave
+        // maximum, so drains always run with every lane; pairing the columns
+        // on either side of the target's (one long where the other is short)
+        // evens out the lanes' trip counts.  A lone run is B empty.  Loads are
+        // issued U at a time, double-buffered: the next U records are in
+        // flight while these are tested (and while a drain runs).
+        auto scan32 = [&](int jbA, int lenA, double xtA, double ytA, int jbB, int lenB, double xtB, double ytB) {
             if constexpr (FP32) {
+                const int c4a = (lenA + U - 1) / U * U;
+                const int tot = c4a + lenB;
+                const int maxtot = wave_max(tot);
+                // loads from run B are clamped to min(m - c4a, lenB - 1): past a
+                // run they stay within the padded arrays (jb + len - 1 + U - 1 <
+                // capacity + 64) and are rejected
+                const int lmB = max(lenB - 1, 0);
+                auto rec = [&](int m0) { return m0 < c4a ? jbA + m0 : jbB + min(m0 - c4a, lmB); };
                 // fixed-point displacements: exact integer differences (the
                 // int32 wrap is the minimum image in x and y), one rounding
                 // each to FP32; exact FP64 geometry for pairs within `near`
-                const uint4 *p16 = a.src16 + jb;
                 const float rc2s = ISO ? d.rc2q : d.rc2f;
                 const float near2s = ISO ? d.near2q : d.near2f;
-                // double-buffered: the next U records are in flight while
-                // these are tested (and while a drain runs)
                 uint4 sv[U];
+                {
+                    const uint4 *pq = a.src16 + rec(0);
 #pragma unroll
-                for (int k = 0; k < U; k++) sv[k] = p16[k];
-                for (int m0 = 0; m0 < maxlen; m0 += U) {
+                    for (int k = 0; k < U; k++) sv[k] = pq[k];
+                }
+                for (int m0 = 0; m0 < maxtot; m0 += U) {
                     uint4 nx[U];
-                    if (m0 + U < maxlen) {
-                        const uint4 *pq = p16 + min(m0 + U, lm);
+                    if (m0 + U < maxtot) {
+                        const uint4 *pq = a.src16 + rec(m0 + U);
 #pragma unroll
                         for (int k = 0; k < U; k++) nx[k] = pq[k];
                     }
                     if (qu.full()) qu.drain();
+                    const bool inA = m0 < c4a;
+                    const int lim = inA ? lenA : tot;          // candidates m < lim
 #pragma unroll
                     for (int k = 0; k < U; k++) {
                         const int m = m0 + k;
@@ -598,10 +607,10 @@ void k_real(RealArgs a) {
                         float dz = (float)(int)(tzf - sv[k].z);
                         if (!ISO) { dx *= d.ux; dy *= d.uy; dz *= d.uz; }
                         const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                        bool acc = m < len && r2 < rc2s;
+                        bool acc = m < lim && r2 < rc2s;
                         if (acc && r2 < near2s) {
-                            const double4 s64 = p[m];
-                            double ex = xt - s64.x, ey = yt - s64.y;
+                            const double4 s64 = src[inA ? jbA + m : jbB + (m - c4a)];
+                            double ex = (inA ? xtA : xtB) - s64.x, ey = (inA ? ytA : ytB) - s64.y;
                             // the true displacement is below `near`, far from half a
                             // period, so rounding by the reciprocal finds the same image
                             ex -= d.Lx * rint(ex * d.inv_Lx);
@@ -617,75 +626,119 @@ void k_real(RealArgs a) {
 #pragma unroll
                     for (int k = 0; k < U; k++) sv[k] = nx[k];
                 }
-                return;
             }
-            for (int m0 = 0; m0 < maxlen; m0 += U) {
-                if (qu.full()) qu.drain();
-                const double4 *pq = p + min(m0, lm);
-                double4 sv[U];
+        };
+        // FP64: scan one run [jb, jb + len); loads U at a time from
+        // min(m0, len - 1), past the run inside the padded arrays and rejected
+        auto scan64 = [&](int jb, int len, double xt, double yt, int self) {
+            if constexpr (!FP32) {
+                const int maxlen = wave_max(len);
+                const double4 *p = src + jb;
+                const int lm = max(len - 1, 0);
+                for (int m0 = 0; m0 < maxlen; m0 += U) {
+                    if (qu.full()) qu.drain();
+                    const double4 *pq = p + min(m0, lm);
+                    double4 sv[U];
 #pragma unroll
-                for (int k = 0; k < U; k++) sv[k] = pq[k];
+                    for (int k = 0; k < U; k++) sv[k] = pq[k];
 #pragma unroll
-                for (int k = 0; k < U; k++) {
-                    const int m = m0 + k;
-                    double dx = xt - sv[k].x;
-                    double dy = yt - sv[k].y;
-                    // the images differ only where |dx| is near half a period,
-                    // beyond r_c <= period / 2 either way
-                    if (allx) dx -= d.Lx * rint(dx * d.inv_Lx);
-                    if (ally) dy -= d.Ly * rint(dy * d.inv_Ly);
-                    const double dz = tz - sv[k].z;
-                    const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-                    qu.push(m < len && r2 < d.rc2 && m != self, (T)dx, (T)dy, (T)dz, (T)sv[k].w);
+                    for (int k = 0; k < U; k++) {
+                        const int m = m0 + k;
+                        double dx = xt - sv[k].x;
+                        double dy = yt - sv[k].y;
+                        // the images differ only where |dx| is near half a period,
+                        // beyond r_c <= period / 2 either way
+                        if (allx) dx -= d.Lx * rint(dx * d.inv_Lx);
+                        if (ally) dy -= d.Ly * rint(dy * d.inv_Ly);
+                        const double dz = tz - sv[k].z;
+                        const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+                        qu.push(m < len && r2 < d.rc2 && m != self, (T)dx, (T)dy, (T)dz, (T)sv[k].w);
+                    }
                 }
             }
         };
+        // the runs of one column (cells along y within the sphere's extent
+        // in this layer): [jb1, jb1 + len1) unshifted and, where the range
+        // wraps around the periodic y boundary, [jb2, jb2 + len2) shifted by sy2
+        struct Runs {
+            int jb1, len1, jb2, len2;
+            double xt, sy2;
+        };
+        auto col_runs = [&](bool lay_on, int lz, float dzmin, int ox) {
+            Runs R{0, 0, 0, 0, 0.0, 0.0};
+            const int dxc = allx ? ox - cx : ox;       // column offset in cells
+            int cxx = allx ? ox : cx + ox;
+            if (!allx) cxx += cxx < 0 ? d.ncx : (cxx >= d.ncx ? -d.ncx : 0);
+            float dxmin = 0.0f;
+            if (!allx) dxmin = dxc > 0 ? dxc * hxf - xrel : (dxc < 0 ? xrel - (dxc + 1) * hxf : 0.0f);
+            R.xt = me.x - dxc * d.hx;
+            const float ye2 = rcm2 - dxmin * dxmin - dzmin * dzmin;
+            if (lay_on && ye2 > 0.0f) {
+                const int row = (lz * d.ncx + cxx) * d.ncy;
+                if (ally) {
+                    R.jb1 = start[row];
+                    R.len1 = start[row + d.ncy] - R.jb1;
+                } else {
+                    const float ye = __builtin_amdgcn_sqrtf(ye2) + rmarg;
+                    int cylo = cy + (int)floorf((yrel - ye) * inv_hyf);
+                    int cyhi = cy + (int)floorf((yrel + ye) * inv_hyf);
+                    cylo = max(cylo, cy - d.reach_y);
+                    cyhi = min(cyhi, cy + d.reach_y);
+                    const int ya = max(cylo, 0), yb = min(cyhi, d.ncy - 1);
+                    if (ya <= yb) { R.jb1 = start[row + ya]; R.len1 = start[row + yb + 1] - R.jb1; }
+                    if (cylo < 0) {
+                        R.jb2 = start[row + cylo + d.ncy];
+                        R.len2 = start[row + d.ncy] - R.jb2;
+                        R.sy2 = -d.Ly;
+                    } else if (cyhi >= d.ncy) {
+                        R.jb2 = start[row];
+                        R.len2 = start[row + cyhi - d.ncy + 1] - R.jb2;
+                        R.sy2 = d.Ly;
+                    }
+                }
+            }
+            R.jb1 += shift;
+            R.jb2 += shift;
+            return R;
+        };
+        // one column alone (its wrapped run too); the target itself is
+        // excluded from the direct family only
+        auto scan_col = [&](const Runs &R) {
+            if constexpr (FP32) {
+                scan32(R.jb1, R.len1, R.xt, me.y, R.jb1, 0, R.xt, me.y);
+                if (__ballot(R.len2 > 0) != 0) scan32(R.jb2, R.len2, R.xt, me.y - R.sy2, R.jb2, 0, R.xt, me.y);
+            } else {
+                scan64(R.jb1, R.len1, R.xt, me.y, f == 0 ? t - R.jb1 : -1);
+                if (__ballot(R.len2 > 0) != 0) scan64(R.jb2, R.len2, R.xt, me.y - R.sy2, f == 0 ? t - R.jb2 : -1);
+            }
+        };
         const int xlo = allx ? 0 : -d.reach, xhi = allx ? d.ncx - 1 : d.reach;
+        const int ncol = xhi - xlo + 1;
         for (int lz = wzlo; lz <= wzhi; lz++) {
             const bool lay_on = lz >= lzlo && lz <= lzhi;
             const float dzmin = (float)fmax(0.0, fmax(lz * d.hz - tz, tz - (lz + 1) * d.hz));
-            for (int ox = xlo + (int)blockIdx.y; ox <= xhi; ox += a.nsplit) {
-                const int dxc = allx ? ox - cx : ox;       // column offset in cells
-                int cxx = allx ? ox : cx + ox;
-                if (!allx) cxx += cxx < 0 ? d.ncx : (cxx >= d.ncx ? -d.ncx : 0);
-                float dxmin = 0.0f;
-                if (!allx) dxmin = dxc > 0 ? dxc * hxf - xrel : (dxc < 0 ? xrel - (dxc + 1) * hxf : 0.0f);
-                const double xt = me.x - dxc * d.hx;
-                const float ye2 = rcm2 - dxmin * dxmin - dzmin * dzmin;
-                // up to two runs of cells along y: [ya, yb] unshifted, the wrapped one shifted by sy2
-                int jb1 = 0, len1 = 0, jb2 = 0, len2 = 0;
-                double sy2 = 0.0;
-                if (lay_on && ye2 > 0.0f) {
-                    const int row = (lz * d.ncx + cxx) * d.ncy;
-                    if (ally) {
-                        jb1 = start[row];
-                        len1 = start[row + d.ncy] - jb1;
+            if (FP32 && a.nsplit == 1) {
+                // columns in the order 0, -1, +1, -2, +2 (every column in
+                // index order when all are searched): the first alone, then
+                // pairs scanned as one sequence per lane
+                auto col = [&](int i) { return allx ? i : (i == 0 ? 0 : ((i & 1) ? -((i + 1) >> 1) : (i >> 1))); };
+                scan_col(col_runs(lay_on, lz, dzmin, col(0)));
+                for (int i = 1; i < ncol; i += 2) {
+                    const Runs A = col_runs(lay_on, lz, dzmin, col(i));
+                    if (i + 1 < ncol) {
+                        const Runs B = col_runs(lay_on, lz, dzmin, col(i + 1));
+                        scan32(A.jb1, A.len1, A.xt, me.y, B.jb1, B.len1, B.xt, me.y);
+                        if (__ballot(A.len2 > 0) != 0)
+                            scan32(A.jb2, A.len2, A.xt, me.y - A.sy2, A.jb2, 0, A.xt, me.y);
+                        if (__ballot(B.len2 > 0) != 0)
+                            scan32(B.jb2, B.len2, B.xt, me.y - B.sy2, B.jb2, 0, B.xt, me.y);
                     } else {
-                        const float ye = __builtin_amdgcn_sqrtf(ye2) + rmarg;
-                        int cylo = cy + (int)floorf((yrel - ye) * inv_hyf);
-                        int cyhi = cy + (int)floorf((yrel + ye) * inv_hyf);
-                        cylo = max(cylo, cy - d.reach_y);
-                        cyhi = min(cyhi, cy + d.reach_y);
-                        const int ya = max(cylo, 0), yb = min(cyhi, d.ncy - 1);
-                        if (ya <= yb) { jb1 = start[row + ya]; len1 = start[row + yb + 1] - jb1; }
-                        if (cylo < 0) {
-                            jb2 = start[row + cylo + d.ncy];
-                            len2 = start[row + d.ncy] - jb2;
-                            sy2 = -d.Ly;
-                        } else if (cyhi >= d.ncy) {
-                            jb2 = start[row];
-                            len2 = start[row + cyhi - d.ncy + 1] - jb2;
-                            sy2 = d.Ly;
-                        }
+                        scan_col(A);
                     }
                 }
-                jb1 += shift;
-                jb2 += shift;
-                // the target itself is excluded from the direct family only
-                const int self1 = f == 0 ? t - jb1 : -1;
-                const int self2 = f == 0 ? t - jb2 : -1;
-                scan(jb1, len1, xt, me.y, self1);
-                if (__ballot(len2 > 0) != 0) scan(jb2, len2, xt, me.y - sy2, self2);
+            } else {
+                for (int ox = xlo + (int)blockIdx.y; ox <= xhi; ox += a.nsplit)
+                    scan_col(col_runs(lay_on, lz, dzmin, ox));
             }
         }
         qu.flush();
