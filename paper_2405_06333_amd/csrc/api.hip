@@ -634,10 +634,12 @@ rbe2d_status vv_unit(rbe2d_ctx *h, double *pos, double *vel, const double *q, do
     hipStream_t ks = h->side;
     RBE2D_TRY(h, hipEventRecord(h->fork_ev, s), "fork event");
     RBE2D_TRY(h, hipStreamWaitEvent(ks, h->fork_ev, 0), "fork wait");
+    // real space first: its latency-bound cell list then starts ahead of the
+    // structure factors (also in a captured graph, whose nodes follow this order)
+    RBE2D_TRY(h, launch_real(h, pos, q, false, s), "real-space launch");
     RBE2D_TRY(h, launch_kcoef_sf(h, ks, true), "structure-factor launch");
     RBE2D_TRY(h, launch_kforce(h, pos, q, F, nullptr, RBE2D_KSPACE | RBE2D_IBC, false, false, false, nullptr, ks),
               "force launch");
-    RBE2D_TRY(h, launch_real(h, pos, q, false, s), "real-space launch");
     RBE2D_TRY(h, hipEventRecord(h->join_ev, ks), "join event");
     RBE2D_TRY(h, hipStreamWaitEvent(s, h->join_ev, 0), "join wait");
     if (!last) {
