@@ -510,9 +510,12 @@ rbe2d_status run_common(rbe2d_ctx *h, const double *pos, const double *q, uint32
         RBE2D_TRY(h, hipEventRecord(h->fork_ev, s), "fork event");
         RBE2D_TRY(h, hipStreamWaitEvent(ks, h->fork_ev, 0), "fork wait");
     }
+    // with two streams, real space is enqueued first (its cell list starts
+    // ahead of the structure factors); on one stream the order is as listed
+    if (real && ks != s) RBE2D_TRY(h, launch_real(h, pos, q, want_dg, s), "real-space launch");
     if (kside) RBE2D_TRY(h, launch_prep(h, pos, q, ks), "prep launch");
     if (flags & RBE2D_KSPACE) RBE2D_TRY(h, launch_kcoef_sf(h, ks), "structure-factor launch");
-    if (real) RBE2D_TRY(h, launch_real(h, pos, q, want_dg, s), "real-space launch");
+    if (real && ks == s) RBE2D_TRY(h, launch_real(h, pos, q, want_dg, s), "real-space launch");
     if (ks != s) {
         RBE2D_TRY(h, hipEventRecord(h->join_ev, ks), "join event");
         RBE2D_TRY(h, hipStreamWaitEvent(s, h->join_ev, 0), "join wait");
@@ -532,11 +535,11 @@ rbe2d_status compute_forces(rbe2d_ctx *h, const double *pos, const double *q, do
         hipStream_t ks = h->side;
         RBE2D_TRY(h, hipEventRecord(h->fork_ev, s), "fork event");
         RBE2D_TRY(h, hipStreamWaitEvent(ks, h->fork_ev, 0), "fork wait");
+        RBE2D_TRY(h, launch_real(h, pos, q, false, s), "real-space launch");
         RBE2D_TRY(h, launch_prep(h, pos, q, ks), "prep launch");
         if (parts & RBE2D_KSPACE) RBE2D_TRY(h, launch_kcoef_sf(h, ks), "structure-factor launch");
         RBE2D_TRY(h, launch_kforce(h, pos, q, F, nullptr, parts & ~(uint32_t)RBE2D_REAL, accumulate, false, false,
                                    nullptr, ks), "force launch");
-        RBE2D_TRY(h, launch_real(h, pos, q, false, s), "real-space launch");
         RBE2D_TRY(h, hipEventRecord(h->join_ev, ks), "join event");
         RBE2D_TRY(h, hipStreamWaitEvent(s, h->join_ev, 0), "join wait");
         RBE2D_TRY(h, launch_add_real(h, F, vel, 0.5 * dt, s), "real-space add");
