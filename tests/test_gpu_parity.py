@@ -164,12 +164,15 @@ def test_close_pairs(torch, R, orc, precision):
     assert rel.max() <= 10 * TOL[precision], rel.max()
 
 
-def test_small_box_minimum_image(torch, R, orc):
-    """Lx < 3 r_c: fewer than three cells per axis, minimum image per pair."""
-    w = inputs.small_random(5, 200, L=7.0, H=3.0, gamma_top=0.3, gamma_bot=0.2, alpha=1.2, r_c=3.4,
-                            P=20, M=2)
-    F, E, ref, _ = run_pair(torch, R, orc, w, "fp64")
-    assert_parity(F, E, ref, 1e-9)
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("Ly", [7.0, 12.0], ids=["square", "rect"])
+def test_small_box_minimum_image(torch, R, orc, precision, Ly):
+    """Lx < 2.5 r_c: the pair kernel searches every x-column (four of them,
+    the FP32 kernel as one column alone, one pair and one more alone), and
+    every y-cell of the square box, with the minimum image per pair."""
+    w = inputs.Workload(f"smallbox{Ly:g}", 200, 7.0, Ly, 3.0, 0.3, 0.2, 1.2, 3.4, 20, 2, seed=5)
+    F, E, ref, _ = run_pair(torch, R, orc, w, precision)
+    assert_parity(F, E, ref, TOL[precision])
 
 
 def test_empty_input(torch, R):
