@@ -217,7 +217,7 @@ rbe2d_status setup_system(const rbe2d_params *pin, SysHost &sh) {
     }
     d.ncx = ncx; d.ncy = ncy; d.ncz = ncz;
     d.hx = p.Lx / ncx; d.hy = p.Ly / ncy; d.hz = p.H / ncz;
-    d.inv_hy = 1.0 / d.hy; d.inv_hz = 1.0 / d.hz;
+    d.inv_hx = 1.0 / d.hx; d.inv_hy = 1.0 / d.hy; d.inv_hz = 1.0 / d.hz;
     d.inv_Lx = 1.0 / p.Lx; d.inv_Ly = 1.0 / p.Ly; d.inv_Lz = 1.0 / d.Lz;
     // fixed-point frame of the FP32 pair kernel.  z (and every transformed
     // target height within r_c of the slab) lies in [-zoff, zspan - zoff);
@@ -528,16 +528,21 @@ rbe2d_status run_common(rbe2d_ctx *h, const double *pos, const double *q, uint32
 // scatter runs on the side stream (writing F) while the cell list and pair
 // kernel run on `s`; after the join one pass adds the real-space forces and,
 // when vel is set, applies the closing half kick v += dt/2 F of an MD step.
+// With mxs set, the MD's short-range forces are added too (on `s`, into the
+// pair kernel's output while the k-space chain runs).
 rbe2d_status compute_forces(rbe2d_ctx *h, const double *pos, const double *q, double *F, uint32_t parts,
-                            bool accumulate, double *vel, double dt, hipStream_t s) {
+                            bool accumulate, double *vel, double dt, hipStream_t s, const MdExtra *mxs) {
     const bool kside = (parts & (RBE2D_KSPACE | RBE2D_IBC)) != 0;
     if (kside && (parts & RBE2D_REAL) && h->n_total > 0) {
         hipStream_t ks = h->side;
         RBE2D_TRY(h, hipEventRecord(h->fork_ev, s), "fork event");
         RBE2D_TRY(h, hipStreamWaitEvent(ks, h->fork_ev, 0), "fork wait");
         RBE2D_TRY(h, launch_real(h, pos, q, false, s), "real-space launch");
-        RBE2D_TRY(h, launch_prep(h, pos, q, ks), "prep launch");
-        if (parts & RBE2D_KSPACE) RBE2D_TRY(h, launch_kcoef_sf(h, ks), "structure-factor launch");
+        if (mxs) RBE2D_TRY(h, launch_short(h, *mxs, nullptr, nullptr, s, true), "short-range launch");
+        // with k-space the assembly launch computes the IBC scalars
+        const bool sc_asm = (parts & RBE2D_KSPACE) != 0;
+        RBE2D_TRY(h, launch_prep(h, pos, q, ks, !sc_asm), "prep launch");
+        if (parts & RBE2D_KSPACE) RBE2D_TRY(h, launch_kcoef_sf(h, ks, true), "structure-factor launch");
         RBE2D_TRY(h, launch_kforce(h, pos, q, F, nullptr, parts & ~(uint32_t)RBE2D_REAL, accumulate, false, false,
                                    nullptr, ks), "force launch");
         RBE2D_TRY(h, hipEventRecord(h->join_ev, ks), "join event");
@@ -549,6 +554,7 @@ rbe2d_status compute_forces(rbe2d_ctx *h, const double *pos, const double *q, do
     if (st) return st;
     RBE2D_TRY(h, launch_kforce(h, pos, q, F, nullptr, parts, accumulate, false, (parts & RBE2D_REAL) != 0, nullptr,
                                s), "force launch");
+    if (mxs) RBE2D_TRY(h, launch_short(h, *mxs, F, nullptr, s), "short-range launch");
     if (vel) RBE2D_TRY(h, launch_md_kick(h, vel, F, dt, s), "md kick");
     return RBE2D_OK;
 }
@@ -560,7 +566,7 @@ rbe2d_status run_forces(rbe2d_ctx *h, const double *pos, const double *q, double
     if (st) return st;
     if (h->n_total > 0 && !F) return fail(h, RBE2D_E_INVAL, "F is NULL");
     const uint32_t parts = flags & RBE2D_ALL;
-    st = compute_forces(h, pos, q, F, parts, (flags & RBE2D_ACCUMULATE) != 0, nullptr, 0.0, s);
+    st = compute_forces(h, pos, q, F, parts, (flags & RBE2D_ACCUMULATE) != 0, nullptr, 0.0, s, nullptr);
     if (st) return st;
     if (energy) RBE2D_TRY(h, launch_energy(h, energy, parts, nullptr, nullptr, s), "energy launch");
     return RBE2D_OK;
@@ -608,15 +614,11 @@ rbe2d_status md_step(rbe2d_ctx *h, double *pos, double *vel, const double *q, do
         RBE2D_TRY(h, launch_md_kick_drift_langevin(h, pos, vel, F, dt, *mx, seed, sbase,
                                                    dev_step ? h->w.step : nullptr, s), "md drift");
     RBE2D_TRY(h, launch_sample(h, seed, sbase, dev_step ? h->w.step : nullptr, s), "md sample");
+    // short-range forces and the closing half kick are fused into the force
+    // evaluation
     const bool shortr = mx && mx->short_on();
-    // the closing half kick is fused into the force pass unless short-range
-    // forces still have to be added
-    rbe2d_status st = compute_forces(h, pos, q, F, RBE2D_ALL, false, shortr ? nullptr : vel, dt, s);
+    rbe2d_status st = compute_forces(h, pos, q, F, RBE2D_ALL, false, vel, dt, s, shortr ? mx : nullptr);
     if (st) return st;
-    if (shortr) {
-        RBE2D_TRY(h, launch_short(h, *mx, F, nullptr, s), "md short-range");
-        RBE2D_TRY(h, launch_md_kick(h, vel, F, dt, s), "md kick");
-    }
     if (dev_step) RBE2D_TRY(h, launch_step_inc(h, s), "md step counter");
     return RBE2D_OK;
 }

@@ -182,12 +182,12 @@ static void launch_prep_kernel(rbe2d_ctx *h, const PrepArgs &a, hipStream_t s) {
         hipLaunchKernelGGL((k_prep<false, MD>), dim3(h->n_blocks), dim3(kBlock), 0, s, a);
 }
 
-hipError_t launch_prep(rbe2d_ctx *h, const double *pos, const double *q, hipStream_t s) {
+hipError_t launch_prep(rbe2d_ctx *h, const double *pos, const double *q, hipStream_t s, bool scalars) {
     // the k-vector table needs only the k-set: first, off the particles' path
     launch_ktable(h, s);
     prof_begin(h, 0, s);
     launch_prep_kernel<0>(h, prep_args(h, pos, q), s);
-    launch_scalars(h, s);
+    if (scalars) launch_scalars(h, s);
     prof_end(h, 0, s);
     return hipGetLastError();
 }

@@ -53,7 +53,7 @@ struct SysDesc {
     double g1, cgam, dg1t, dg1b, dcgt, dcgb;   // IBC image-dipole coefficients
     double cfac;                               // 2 pi S pref / (V P)
     double scale_h;                            // 2^fh_bits (FP32 phase split)
-    double hx, hy, hz, inv_hy, inv_hz;         // cell sizes
+    double hx, hy, hz, inv_hx, inv_hy, inv_hz;  // cell sizes
     double inv_Lx, inv_Ly, inv_Lz;
     int ncx, ncy, ncz, reach, reach_y, nfam, M, fh_bits, cbase;
     int nmax[3], cdf_off[3];                   // sampler tables in the shared CDF array
@@ -217,7 +217,9 @@ struct rbe2d_ctx {
 namespace rbe2d {
 
 // kernel launchers (return hipSuccess or the launch error); all systems at once
-hipError_t launch_prep(rbe2d_ctx *h, const double *pos, const double *q, hipStream_t s);
+// k-vector table, particle records and IBC block sums; with scalars, also
+// the IBC scalars (else the assembly launch computes them)
+hipError_t launch_prep(rbe2d_ctx *h, const double *pos, const double *q, hipStream_t s, bool scalars = true);
 // structure factors and per-k assembly; with_scalars: the assembly launch
 // also computes the IBC scalars (otherwise the prep launch does)
 hipError_t launch_kcoef_sf(rbe2d_ctx *h, hipStream_t s, bool with_scalars = false);
@@ -230,7 +232,10 @@ hipError_t launch_real(rbe2d_ctx *h, const double *pos, const double *q, bool wa
 hipError_t launch_cells(rbe2d_ctx *h, const double *pos, const double *q, hipStream_t s);
 hipError_t launch_pairs(rbe2d_ctx *h, bool want_dg, hipStream_t s);
 hipError_t launch_add_real(rbe2d_ctx *h, double *F, double *vel, double half_dt, hipStream_t s);
-hipError_t launch_short(rbe2d_ctx *h, const MdExtra &mx, double *F, double *energy, hipStream_t s);
+// short-range forces added to F, or with into_real to the pair kernel's
+// per-particle output (then folded into F with the real-space forces)
+hipError_t launch_short(rbe2d_ctx *h, const MdExtra &mx, double *F, double *energy, hipStream_t s,
+                        bool into_real = false);
 hipError_t launch_md_kick_drift_langevin(rbe2d_ctx *h, double *pos, double *vel, const double *F, double dt,
                                          const MdExtra &mx, uint64_t seed, uint64_t stream_base,
                                          const long long *dev_step, hipStream_t s);

@@ -900,9 +900,11 @@ hipError_t launch_add_real(rbe2d_ctx *h, double *F, double *vel, double half_dt,
 // ---------------------------------------------------------------------------
 // Short-range forces of the MD (purely repulsive shifted-truncated LJ between
 // ions and against the walls), on the cell list of the pair kernel.  One
-// thread per target in cell order; the cells within the LJ cutoff of the
-// target's cell are searched (all columns or rows of a small box once).
-// Forces are added to F; per-wave energy sums go to spart.
+// thread per target in cell order; within the layers and x-columns that come
+// within the LJ cutoff of the target, the cells along y within its y-extent
+// (all columns or rows of a small box once).  Forces are added to
+// F[stride * i + 0..2] (the caller's N x 3 forces, or the pair kernel's
+// per-particle output); per-wave energy sums go to spart.
 // ---------------------------------------------------------------------------
 
 struct ShortArgs {
@@ -913,6 +915,7 @@ struct ShortArgs {
     int n_sys, n_waves;
     MdExtra mx;
     double *F;
+    int stride;
     double *spart;
 };
 
@@ -935,27 +938,43 @@ __global__ __launch_bounds__(kBlock) void k_short(ShortArgs a) {
         const int cy = cid % d.ncy, cx = (cid / d.ncy) % d.ncx, cz = cid / (d.ncy * d.ncx);
         const double xt = me.x + cx * d.hx;   // wrapped x of the target
         if (a.mx.eps != 0.0) {
-            const double rc = sqrt(a.mx.rc2);
-            const int rx = (int)ceil(rc / d.hx), ry = (int)ceil(rc / d.hy), rz = (int)ceil(rc / d.hz);
+            // cell ranges within the cutoff, with a 1e-9 margin (cells were
+            // assigned by division); a small box searches each column or row once
+            const double rc = sqrt(a.mx.rc2) * (1.0 + 1e-9);
+            const int rx = (int)ceil(rc / d.hx), ry = (int)ceil(rc / d.hy);
             const bool allx = d.ncx <= 2 * rx, ally = d.ncy <= 2 * ry;
-            const int x0 = allx ? 0 : cx - rx, x1 = allx ? d.ncx - 1 : cx + rx;
-            const int y0 = ally ? 0 : cy - ry, y1 = ally ? d.ncy - 1 : cy + ry;
-            const int z0 = max(0, cz - rz), z1 = min(d.ncz - 1, cz + rz);
+            const int x0 = allx ? 0 : cx + (int)floor((me.x - rc) * d.inv_hx);
+            const int x1 = allx ? d.ncx - 1 : cx + (int)floor((me.x + rc) * d.inv_hx);
+            const double yrel = me.y - cy * d.hy;
+            const int y0 = ally ? 0 : cy + (int)floor((yrel - rc) * d.inv_hy);
+            const int y1 = ally ? d.ncy - 1 : cy + (int)floor((yrel + rc) * d.inv_hy);
+            const int z0 = max(0, (int)floor((me.z - rc) * d.inv_hz));
+            const int z1 = min(d.ncz - 1, (int)floor((me.z + rc) * d.inv_hz));
             const int *start = a.start + d.cbase;
             for (int lz = z0; lz <= z1; lz++)
                 for (int ix = x0; ix <= x1; ix++) {
-                    const int cxx = (ix + d.ncx) % d.ncx;
-                    for (int iy = y0; iy <= y1; iy++) {
-                        const int cyy = (iy + d.ncy) % d.ncy;
-                        const int c = (lz * d.ncx + cxx) * d.ncy + cyy;
-                        const int b = start[c] + shift, e = start[c + 1] + shift;
+                    const int cxx = (ix % d.ncx + d.ncx) % d.ncx;
+                    const int row = (lz * d.ncx + cxx) * d.ncy;
+                    // along y: one run of cells, or two where it wraps
+                    for (int part = 0; part < 2; part++) {
+                        int ya = y0, yb = y1;
+                        if (!ally) {
+                            if (part == 0) { ya = max(y0, 0); yb = min(y1, d.ncy - 1); }
+                            else if (y0 < 0) { ya = y0 + d.ncy; yb = d.ncy - 1; }
+                            else if (y1 >= d.ncy) { ya = 0; yb = y1 - d.ncy; }
+                            else break;
+                        } else if (part == 1) {
+                            break;
+                        }
+                        if (ya > yb) continue;
+                        const int b = start[row + ya] + shift, e = start[row + yb + 1] + shift;
                         for (int j = b; j < e; j++) {
                             if (j == t) continue;
                             const double4 sj = a.src[j];
                             double dx = xt - (sj.x + cxx * d.hx);
                             double dy = me.y - sj.y;
-                            dx -= d.Lx * rint(dx / d.Lx);
-                            dy -= d.Ly * rint(dy / d.Ly);
+                            dx -= d.Lx * rint(dx * d.inv_Lx);
+                            dy -= d.Ly * rint(dy * d.inv_Ly);
                             const double dz = me.z - sj.z;
                             const double r2 = dx * dx + dy * dy + dz * dz;
                             if (r2 < a.mx.rc2) {
@@ -974,9 +993,10 @@ __global__ __launch_bounds__(kBlock) void k_short(ShortArgs a) {
             if (ht > 0.0 && ht < a.mx.hcut) { ew += lj_rep(a.mx.sigw2 / (ht * ht), a.mx.epsw, &rf); fz -= rf / ht; }
         }
         const int i = a.sidx[t];
-        a.F[3 * (int64_t)i] += fx;
-        a.F[3 * (int64_t)i + 1] += fy;
-        a.F[3 * (int64_t)i + 2] += fz;
+        double *o = a.F + (int64_t)a.stride * i;
+        o[0] += fx;
+        o[1] += fy;
+        o[2] += fz;
     }
     ep = wave_sum(ep);
     ew = wave_sum(ew);
@@ -1003,13 +1023,16 @@ __global__ __launch_bounds__(kBlock) void k_short_energy(const double *spart, La
     }
 }
 
-hipError_t launch_short(rbe2d_ctx *h, const MdExtra &mx, double *F, double *energy, hipStream_t s) {
+hipError_t launch_short(rbe2d_ctx *h, const MdExtra &mx, double *F, double *energy, hipStream_t s, bool into_real) {
     prof_begin(h, 9, s);
     if (h->n_total > 0 && mx.short_on()) {
         ShortArgs a;
         a.src = h->w.sorted; a.sidx = h->w.sidx; a.scell = h->w.scell; a.start = h->w.start;
         a.sys = h->w.sys; a.lay = h->w.lay; a.n_sys = h->n_sys; a.n_waves = h->n_swaves;
-        a.mx = mx; a.F = F; a.spart = h->w.spart;
+        a.mx = mx; a.spart = h->w.spart;
+        // into_real: add to the pair kernel's per-particle output (x, y, z, phi)
+        a.F = into_real ? (double *)h->w.freal : F;
+        a.stride = into_real ? 4 : 3;
         hipLaunchKernelGGL(k_short, dim3((h->n_swaves * kWave + kBlock - 1) / kBlock), dim3(kBlock), 0, s, a);
     }
     if (energy) {
