@@ -89,6 +89,8 @@ def parse():
     ap.add_argument("--cpu-targets", type=int, default=32, help="oracle force targets")
     ap.add_argument("--side-steps", type=int, default=10, help="steps of each side measurement (0 = skip)")
     ap.add_argument("--no-autotune", action="store_true", help="use the built-in launch heuristics")
+    ap.add_argument("--parts-only", type=int, default=0,
+                    help="only time this many force calls of each half alone (for counter runs)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (HBM counter calibration)")
     return ap.parse_args()
@@ -395,6 +397,13 @@ def main():
     import torch
     if a.copy_mib:
         copy_probe(torch, a.copy_mib)
+        return 0
+    if a.parts_only:
+        from paper_2405_06333_amd import inputs as _inputs, rbe2d as _R
+        _R.lib()
+        alone = run_parts(_R, torch, _inputs.LARGE_MD, a.precision, a.parts_only)
+        print(json.dumps({h: {k: {"ms_total": t, "launches": n} for k, (t, n) in v.items() if n}
+                          for h, v in alone.items()}), flush=True)
         return 0
     from paper_2405_06333_amd import inputs, rbe2d as R
     R.lib()

@@ -569,39 +569,54 @@ __global__ __launch_bounds__(kBlock) void k_force32(ForceArgs a) {
     const int l1 = min(a.P, l0 + a.k_per_split);
     double Fx = 0, Fy = 0, Fz = 0, Pt = 0;
     if (a.do_kspace) {
+        // per k: n (kn), k and |k_xy|^2 (kv), and the amplitudes (ab for the
+        // potentials, else their polar form)
+        constexpr int kExtra = MODE == 1 ? 1 : 2;
+        float fx = 0, fy = 0, fz = 0, pt = 0;
+        auto one = [&](const float4 &n, const float4 &kv, const float4 &ex) {
+            float pxy = fractf(fmaf(n.y, pa.z, n.x * pa.x));
+            pxy = fmaf(n.x, pa.y, pxy);
+            pxy = fmaf(n.y, pa.w, pxy);
+            const float pz = fmaf(n.z, pb.y, fractf(n.z * pb.x));
+            float X, Y;   // Im(e^{-i ph} cA), Im(e^{-i phh} cB)
+            if (MODE == 1) {
+                // the potential needs the real parts too (ex = cA, cB)
+                const float ph = pxy + pz, phh = pxy - pz;
+                const float c1f = cos_rev(ph), s1f = sin_rev(ph);
+                const float c2f = cos_rev(phh), s2f = sin_rev(phh);
+                X = fmaf(ex.y, c1f, -ex.x * s1f);
+                Y = fmaf(ex.w, c2f, -ex.z * s2f);
+                pt = fmaf(ex.x, c1f, pt); pt = fmaf(ex.y, s1f, pt);
+                pt = fmaf(ex.z, c2f, pt); pt = fmaf(ex.w, s2f, pt);
+            } else {
+                // polar form: one transcendental per product
+                X = ex.x * sin_rev((ex.y - pxy) - pz);
+                Y = ex.z * sin_rev((ex.w - pxy) + pz);
+            }
+            const float sp = X + Y, sm = X - Y;
+            fx = fmaf(kv.x, sp, fx);
+            fy = fmaf(kv.y, sp, fy);
+            fz = fmaf(kv.z, sm, fz);
+            if (MODE == 2) pt = fmaf(kv.w * sp, sp, fmaf(kv.z * sm, kv.z * sm, pt));
+        };
         for (int c0 = l0; c0 < l1; c0 += 64) {
             const int c1 = min(l1, c0 + 64);
-            float fx = 0, fy = 0, fz = 0, pt = 0;
-            for (int l = c0; l < c1; l++) {
-                const float4 n = kn[l];
-                const float4 kv = kf[3 * l];
-                float pxy = fractf(fmaf(n.y, pa.z, n.x * pa.x));
-                pxy = fmaf(n.x, pa.y, pxy);
-                pxy = fmaf(n.y, pa.w, pxy);
-                const float pz = fmaf(n.z, pb.y, fractf(n.z * pb.x));
-                float X, Y;   // Im(e^{-i ph} cA), Im(e^{-i phh} cB)
-                if (MODE == 1) {
-                    // the potential needs the real parts too
-                    const float4 ab = kf[3 * l + 1];
-                    const float ph = pxy + pz, phh = pxy - pz;
-                    const float c1f = cos_rev(ph), s1f = sin_rev(ph);
-                    const float c2f = cos_rev(phh), s2f = sin_rev(phh);
-                    X = fmaf(ab.y, c1f, -ab.x * s1f);
-                    Y = fmaf(ab.w, c2f, -ab.z * s2f);
-                    pt = fmaf(ab.x, c1f, pt); pt = fmaf(ab.y, s1f, pt);
-                    pt = fmaf(ab.z, c2f, pt); pt = fmaf(ab.w, s2f, pt);
-                } else {
-                    // polar form: one transcendental per product
-                    const float4 pol = kf[3 * l + 2];
-                    X = pol.x * sin_rev((pol.y - pxy) - pz);
-                    Y = pol.z * sin_rev((pol.w - pxy) + pz);
+            fx = fy = fz = pt = 0;
+            int l = c0;
+            // four k at a time: their records are fetched together (scalar
+            // loads), one wait per four instead of one per k
+            for (; l + 4 <= c1; l += 4) {
+                float4 n[4], kv[4], ex[4];
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
+                    n[j] = kn[l + j];
+                    kv[j] = kf[3 * (l + j)];
+                    ex[j] = kf[3 * (l + j) + kExtra];
                 }
-                const float sp = X + Y, sm = X - Y;
-                fx = fmaf(kv.x, sp, fx);
-                fy = fmaf(kv.y, sp, fy);
-                fz = fmaf(kv.z, sm, fz);
-                if (MODE == 2) pt = fmaf(kv.w * sp, sp, fmaf(kv.z * sm, kv.z * sm, pt));
+#pragma unroll
+                for (int j = 0; j < 4; j++) one(n[j], kv[j], ex[j]);
             }
+            for (; l < c1; l++) one(kn[l], kf[3 * l], kf[3 * l + kExtra]);
             Fx += fx; Fy += fy; Fz += fz; Pt += pt;
         }
     }
