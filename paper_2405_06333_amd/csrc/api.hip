@@ -627,12 +627,13 @@ rbe2d_status md_step(rbe2d_ctx *h, double *pos, double *vel, const double *q, do
 // the current positions (whose k-set is drawn, with its k-vector table, and
 // whose k-space particle records and IBC block sums the preceding MD pass
 // wrote).  The k-space chain (structure factors, assembly with the IBC
-// scalars, force scatter) runs on the side stream, real space on s.  After the forces, either the closing half kick
-// (last step of the run) or one pass with the closing and next opening half
-// kicks, the next drift and the next records.  Meanwhile the side stream
-// draws the next step's k-set (device step counter: incremented there
-// first).  The next step's fork orders that draw before the next k-space
-// chain; a captured step joins it back explicitly (join_tail).
+// scalars, force scatter) runs on the side stream, real space on s.  After
+// the forces, either the closing half kick (last step of the run) or one
+// pass with the closing and next opening half kicks, the next drift and the
+// next records.  Meanwhile the side stream draws the next step's k-set
+// (device step counter: incremented there first) and builds its table.
+// The next step's fork orders that draw before the next k-space chain; a
+// captured step joins it back explicitly (join_tail).
 rbe2d_status vv_unit(rbe2d_ctx *h, double *pos, double *vel, const double *q, double *F, double dt, double zlo,
                      double zhi_from_top, uint64_t seed, int64_t step, bool dev_step, bool last, bool join_tail,
                      hipStream_t s) {
