@@ -182,3 +182,46 @@ def test_velocity_verlet_steps_match_oracle(torch, R, orc, use_graph):
     assert rel_rms(V_.cpu().numpy(), v) <= 1e-11
     assert rel_rms(F_.cpu().numpy(), F) <= 1e-9
     assert np.array_equal(s.get_kset(), orc.draw_kset(o, seed, step0 + 3))
+
+
+def _wall_fractions(torch, R, gamma, seed=61, N=600, L=24.0, H=8.0, band=1.0):
+    """Langevin + WCA run of a 2:1 electrolyte (Bjerrum length 3.5 sigma) with
+    dielectric contrast gamma at both faces: the fraction of cation and of
+    anion positions within `band` of either wall, over 100 snapshots after
+    3000 steps of equilibration."""
+    w = inputs.small_random(seed, N, L=L, H=H, gamma_top=gamma, gamma_bot=gamma, alpha=0.6, r_c=6.0, P=64, M=8,
+                            valence=(2, -1), margin=0.6).with_(extra={"dmin": 0.9})
+    pos, q = inputs.sample(w)
+    md = R.md_params(gamma=1.0, kT=1.0, sigma=1.0, eps=1.0, sigma_wall=0.5, eps_wall=1.0, wall_margin=0.05)
+    s = R.Slab(**w.slab_kwargs(), precision="fp32", n_max=N, coulomb_prefactor=3.5)
+    P_, Q_ = to_dev(torch, pos), to_dev(torch, q)
+    V_ = torch.zeros_like(P_)
+    s.sample_kset(7, 0)
+    F_ = s.forces(P_, Q_)
+    s.short_forces(P_, Q_, md, F=F_)
+    s.md_run_ex(P_, V_, Q_, F_, 5e-3, md, 7, 0, 3000, use_graph=True)
+    zs, step = [], 3000
+    for _ in range(100):
+        s.md_run_ex(P_, V_, Q_, F_, 5e-3, md, 7, step, 30, use_graph=True)
+        step += 30
+        zs.append(P_[:, 2].cpu().numpy().copy())
+    s.check()
+    z = np.stack(zs)
+    near = (z < band) | (z > H - band)
+    return float(near[:, q > 0].mean()), float(near[:, q < 0].mean())
+
+
+def test_ion_depletion_near_insulating_interfaces(torch, R):
+    """The MD around the path reproduces the ion-depletion effect near
+    insulator-like interfaces (gamma = 0.939 at both faces, Sec. 4): images of
+    the same sign push every ion away from the walls (energy ~ gamma q^2
+    l_B / 4d at distance d), strongest for the divalent cations, and images of
+    the opposite sign (gamma = -0.939) draw them in.  Same ions, seeds and
+    steps with gamma = 0 as the reference; measured 0.101 of the cation
+    positions within one sigma of a wall at gamma = 0, 0.058 at +0.939, 0.19
+    at -0.939 (two seeds agree to 0.005)."""
+    c0, a0 = _wall_fractions(torch, R, 0.0)
+    cp, ap = _wall_fractions(torch, R, 0.939)
+    cm, am = _wall_fractions(torch, R, -0.939)
+    assert cp < 0.75 * c0 and cm > 1.4 * c0, (c0, cp, cm)
+    assert ap < a0 < am, (a0, ap, am)
