@@ -609,7 +609,9 @@ rbe2d_status md_step(rbe2d_ctx *h, double *pos, double *vel, const double *q, do
                      const MdExtra *mx, hipStream_t s) {
     const uint64_t sbase = (uint64_t)step * (uint64_t)h->n_sys;
     // (without mx this runs only for an empty layout: plain velocity Verlet
-    // with particles takes vv_run)
+    // with particles takes vv_run, which applies the wall bounds)
+    (void)zlo;
+    (void)zhi_from_top;
     if (mx)
         RBE2D_TRY(h, launch_md_kick_drift_langevin(h, pos, vel, F, dt, *mx, seed, sbase,
                                                    dev_step ? h->w.step : nullptr, s), "md drift");

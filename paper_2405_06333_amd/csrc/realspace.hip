@@ -101,7 +101,7 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int *sh, int *total) 
     sh[threadIdx.x] = v;
     __syncthreads();
     for (int o = 1; o < kScanBlock; o <<= 1) {
-        const int add = threadIdx.x >= o ? sh[threadIdx.x - o] : 0;
+        const int add = (int)threadIdx.x >= o ? sh[threadIdx.x - o] : 0;
         __syncthreads();
         sh[threadIdx.x] += add;
         __syncthreads();
@@ -935,7 +935,7 @@ __global__ __launch_bounds__(kBlock) void k_short(ShortArgs a) {
     if (active) {
         const double4 me = a.src[t];
         const int cid = a.scell[t];
-        const int cy = cid % d.ncy, cx = (cid / d.ncy) % d.ncx, cz = cid / (d.ncy * d.ncx);
+        const int cy = cid % d.ncy, cx = (cid / d.ncy) % d.ncx;
         const double xt = me.x + cx * d.hx;   // wrapped x of the target
         if (a.mx.eps != 0.0) {
             // cell ranges within the cutoff, with a 1e-9 margin (cells were
