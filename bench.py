@@ -392,7 +392,7 @@ def cpu_baseline(w, n_sample, n_targets):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {a.gpus} is not supported", file=sys.stderr)
+        print(f"bench.py: runs on one GPU only (the kernels work on one GPU's share); --gpus {a.gpus} is not supported", file=sys.stderr)
         return 2
     import torch
     if a.copy_mib:
