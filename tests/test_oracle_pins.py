@@ -6,9 +6,12 @@ conditions of electrostatics), an exact identity, an invariant, or a
 statistical property stated by the paper's theorems.
 """
 import math
+import os
 
 import numpy as np
 import pytest
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
 
@@ -531,9 +534,15 @@ def test_baoab_thermostat_reaches_equipartition(orc):
 
 def test_image_order_reproduces_the_papers_example(orc):
     """After Theorem 3.2: for H about max(Lx, Ly) and |gamma| = 1, an accuracy
-    of 1e-5 needs M = 3 image levels."""
-    assert orc.image_order_for(1e-5, 1.0, 1.0, 10.0, 10.0) == 3
-    assert orc.image_order_for(1e-5, -1.0, 1.0, 10.0, 10.0) == 3
+    of 1e-5 needs M = 3 image levels (fixture tests/golden/image_order_example.txt)."""
+    rows = []
+    with open(os.path.join(GOLDEN, "image_order_example.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                rows.append(line.split())
+    assert rows
+    for tol, gt, gb, H, L, M in rows:
+        assert orc.image_order_for(float(tol), float(gt), float(gb), float(H), float(L)) == int(M)
     # no interface: no image is needed; one interface: its single image
     assert orc.image_order_for(1e-5, 0.0, 0.0, 10.0, 100.0) == 0
     assert orc.image_order_for(1e-5, 0.0, 0.9, 10.0, 100.0) == 1
