@@ -175,6 +175,16 @@ def test_small_box_minimum_image(torch, R, orc, precision, Ly):
     assert_parity(F, E, ref, TOL[precision])
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_cutoff_at_half_box(torch, R, orc, precision):
+    """r_c = Lx/2 = Ly/2, the largest cutoff the minimum image allows: every
+    column and y-cell of the box is searched, displacements reach half a
+    period, and with H < r_c the image orders 1 and 2 enter real space."""
+    w = inputs.Workload("halfbox", 240, 8.0, 8.0, 3.0, 0.5, -0.3, 1.0, 4.0, 30, 3, seed=6)
+    F, E, ref, _ = run_pair(torch, R, orc, w, precision)
+    assert_parity(F, E, ref, TOL[precision])
+
+
 def test_empty_input(torch, R):
     w = inputs.SMALL_FP64
     slab = gpu_slab(R, w, "fp64", n_max=10)
