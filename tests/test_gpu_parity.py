@@ -185,6 +185,28 @@ def test_cutoff_at_half_box(torch, R, orc, precision):
     assert_parity(F, E, ref, TOL[precision])
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_lateral_positions_any_real(torch, R, orc, precision):
+    """x and y are periodic: positions moved by whole periods (negative ones,
+    and up to 1000 periods away) give the forces and energies of the
+    positions in the box, compared with the oracle on the latter."""
+    w = inputs.DIELECTRIC.with_(N=600)
+    pos, q = inputs.sample(w)
+    rng = np.random.default_rng(11)
+    m = rng.integers(-3, 4, size=(w.N, 2)).astype(float)
+    m[:8] = [[1000, -1000], [-1000, 1000], [-1, -1], [-1, 0], [0, -1], [999, 3], [-2, 999], [1, 1]]
+    shifted = pos.copy()
+    shifted[:, 0] += m[:, 0] * w.Lx
+    shifted[:, 1] += m[:, 1] * w.Ly
+    slab = gpu_slab(R, w, precision)
+    kset = slab.draw_kset(w.seed, 0)
+    slab.set_kset(kset)
+    F, E = slab.forces(to_dev(torch, shifted), to_dev(torch, q), want_energy=True)
+    slab.check()
+    ref = orc.evaluate(oracle_slab(orc, w, slab.Lz_ext), pos, q, kset)
+    assert_parity(F.cpu().numpy(), E.cpu().numpy(), ref, TOL[precision])
+
+
 def test_empty_input(torch, R):
     w = inputs.SMALL_FP64
     slab = gpu_slab(R, w, "fp64", n_max=10)
