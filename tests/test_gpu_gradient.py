@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 from paper_2405_06333_amd import inputs
-from tests.gpu_common import gpu_slab, oracle_slab, rel_rms, to_dev
+from tests.gpu_common import energy_scale, gpu_slab, oracle_slab, rel_rms, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -215,3 +215,32 @@ def test_backward_reuses_forward_state(torch, R, precision):
     for res in (reused, between, other):
         for a, b in zip(fresh, res):
             assert rel_rms(b, a) <= tol
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("fp32", 1e-5)])
+def test_non_neutral_charges_and_prefactor(torch, R, orc, precision, tol):
+    """Charges of either sign and any size with a nonzero total (the literal
+    formulas, no neutralising background) and a Coulomb prefactor c: forces,
+    energies and the three gradients are c times the oracle's values at unit
+    prefactor."""
+    w = inputs.small_random(23, 500, L=12.0, H=4.0, gamma_top=-0.6, gamma_bot=0.85, alpha=0.9, r_c=4.5,
+                            P=60, M=4)
+    pos, _ = inputs.sample(w)
+    q = np.random.default_rng(5).uniform(-1.5, 2.0, w.N)
+    assert abs(q.sum()) > 10.0
+    c = 2.5
+    slab = gpu_slab(R, w, precision, coulomb_prefactor=c)
+    n = slab.draw_kset(9)
+    slab.set_kset(n)
+    F, E = slab.forces(to_dev(torch, pos), to_dev(torch, q), want_energy=True)
+    slab.check()
+    F, E = F.cpu().numpy(), E.cpu().numpy()
+    dr, dq, dg = gpu_grads(torch, slab, pos, q)
+    r, dgo = oracle_grads(orc, oracle_slab(orc, w, slab.Lz_ext), pos, q, n)
+    assert rel_rms(F, c * r.F) <= tol
+    scale = c * energy_scale(r)
+    for k, (eg, er) in enumerate(zip(E, r.energies())):
+        assert abs(eg - c * er) <= tol * scale, f"energy[{k}] {eg!r} vs {c * er!r}"
+    assert rel_rms(dr, -c * r.F) <= tol
+    assert rel_rms(dq, c * r.phi) <= tol
+    assert np.allclose(dg, c * dgo, rtol=tol, atol=tol * c * np.abs(dgo).max())
