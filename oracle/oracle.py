@@ -404,10 +404,14 @@ def image_sources(slab: Slab, pos, q, M=None):
     return np.array(sp), np.array(sq), np.array(own), np.array(real)
 
 
-def ewald2d_images(slab: Slab, pos, q, alpha=None, nreal=4, hcut=40.0):
+def ewald2d_images(slab: Slab, pos, q, alpha=None, nreal=4, hcut=40.0, parts=("real", "fourier")):
     """Energy of the truncated image system, U^c_M = 1/2 sum_i q_i phi_M(r_i),
     by the exact Ewald2D formulas (Eqs. (2.6)-(2.9)) applied with the real
     charges as targets and the real charges plus their images as sources.
+    ``parts`` selects the erfc (real-space) part and/or the long-range part
+    (the reciprocal sum of Eq. (2.7), the zero mode of Eq. (2.9) and the
+    self-energy correction), whose sum is the energy; the long-range part
+    alone is what the Fourier expression of Theorem 3.3 approximates.
     O(N^2 M) -- for small N only."""
     from scipy.special import erfc, erf, erfcx
     pos, q = _prep(pos, q)
@@ -430,14 +434,18 @@ def ewald2d_images(slab: Slab, pos, q, alpha=None, nreal=4, hcut=40.0):
     for i in range(N):
         phi = 0.0
         d = pos[i][None, :] - sp                       # (S,3)
-        # real space: all lattice shifts, excluding the (i, n=0) self term
-        r = d[:, None, :] + shifts[None, :, :]
-        rr = np.sqrt((r ** 2).sum(axis=2))
-        self_mask = (own == i) & real
-        zero_shift = (shifts[:, 0] == 0) & (shifts[:, 1] == 0)
-        excl = self_mask[:, None] & zero_shift[None, :]
-        rr_safe = np.where(excl, 1.0, rr)
-        phi += (sq[:, None] * np.where(excl, 0.0, erfc(a * rr_safe) / rr_safe)).sum()
+        if "real" in parts:
+            # real space: all lattice shifts, excluding the (i, n=0) self term
+            r = d[:, None, :] + shifts[None, :, :]
+            rr = np.sqrt((r ** 2).sum(axis=2))
+            self_mask = (own == i) & real
+            zero_shift = (shifts[:, 0] == 0) & (shifts[:, 1] == 0)
+            excl = self_mask[:, None] & zero_shift[None, :]
+            rr_safe = np.where(excl, 1.0, rr)
+            phi += (sq[:, None] * np.where(excl, 0.0, erfc(a * rr_safe) / rr_safe)).sum()
+        if "fourier" not in parts:
+            U += 0.5 * q[i] * phi
+            continue
         # Fourier part, Eq. (2.7): (pi/(Lx Ly)) sum_h' e^{i h.rho} G_a(h, z)/h
         z = d[:, 2]
         ph = np.cos(np.outer(d[:, 0], hx) + np.outer(d[:, 1], hy))   # (S, nh)
@@ -576,7 +584,7 @@ def baoab_step(pos, vel, F, dt, gamma, kT, normals, Lx, Ly, zlo, zhi, force):
 # ---------------------------------------------------------------------------
 
 def image_truncation_estimate(M, g_top, g_bot, H, Lmax):
-    """Eq. (3.37) with unit constant: |g_top|^floor((M+1)/2) |g_bot|^ceil((M+1)/2)
+    """Eq. (3.9) with unit constant: |g_top|^floor((M+1)/2) |g_bot|^ceil((M+1)/2)
     exp(-2 pi H (M-1) / max(Lx, Ly))."""
     a = abs(g_top) ** ((M + 1) // 2) if (M + 1) // 2 else 1.0
     b = abs(g_bot) ** ((M + 2) // 2) if (M + 2) // 2 else 1.0
@@ -584,7 +592,7 @@ def image_truncation_estimate(M, g_top, g_bot, H, Lmax):
 
 
 def image_order_for(tol, g_top, g_bot, H, Lmax, M_max=64):
-    """Smallest M >= 0 whose Eq. (3.37) estimate is at most tol (Theorem 3.2)."""
+    """Smallest M >= 0 whose Eq. (3.9) estimate is at most tol (Theorem 3.2)."""
     for M in range(0, M_max + 1):
         if image_truncation_estimate(M, g_top, g_bot, H, Lmax) <= tol:
             return M

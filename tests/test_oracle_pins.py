@@ -187,6 +187,94 @@ def test_reformulation_converges_to_ewald2d(orc, g_top, g_bot, M):
     assert errs[0] > errs[1] > errs[2] or errs[0] < 1e-9
 
 
+LZ_CASES = [
+    # g_top, g_bot, M, alpha, L, eps, branch of Eq. (3.23) that sets the height
+    (1.0, 1.0, 2, 1.0, 10.0, 1e-3, "elc"),
+    (1.0, 1.0, 2, 1.0, 10.0, 1e-5, "elc"),
+    (0.95, -0.95, 3, 1.0, 10.0, 1e-5, "elc"),
+    (1.0, 1.0, 2, 0.1, 10.0, 1e-5, "err"),
+    (-1.0, 1.0, 1, 0.12, 8.0, 1e-3, "err"),
+]
+
+
+@pytest.mark.parametrize("g_top,g_bot,M,alpha,L,eps,branch", LZ_CASES)
+def test_extended_height_meets_its_tolerance(orc, g_top, g_bot, M, alpha, L, eps, branch):
+    """Eq. (3.23) pinned by the error it is meant to bound (Theorem 3.3): the
+    deterministic k-sum + self + IBC terms at L_z = lz_ext(eps) reproduce the
+    long-range (erf) part of Ewald2D with images to within ~eps relative, and
+    the error grows when L_z is cut below it.  The two branches of the max are
+    exercised separately: the lateral term (ELC error, Eq. (3.21)) for
+    alpha L >> 1 and the Gaussian term (remainder, Eq. (3.22)) for small
+    alpha.  A dropped (M+1)H, a min for the max or a decimal logarithm each
+    fail at least one case."""
+    H = 3.0
+    pos, q = small_system(3, N=6, L=L, H=H)
+    base = dict(Lx=L, Ly=L, H=H, g_top=g_top, g_bot=g_bot, alpha=alpha, rc=L / 2 - 0.01, M=M, P=10)
+    u = orc.ewald2d_images(orc.Slab(**base), pos, q, parts=("fourier",))
+
+    def err(Lz):
+        s = orc.Slab(**base, Lz=Lz)
+        r = orc.evaluate(s, pos, q, *orc.full_kset(s, 40.0), parts=("kspace", "ibc"))
+        return abs(r.E_k + r.E_self + r.E_ibc - u) / abs(u)
+
+    lg = math.log(1.0 / eps)
+    lateral, gauss = L / (2 * math.pi) * lg, math.sqrt(lg) / alpha
+    assert (lateral > gauss) == (branch == "elc")
+    lz = orc.lz_ext(L, L, H, M, alpha, eps)
+    assert err(lz) <= 2.0 * eps
+    if branch == "elc":
+        lg10 = math.log10(1.0 / eps)
+        wrong = [max(lateral, gauss) + H,                                  # (M+1)H dropped
+                 (M + 1) * H + min(lateral, gauss),                        # min for max
+                 (M + 1) * H + max(L / (2 * math.pi) * lg10, math.sqrt(lg10) / alpha)]   # log10
+        for w in wrong:
+            assert err(w) >= 20.0 * eps, w
+    else:
+        # the lateral term alone is not enough where the Gaussian one is larger
+        assert err((M + 1) * H + lateral) >= 1.5 * eps
+
+
+def _fold_by_reflections(z, v, zlo, zhi):
+    """Specular walls by definition: mirror the point in the wall it has
+    crossed, flip v, repeat until it lies between the walls."""
+    while z < zlo or z > zhi:
+        z = 2.0 * zlo - z if z < zlo else 2.0 * zhi - z
+        v = -v
+    return z, v
+
+
+def test_fold_z_is_specular_reflection(orc):
+    """The integrator's wall fold against (a) repeated mirror reflections and
+    (b) the closed form of free flight between two reflecting walls: the
+    unfolded coordinate u = z - zlo maps to the triangle wave
+    zlo + (W/pi) arccos(cos(pi u / W)), W = zhi - zlo, with v_z multiplied by
+    sign(sin(pi u / W)).  Covers no crossing, one crossing of either wall,
+    and several folds in one step in both directions."""
+    rng = np.random.default_rng(12)
+    zlo, zhi = 0.3, 5.7
+    W = zhi - zlo
+    n_multi = 0
+    for k in range(4000):
+        z0 = rng.uniform(zlo, zhi)
+        v = rng.normal(0.0, 1.0) * (10.0 ** rng.uniform(-2, 1.2)) * W   # up to ~16 W per unit time
+        z1 = z0 + v
+        zf, vf = orc.fold_z(z1, v, zlo, zhi)
+        zb, vb = _fold_by_reflections(z1, v, zlo, zhi)
+        assert abs(zf - zb) <= 1e-12 * max(1.0, abs(z1)) and vf == vb, (z0, v)
+        u = z1 - zlo
+        zc = zlo + W / math.pi * math.acos(math.cos(math.pi * u / W))
+        sgn = math.copysign(1.0, math.sin(math.pi * u / W))
+        assert abs(zf - zc) <= 1e-9 * max(1.0, abs(u)) and vf == sgn * v
+        assert zlo <= zf <= zhi
+        n_multi += abs(u) > 2 * W
+    assert n_multi > 200
+    # exact cases: one crossing of each wall, two folds (below, then above)
+    assert orc.fold_z(zlo - 0.25, -3.0, zlo, zhi) == pytest.approx((zlo + 0.25, 3.0))
+    assert orc.fold_z(zhi + 0.5, 2.0, zlo, zhi) == pytest.approx((zhi - 0.5, -2.0))
+    z, v = orc.fold_z(zlo - (W + 0.5), -7.0, zlo, zhi)
+    assert (z, v) == pytest.approx((zhi - 0.5, -7.0))
+
+
 # --------------------------------------------------------------------------
 # Recalibration identity (Sec. 3.4): Y_odd / Y_even folding == explicit images
 # --------------------------------------------------------------------------
@@ -551,7 +639,7 @@ def test_image_order_reproduces_the_papers_example(orc):
 @pytest.mark.parametrize("g,H,L,tol", [(0.9, 10.0, 50.0, 1e-5), (0.95, 40.0, 800.0, 1e-5), (0.5, 5.0, 20.0, 1e-8),
                                        (1.0, 3.0, 9.0, 1e-4)])
 def test_image_order_matches_closed_form(orc, g, H, L, tol):
-    """For |gamma_top| = |gamma_bot| the smallest admissible M is Eq. (3.38)
+    """For |gamma_top| = |gamma_bot| the smallest admissible M is Eq. (3.10)
     rounded up."""
     a = 4 * np.pi * H / L
     lg = np.log(g * g)
