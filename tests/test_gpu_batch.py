@@ -222,28 +222,37 @@ def test_batch_md_step_forces_match_oracle(torch, R, orc):
         assert rel_rms(F[off[r]:off[r + 1]], ref.F) <= 1e-9
 
 
-def test_replica_batch_sampled_parity(torch, R, orc):
-    """The 64-replica batch at full size, FP32 phases, in the launch
-    configuration the benchmark times: sampled particles of four replicas
-    against the oracle's per-target forces."""
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_replica_batch_sampled_parity(torch, R, orc, precision):
+    """The 64-replica batch at full size, in the launch configuration the
+    benchmark times (FP32 phases, and the FP64 batch it reports beside it):
+    sampled particles of four replicas against the oracle's per-target
+    forces, and the k-space, self and IBC energies of every replica (the
+    oracle sums them over all particles of the replica)."""
     ws = inputs.replicas()
     pos, q, counts = batch_inputs(ws)
-    b = make_batch(R, ws, "fp32")
+    b = make_batch(R, ws, precision)
     off = b.offsets(counts)
     b.sample_kset(ws[0].seed, 0)
     kset = b.get_kset()
+    print(f"replicas {precision} total N={off[-1]}", flush=True)
     F, E = b.forces(off, to_dev(torch, pos), to_dev(torch, q), want_energy=True)
     b.check()
     F, E = F.cpu().numpy(), E.cpu().numpy()
     assert np.isfinite(F).all() and np.isfinite(E).all()
+    tol = TOL[precision]
     rng = np.random.default_rng(0)
-    for r in (0, 17, 40, 63):
-        w = ws[r]
-        tg = np.sort(rng.choice(w.N, 24, replace=False))
+    sampled = (0, 17, 40, 63)
+    for r, w in enumerate(ws):
+        tg = np.sort(rng.choice(w.N, 24, replace=False)) if r in sampled else np.zeros(1, dtype=np.int64)
         ref = orc.evaluate(oracle_slab(orc, w, b.Lz_ext[r]), pos[off[r]:off[r + 1]], q[off[r]:off[r + 1]],
                            kset[r], targets=tg)
-        err = rel_rms(F[off[r] + tg], ref.F)
-        assert err <= 1e-5, f"replica {r}: sampled force rel-RMS {err:.3e}"
+        if r in sampled:
+            err = rel_rms(F[off[r] + tg], ref.F)
+            assert err <= tol, f"replica {r}: sampled force rel-RMS {err:.3e}"
+        scale = abs(E[r][1]) + abs(ref.E_k) + abs(ref.E_self) + abs(ref.E_ibc)
+        for k, er in ((2, ref.E_k), (3, ref.E_self), (4, ref.E_ibc)):
+            assert abs(E[r][k] - er) <= tol * scale, f"replica {r} energy[{k}] {E[r][k]!r} vs {er!r}"
 
 
 def test_autotune_single_keeps_results(torch, R, orc):

@@ -275,13 +275,36 @@ def test_invalid_arguments(torch, R):
         slab.set_kset(bad)                  # zero vectors
 
 
-def test_large_md_sampled_particles(torch, R, orc):
+def assert_energy_parts(E, ref, tol):
+    """E_k, E_self and E_ibc (computed by the oracle over every particle, also
+    when its forces are sampled) against the GPU's, relative to the sum of
+    the magnitudes of all four components (E_real taken from the GPU: the
+    oracle's real-space energy is summed over the sampled targets only)."""
+    scale = abs(E[1]) + abs(ref.E_k) + abs(ref.E_self) + abs(ref.E_ibc)
+    for k, er in ((2, ref.E_k), (3, ref.E_self), (4, ref.E_ibc)):
+        assert abs(E[k] - er) <= tol * scale, f"energy[{k}] {E[k]!r} vs {er!r}"
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_large_md_sampled_particles(torch, R, orc, precision):
     """The 1e6-ion slab in the launch configuration of the benchmark (FP32
-    phases): forces on 96 sampled particles against the oracle."""
+    phases, and the plain FP64 path the benchmark reports beside it): forces
+    on 96 sampled particles, the potential dE/dq_i on the same particles
+    (adjoint entry point) and the k-space, self and IBC energies of the whole
+    slab against the oracle."""
     w = inputs.LARGE_MD
     rng = np.random.default_rng(11)
     targets = np.sort(rng.choice(w.N, 96, replace=False))
-    F, E, ref, slab = run_pair(torch, R, orc, w, "fp32", targets=targets, seed_stream=0)
+    print(f"large_md {precision} N={w.N}", flush=True)
+    F, E, ref, slab = run_pair(torch, R, orc, w, precision, targets=targets, seed_stream=0)
     err = rel_rms(F[targets], ref.F)
-    assert err <= 1e-5, err
+    assert err <= TOL[precision], err
     assert np.all(np.isfinite(F))
+    assert_energy_parts(E, ref, TOL[precision])
+    pos, q = inputs.sample(w)
+    P_, Q_ = to_dev(torch, pos), to_dev(torch, q)
+    slab.energy(P_, Q_)
+    gE = torch.ones((), dtype=torch.float64, device="cuda")
+    _, dq, _ = slab.energy_backward(P_, Q_, gE, want=(False, True, False))
+    slab.check()
+    assert rel_rms(dq.cpu().numpy()[targets], ref.phi) <= TOL[precision]
