@@ -143,7 +143,12 @@ rbe2d_status rbe2d_sample_kset(rbe2d_handle h, uint64_t seed, uint64_t stream_id
 /* Copies the current k-set to n_host (P x 3 int32) and synchronises. */
 rbe2d_status rbe2d_get_kset(rbe2d_handle h, int32_t *n_host, void *stream);
 
-/* Forces (and optionally energies) for N <= n_max charges.
+/* Forces (and optionally energies) for N <= n_max charges: the RBE2D
+ * splitting of Theorem 3.3 (Eq. (3.16) with the ELC and remainder terms
+ * dropped), the k-space part by the random batch estimator over the handle's
+ * k-set with the recalibrated structure factors of Sec. 3.4 (force:
+ * Eqs. (3.25)-(3.26)), the real-space part by the erfc pair sum of Eq. (3.12)
+ * over real charges and images within r_c, plus the IBC and self terms.
  *   pos    device, N x 3      q      device, N
  *   F      device, N x 3, written (or accumulated with RBE2D_ACCUMULATE)
  *   energy device, 5 doubles or NULL: {total, real, kspace, self, ibc}
@@ -154,12 +159,16 @@ rbe2d_status rbe2d_get_kset(rbe2d_handle h, int32_t *n_host, void *stream);
 rbe2d_status rbe2d_forces(rbe2d_handle h, int64_t N, const double *pos, const double *q,
                           double *F, double *energy, uint32_t flags, void *stream);
 
-/* Energy only: energy (device, 5 doubles) as in rbe2d_forces with
+/* Energy only (Theorem 3.3: E_real of Eq. (3.12), the k-space estimator
+ * sum_l c_l Re(rho(k_l) conj(rho^M(k_l))) with the weights of Eq. (3.26),
+ * E_self and U_IBC^M): energy (device, 5 doubles) as in rbe2d_forces with
  * RBE2D_ALL.  Same errors. */
 rbe2d_status rbe2d_energy(rbe2d_handle h, int64_t N, const double *pos, const double *q,
                           double *energy, void *stream);
 
-/* Adjoint of rbe2d_energy at the current k-set: given gE = dL/dE (device
+/* Adjoint of rbe2d_energy (the derivatives of the energy of Theorem 3.3
+ * with Eq. (3.12) and the estimator of Eqs. (3.25)-(3.26)) at the current
+ * k-set: given gE = dL/dE (device
  * scalar), writes dL/dr (device N x 3), dL/dq (device N) and
  * dL/dgamma (device 2: top, bot); any output may be NULL.  Nothing of size
  * N x P is stored: when the call directly follows rbe2d_energy on the same

@@ -240,12 +240,16 @@ __device__ __forceinline__ TileChunk tile_chunk(int b, int nkc) {
     return TileChunk{(j / nkc) * 8 + (b & 7), j % nkc};
 }
 
+// FP32 phases and transcendentals; each thread sums its (at most 16)
+// particles in FP32, and every sum after that -- across the 64 lanes, the
+// waves of the block and (in the assembly) the tiles -- is in FP64.
 template <int KC>
 __global__ __launch_bounds__(kBlock) void k_sf32(const float4 *__restrict__ p32,
                                                  const float4 *__restrict__ kn, const int *tbase,
                                                  int n_sys, int per_thread, int P_pad, int n_tiles,
-                                                 float *__restrict__ part) {
-    __shared__ float sh[kBlock / 64][64];
+                                                 double *__restrict__ part) {
+    static_assert(4 * KC == 64, "one wave-transposed value per lane");
+    __shared__ double sh[kBlock / 64][64];
     const TileChunk tc = tile_chunk((int)blockIdx.x, P_pad / KC);
     if (tc.tile >= n_tiles) return;
     const int r = find_sys(tbase, n_sys, tc.tile);
@@ -274,11 +278,23 @@ __global__ __launch_bounds__(kBlock) void k_sf32(const float4 *__restrict__ p32,
         }
     }
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    wave_transpose_reduce<4 * KC>(acc, lane);
-    sh[wid][lane] = acc[0];
+    // first butterfly stage of the wave transpose-reduce: the FP32 values are
+    // exchanged, then widened and added in FP64; the other stages run in FP64
+    double v[2 * KC];
+    {
+        const bool upper = (lane & 32) != 0;
+#pragma unroll
+        for (int i = 0; i < 2 * KC; i++) {
+            const float send = upper ? acc[i] : acc[i + 2 * KC];
+            const float keep = upper ? acc[i + 2 * KC] : acc[i];
+            v[i] = (double)keep + (double)__shfl_xor(send, 32, 64);
+        }
+    }
+    TransposeStage<KC, 2 * KC, double>::run(v, lane);
+    sh[wid][lane] = v[0];
     __syncthreads();
     if (threadIdx.x < 4 * KC) {
-        float t = 0.0f;
+        double t = 0.0;
 #pragma unroll
         for (int w = 0; w < kBlock / 64; w++) t += sh[w][threadIdx.x];
         part[((int64_t)tc.tile * P_pad + tc.kc * KC) * 4 + threadIdx.x] = t;
@@ -337,8 +353,7 @@ __global__ __launch_bounds__(kBlock) void k_sf64(const double4 *__restrict__ p64
 // ---------------------------------------------------------------------------
 
 struct AssembleArgs {
-    const void *part;
-    int fp32_part;
+    const double *part;         // structure-factor partials [tile][P_pad][4], FP64 in both precisions
     int P, P_pad;
     const int *tbase;
     const int32_t *kset;
@@ -371,13 +386,7 @@ __global__ __launch_bounds__(64) void k_assemble(AssembleArgs a) {
     double s[4] = {0, 0, 0, 0};
     for (int t = a.tbase[r] + lane; t < a.tbase[r + 1]; t += 64) {
         const int64_t o = ((int64_t)t * a.P_pad + l) * 4;
-        if (a.fp32_part) {
-            const float *p = (const float *)a.part;
-            for (int c = 0; c < 4; c++) s[c] += (double)p[o + c];
-        } else {
-            const double *p = (const double *)a.part;
-            for (int c = 0; c < 4; c++) s[c] += p[o + c];
-        }
+        for (int c = 0; c < 4; c++) s[c] += a.part[o + c];
     }
     for (int c = 0; c < 4; c++) s[c] = wave_sum(s[c]);
     // Y_odd, Y_even and their gamma derivatives; lane handles order o = lane+1, lane+65, ...
@@ -464,7 +473,7 @@ hipError_t launch_kcoef_sf(rbe2d_ctx *h, hipStream_t s, bool with_scalars) {
         if (fp32) {
             const dim3 g((unsigned)tiles8 * (h->P_pad / kKChunk32));
             hipLaunchKernelGGL(k_sf32<kKChunk32>, g, dim3(kBlock), 0, s, h->w.p32, h->w.kn32, h->w.lay.tbase,
-                               h->n_sys, h->per, h->P_pad, h->n_tiles, (float *)h->w.sfpart);
+                               h->n_sys, h->per, h->P_pad, h->n_tiles, (double *)h->w.sfpart);
         } else {
             const dim3 g((unsigned)tiles8 * (h->P_pad / kKChunk64));
             hipLaunchKernelGGL(k_sf64<kKChunk64>, g, dim3(kBlock), 0, s, h->w.p64, h->w.kn64, h->w.lay.tbase,
@@ -473,7 +482,7 @@ hipError_t launch_kcoef_sf(rbe2d_ctx *h, hipStream_t s, bool with_scalars) {
     }
     prof_end(h, 1, s);
     AssembleArgs a;
-    a.part = h->w.sfpart; a.fp32_part = fp32; a.P = h->P; a.P_pad = h->P_pad;
+    a.part = (const double *)h->w.sfpart; a.P = h->P; a.P_pad = h->P_pad;
     a.tbase = h->w.lay.tbase; a.kset = h->w.kset; a.sys = h->w.sys; a.img = h->w.img;
     a.krec = h->w.krec; a.kf32 = h->w.kf32;
     a.n_sys = h->n_sys; a.with_scalars = with_scalars; a.sc = scal_args(h);

@@ -111,7 +111,7 @@ struct Workspace {
     int32_t *kset = nullptr;    // n_sys x P x 3
     float4 *kn32 = nullptr;     // per k: (nx, ny, nz, 0) as floats
     double4 *kn64 = nullptr;    // per k: (nx, ny, nz, 0) as doubles
-    void *sfpart = nullptr;     // structure-factor partials [tile][P_pad][4] (float or double)
+    void *sfpart = nullptr;     // structure-factor partials [tile][P_pad][4] (FP64)
     double *krec = nullptr;     // per-k records, kKRec doubles each (n_sys x P)
     float4 *kf32 = nullptr;     // per k: (kx, ky, kz, kx^2 + ky^2), (cAr, cAi, cBr, cBi),
                                 // (|cA|, arg cA / 2 pi, |cB|, arg cB / 2 pi)

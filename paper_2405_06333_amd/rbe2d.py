@@ -174,6 +174,7 @@ class Slab:
         self.Lz_ext, self.V, self.S = Lz.value, V.value, S.value
         self.P = int(P)
         self.n_max = int(n_max)
+        self._kgen = 0            # bumped by every call that replaces the k-set
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -203,9 +204,11 @@ class Slab:
         else:
             a = np.ascontiguousarray(n, dtype=np.int32).reshape(self.P, 3)
             self._ok(lib().rbe2d_set_kset(self._h, ctypes.c_void_p(a.ctypes.data), 0, _stream()))
+        self._kgen += 1
 
     def sample_kset(self, seed, stream_id=0):
         self._ok(lib().rbe2d_sample_kset(self._h, ctypes.c_uint64(seed), ctypes.c_uint64(stream_id), _stream()))
+        self._kgen += 1
 
     def get_kset(self):
         out = np.zeros((self.P, 3), dtype=np.int32)
@@ -251,6 +254,7 @@ class Slab:
     def md_run(self, pos, vel, q, F, dt, z_lo, z_hi, seed, step0, n_steps, use_graph=False):
         import torch
         N = int(q.shape[0])
+        self._kgen += 1
         self._ok(lib().rbe2d_md_run(
             self._h, N, _dptr(pos, torch.float64, (N, 3), "pos"), _dptr(vel, torch.float64, (N, 3), "vel"),
             _dptr(q, torch.float64, (N,), "q"), _dptr(F, torch.float64, (N, 3), "F"), float(dt),
@@ -276,6 +280,7 @@ class Slab:
     def _md_ex(self, off, pos, vel, q, F, dt, md, seed, step0, n_steps, use_graph):
         import torch
         N = int(off[-1])
+        self._kgen += 1
         self._ok(lib().rbe2d_md_run_ex(
             self._h, ctypes.c_void_p(off.ctypes.data), _dptr(pos, torch.float64, (N, 3), "pos"),
             _dptr(vel, torch.float64, (N, 3), "vel"), _dptr(q, torch.float64, (N,), "q"),
@@ -360,6 +365,7 @@ class BatchedSlab(Slab):
         if st != RBE2D_OK:
             raise RBE2DError(st, lib().rbe2d_last_error(None).decode())
         self.n_sys = n
+        self._kgen = 0
         self.P = int(arr[0].P)
         self.n_max = [int(a.n_max) for a in arr]
         self.Lz_ext, self.V, self.S = [], [], []
@@ -394,6 +400,7 @@ class BatchedSlab(Slab):
         else:
             a = np.ascontiguousarray(n, dtype=np.int32).reshape(self.n_sys, self.P, 3)
             self._ok(lib().rbe2d_set_kset(self._h, ctypes.c_void_p(a.ctypes.data), 0, _stream()))
+        self._kgen += 1
 
     def get_kset(self):
         out = np.zeros((self.n_sys, self.P, 3), dtype=np.int32)
@@ -434,6 +441,7 @@ class BatchedSlab(Slab):
         import torch
         off = self._off(offsets)
         N = int(off[-1])
+        self._kgen += 1
         self._ok(lib().rbe2d_batch_md_run(
             self._h, ctypes.c_void_p(off.ctypes.data), _dptr(pos, torch.float64, (N, 3), "pos"),
             _dptr(vel, torch.float64, (N, 3), "vel"), _dptr(q, torch.float64, (N,), "q"),
@@ -455,21 +463,25 @@ def energy_function():
     class RBE2DEnergy(torch.autograd.Function):
         @staticmethod
         def forward(ctx, pos, q, gamma, slab):
-            # the kernels use the slab's contrasts; check gamma against them once
-            # per tensor version (the check copies gamma to the host)
-            key = (gamma.data_ptr(), gamma._version, gamma.device)
-            if getattr(slab, "_gamma_checked", None) != key:
-                g = gamma.detach().cpu().tolist()
-                if g[0] != slab.params.gamma_top or g[1] != slab.params.gamma_bot:
-                    raise ValueError("gamma must equal the slab's (gamma_top, gamma_bot)")
-                slab._gamma_checked = key
+            # the kernels use the slab's contrasts: gamma must hold exactly
+            # those values, checked on every call against a device copy
+            ref = getattr(slab, "_gamma_dev", None)
+            if ref is None or ref.device != gamma.device:
+                ref = torch.tensor([slab.params.gamma_top, slab.params.gamma_bot], dtype=torch.float64,
+                                   device=gamma.device)
+                slab._gamma_dev = ref
+            if tuple(gamma.shape) != (2,) or not torch.equal(gamma.detach().to(torch.float64), ref):
+                raise ValueError("gamma must equal the slab's (gamma_top, gamma_bot)")
             E = slab.energy(pos.detach(), q.detach())
             ctx.slab = slab
+            ctx.kgen = slab._kgen     # the backward must see the same k-set
             ctx.save_for_backward(pos, q)
             return E[0]
 
         @staticmethod
         def backward(ctx, gE):
+            if ctx.slab._kgen != ctx.kgen:
+                raise RuntimeError("the slab's k-set was replaced between forward and backward")
             pos, q = ctx.saved_tensors
             gE = gE.detach().to(torch.float64).contiguous().reshape(())
             want = ctx.needs_input_grad[:3]

@@ -181,6 +181,17 @@ def test_autograd_function(torch, R):
     G_bad = torch.tensor([w.gamma_top, 0.5], dtype=torch.float64, device="cuda", requires_grad=True)
     with pytest.raises(ValueError):
         Fn.apply(P_, Q_, G_bad, slab)
+    # the same tensor changed in place (same address and, through .data, the
+    # same version counter) is checked again, not served from a cache
+    G_.data[1] = 0.5
+    with pytest.raises(ValueError):
+        Fn.apply(P_, Q_, G_, slab)
+    G_.data[1] = w.gamma_bot
+    # a k-set replaced between forward and backward is refused
+    E = Fn.apply(P_, Q_, G_, slab)
+    slab.set_kset(slab.draw_kset(3))
+    with pytest.raises(RuntimeError):
+        E.backward()
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
