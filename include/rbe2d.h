@@ -350,6 +350,30 @@ rbe2d_status rbe2d_profile_read(rbe2d_handle h, double *ms, int64_t *launches, i
  * the timed work least.  Errors: RBE2D_E_INVAL (NULL handle). */
 rbe2d_status rbe2d_profile_classes(rbe2d_handle h, uint32_t class_mask);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): rbe2d_forces without a
+ * handle.  Every workspace lives in one 32 MiB file-scope device array of
+ * the library (each GPU that runs this call holds its own copy until the
+ * process ends); the call allocates no device or pinned memory, creates no
+ * stream or event and only enqueues kernels on `stream`, so it can be
+ * captured.  Host-side set-up work (the derived constants and tables of *p)
+ * is redone only when *p changes between calls.
+ *   p        parameters as for rbe2d_create; n_max <= 32768 and P <= 1024
+ *            (larger values return RBE2D_E_INVAL with a message)
+ *   kset     device, P x 3 int32, the k-set (not checked; see rbe2d_set_kset)
+ *   N, pos, q, F, energy, flags   as in rbe2d_forces (N <= p->n_max)
+ *   err_word device int32 or NULL: receives the device error word of this
+ *            call (bit 0: a z outside (0, H), as RBE2D_E_RANGE of rbe2d_check)
+ * Results equal rbe2d_forces on a handle with the same parameters and k-set
+ * up to summation order.  Calls on one GPU share its array, which keeps the
+ * last call's contents (each call rewrites everything it reads): calls that
+ * overlap on one GPU (other streams, other threads) race.  Errors:
+ * RBE2D_E_INVAL (arguments, sizes beyond the maximum), RBE2D_E_HIP; the
+ * message is rbe2d_last_error(NULL). */
+rbe2d_status rbe2d_forces_noalloc(const rbe2d_params *p, const int32_t *kset, int64_t N, const double *pos,
+                                  const double *q, double *F, double *energy, uint32_t flags,
+                                  int32_t *err_word, void *stream);
+
 /* Synchronises `stream` and reports asynchronous errors: RBE2D_E_RANGE if a
  * call since the last check saw z outside (0, H), RBE2D_E_HIP for a failed
  * kernel.  Clears the device error word. */

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 
 #include "rbe2d_internal.h"
 
@@ -288,6 +289,55 @@ void free_all(rbe2d_ctx *h) {
     if (h->side) (void)hipStreamDestroy(h->side);
 }
 
+// Every device workspace of a handle, in one fixed order: A(&ptr, count) is
+// called once per buffer (count elements of *ptr's type).  The handle's
+// capacities (n_sys, n_cap, cap_particles, cap_sorted, total_cells, P,
+// fpart_blocks) must be set.  own_kset: the handle holds its k-set (else the
+// caller's device array is used in place).
+template <typename Alloc>
+void plan_workspace(rbe2d_ctx *h, size_t cdf_total, bool own_kset, Alloc &&A) {
+    const int n = h->n_sys;
+    const int cells = h->total_cells;
+    const int64_t cap_blocks = h->cap_particles / kBlock;
+    Workspace &w = h->w;
+    A(&w.sys, n);
+    A(&w.img, n);
+    A(&w.fam, (size_t)n * kMaxFamilies);
+    A(&w.cdf, cdf_total);
+    A(&w.lay.off, n + 1); A(&w.lay.pbase, n + 1); A(&w.lay.bbase, n + 1);
+    A(&w.lay.tbase, n + 1); A(&w.lay.sbase, n + 1);
+    A(&w.p32, 2 * h->cap_particles);
+    A(&w.p64, h->cap_particles);
+    A(&w.bpart, 4 * cap_blocks);
+    A(&w.scal, 8 * (size_t)n);
+    if (own_kset) A(&w.kset, 3 * (size_t)n * h->P);
+    A(&w.kn32, (size_t)n * h->P_pad);
+    A(&w.kn64, (size_t)n * h->P_pad);
+    double *sfp = nullptr;
+    A(&sfp, (size_t)cap_blocks * h->P_pad * 4);
+    w.sfpart = sfp;
+    A(&w.krec, (size_t)n * h->P * kKRec);
+    A(&w.kf32, 3 * (size_t)n * h->P);
+    A(&w.fpart, (size_t)h->fpart_blocks * kBlock * 4);
+    const int64_t nc = std::max<int64_t>(h->n_cap, 1);
+    A(&w.cell, nc); A(&w.slot, nc); A(&w.tmp, nc);
+    A(&w.count, cells); A(&w.start, cells + 1); A(&w.scanbuf, cells / 1024 + 2);
+    // source records get one wave of padding: the pair kernel reads the first
+    // record of an empty run, which may start at the end of the array
+    A(&w.sorted, h->cap_sorted + kWave); A(&w.sidx, h->cap_sorted); A(&w.scell, h->cap_sorted);
+    if (h->precision == RBE2D_PREC_FP32_PHASE) A(&w.src16, h->cap_sorted + kWave);
+    A(&w.freal, nc); A(&w.dgreal, nc);
+    A(&w.rpart, 3 * (h->cap_sorted / kWave));
+    // the split is only used when there are too few targets to fill the chip
+    h->split_cap = std::min<int64_t>(nc, 1 << 18);
+    A(&w.freal_s, kMaxRealSplit * h->split_cap);
+    A(&w.dgreal_s, kMaxRealSplit * h->split_cap);
+    A(&w.rpart_s, kMaxRealSplit * 3 * (h->cap_sorted / kWave));
+    A(&w.spart, 2 * (h->cap_sorted / kWave));
+    A(&w.err, 4);
+    A(&w.step, 1);
+}
+
 // A handle over n systems: every system is set up and the workspaces are
 // sized for the sum of their n_max.
 rbe2d_status create_handle(int n, const rbe2d_params *ps, bool batch, rbe2d_handle *out) {
@@ -339,48 +389,13 @@ rbe2d_status create_handle(int n, const rbe2d_params *ps, bool batch, rbe2d_hand
     h->cap_particles = std::max<int64_t>(cap_p, kTileMax);
     h->cap_sorted = std::max<int64_t>(cap_s, kWave);
     h->total_cells = cells;
+    h->fpart_blocks = std::min<int64_t>(64 * (h->cap_particles / kBlock), 4096);
     (void)hipGetDevice(&h->device);
 
-    const int64_t cap_blocks = h->cap_particles / kBlock;
-    Workspace &w = h->w;
     hipError_t e = hipSuccess;
     auto A = [&](auto **ptr, size_t cnt) { if (e == hipSuccess) e = dalloc(h, ptr, cnt); };
-    A(&w.sys, n);
-    A(&w.img, n);
-    A(&w.fam, (size_t)n * kMaxFamilies);
-    A(&w.cdf, cdf_total);
-    A(&w.lay.off, n + 1); A(&w.lay.pbase, n + 1); A(&w.lay.bbase, n + 1);
-    A(&w.lay.tbase, n + 1); A(&w.lay.sbase, n + 1);
-    A(&w.p32, 2 * h->cap_particles);
-    A(&w.p64, h->cap_particles);
-    A(&w.bpart, 4 * cap_blocks);
-    A(&w.scal, 8 * (size_t)n);
-    A(&w.kset, 3 * (size_t)n * h->P);
-    A(&w.kn32, (size_t)n * h->P_pad);
-    A(&w.kn64, (size_t)n * h->P_pad);
-    double *sfp = nullptr;
-    A(&sfp, (size_t)cap_blocks * h->P_pad * 4);
-    w.sfpart = sfp;
-    A(&w.krec, (size_t)n * h->P * kKRec);
-    A(&w.kf32, 3 * (size_t)n * h->P);
-    A(&w.fpart, (size_t)std::min<int64_t>(64 * cap_blocks * kBlock, 4096 * kBlock) * 4);
-    const int64_t nc = std::max<int64_t>(n_cap, 1);
-    A(&w.cell, nc); A(&w.slot, nc); A(&w.tmp, nc);
-    A(&w.count, cells); A(&w.start, cells + 1); A(&w.scanbuf, cells / 1024 + 2);
-    // source records get one wave of padding: the pair kernel reads the first
-    // record of an empty run, which may start at the end of the array
-    A(&w.sorted, h->cap_sorted + kWave); A(&w.sidx, h->cap_sorted); A(&w.scell, h->cap_sorted);
-    if (h->precision == RBE2D_PREC_FP32_PHASE) A(&w.src16, h->cap_sorted + kWave);
-    A(&w.freal, nc); A(&w.dgreal, nc);
-    A(&w.rpart, 3 * (h->cap_sorted / kWave));
-    // the split is only used when there are too few targets to fill the chip
-    h->split_cap = std::min<int64_t>(nc, 1 << 18);
-    A(&w.freal_s, kMaxRealSplit * h->split_cap);
-    A(&w.dgreal_s, kMaxRealSplit * h->split_cap);
-    A(&w.rpart_s, kMaxRealSplit * 3 * (h->cap_sorted / kWave));
-    A(&w.spart, 2 * (h->cap_sorted / kWave));
-    A(&w.err, 4);
-    A(&w.step, 1);
+    plan_workspace(h, cdf_total, true, A);
+    Workspace &w = h->w;
     std::vector<SysDesc> descs(n);
     std::vector<ImgTable> imgs(n);
     std::vector<Family> fams((size_t)n * kMaxFamilies);
@@ -416,11 +431,10 @@ rbe2d_status create_handle(int n, const rbe2d_params *ps, bool batch, rbe2d_hand
     return RBE2D_OK;
 }
 
-// Particle layout of all systems for the given counts; uploaded (through
-// pinned staging, ordered on the stream) only when it changes.
-rbe2d_status set_layout(rbe2d_ctx *h, const int64_t *counts, hipStream_t s) {
+// Particle layout of all systems for the given counts into lay (5 (n_sys +
+// 1) ints: off, pbase, bbase, tbase, sbase) and the handle's launch sizes.
+rbe2d_status compute_layout(rbe2d_ctx *h, const int64_t *counts, int *lay) {
     const int n = h->n_sys;
-    h->calls++;
     int64_t total = 0;
     for (int r = 0; r < n; r++) {
         if (counts[r] < 0 || counts[r] > h->sys[r].p.n_max)
@@ -447,8 +461,8 @@ rbe2d_status set_layout(rbe2d_ctx *h, const int64_t *counts, hipStream_t s) {
         }
     }
     const int tile = kBlock * per;
-    std::vector<int> lay(5 * (n + 1), 0);
-    int *off = lay.data(), *pb = off + (n + 1), *bb = pb + (n + 1), *tb = bb + (n + 1), *sb = tb + (n + 1);
+    std::fill(lay, lay + 5 * (n + 1), 0);
+    int *off = lay, *pb = off + (n + 1), *bb = pb + (n + 1), *tb = bb + (n + 1), *sb = tb + (n + 1);
     for (int r = 0; r < n; r++) {
         off[r + 1] = off[r] + (int)counts[r];
         pb[r + 1] = pb[r] + (int)((counts[r] + tile - 1) / tile * tile);
@@ -460,6 +474,17 @@ rbe2d_status set_layout(rbe2d_ctx *h, const int64_t *counts, hipStream_t s) {
     h->n_blocks = bb[n];
     h->n_tiles = tb[n];
     h->n_swaves = sb[n] / kWave;
+    return RBE2D_OK;
+}
+
+// Particle layout of all systems for the given counts; uploaded (through
+// pinned staging, ordered on the stream) only when it changes.
+rbe2d_status set_layout(rbe2d_ctx *h, const int64_t *counts, hipStream_t s) {
+    const int n = h->n_sys;
+    h->calls++;
+    std::vector<int> lay(5 * (n + 1), 0);
+    rbe2d_status st = compute_layout(h, counts, lay.data());
+    if (st) return st;
     if (h->lay_valid && lay == h->lay_host) return RBE2D_OK;
     if (h->lay_ev_pending) RBE2D_TRY(h, hipEventSynchronize(h->lay_ev), "layout wait");
     std::memcpy(h->lay_stage, lay.data(), lay.size() * sizeof(int));
@@ -505,7 +530,7 @@ rbe2d_status run_common(rbe2d_ctx *h, const double *pos, const double *q, uint32
     const bool kside = (flags & (RBE2D_KSPACE | RBE2D_IBC)) != 0;
     const bool real = (flags & RBE2D_REAL) != 0;
     hipStream_t ks = s;
-    if (kside && real && h->n_total > 0) {
+    if (kside && real && h->n_total > 0 && !h->one_stream) {
         ks = h->side;
         RBE2D_TRY(h, hipEventRecord(h->fork_ev, s), "fork event");
         RBE2D_TRY(h, hipStreamWaitEvent(ks, h->fork_ev, 0), "fork wait");
@@ -533,7 +558,7 @@ rbe2d_status run_common(rbe2d_ctx *h, const double *pos, const double *q, uint32
 rbe2d_status compute_forces(rbe2d_ctx *h, const double *pos, const double *q, double *F, uint32_t parts,
                             bool accumulate, double *vel, double dt, hipStream_t s, const MdExtra *mxs) {
     const bool kside = (parts & (RBE2D_KSPACE | RBE2D_IBC)) != 0;
-    if (kside && (parts & RBE2D_REAL) && h->n_total > 0) {
+    if (kside && (parts & RBE2D_REAL) && h->n_total > 0 && !h->one_stream) {
         hipStream_t ks = h->side;
         RBE2D_TRY(h, hipEventRecord(h->fork_ev, s), "fork event");
         RBE2D_TRY(h, hipStreamWaitEvent(ks, h->fork_ev, 0), "fork wait");
@@ -776,6 +801,165 @@ rbe2d_status md_run(rbe2d_ctx *h, double *pos, double *vel, const double *q, dou
     }
     RBE2D_TRY(h, launch_set_step(h, step0, s), "md step counter");
     for (int32_t it = 0; it < n_steps; it++) RBE2D_TRY(h, hipGraphLaunch(h->md_exec, s), "graph launch");
+    return RBE2D_OK;
+}
+
+// ---------------------------------------------------------------------------
+// The evaluation without a handle (rbe2d_forces_noalloc): every workspace is
+// carved from one file-scope device array, so a call allocates no device or
+// pinned memory and creates no stream or event.
+// ---------------------------------------------------------------------------
+
+constexpr int64_t kStaticMaxN = 32768;     // largest n_max of the static path
+constexpr int kStaticMaxP = 1024;          // largest P of the static path
+constexpr int kStaticFparts = 1024;        // particle blocks' worth of force-pass partials
+constexpr size_t kScratchBytes = (size_t)32 << 20;
+constexpr int kMaxDevices = 64;
+
+}  // namespace
+
+// The static path's workspaces (each GPU holds its own copy until the
+// process ends).  Host code never passes this name to a kernel: it is a
+// host-side stand-in, and the device address comes from hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+struct StaticState {
+    unsigned char *base = nullptr;   // device address of `scratch` on this device
+    rbe2d_ctx h;
+    rbe2d_params last{};
+    bool have = false;
+};
+StaticState g_static[kMaxDevices];
+std::mutex g_static_mu;
+
+// Tables of one system, passed by value as kernel arguments (each launch's
+// arguments stay below 4 KB)
+struct PutDesc {
+    SysDesc d;
+    int lay[10];
+};
+constexpr int kFamPerPut = 32;
+struct PutFam {
+    Family f[kFamPerPut];
+    int first, count;
+};
+
+__global__ void k_put_desc(PutDesc a, SysDesc *sys, int *off, int *pbase, int *bbase, int *tbase, int *sbase,
+                           int *err) {
+    if (threadIdx.x != 0) return;
+    *sys = a.d;
+    int *dst[5] = {off, pbase, bbase, tbase, sbase};
+    for (int k = 0; k < 5; k++) {
+        dst[k][0] = a.lay[2 * k];
+        dst[k][1] = a.lay[2 * k + 1];
+    }
+    err[0] = 0;
+}
+__global__ void k_put_img(ImgTable a, ImgTable *img) {
+    if (threadIdx.x == 0) *img = a;
+}
+__global__ void k_put_fam(PutFam a, Family *fam) {
+    if ((int)threadIdx.x < a.count) fam[a.first + threadIdx.x] = a.f[threadIdx.x];
+}
+__global__ void k_copy_err(const int *src, int32_t *dst) {
+    if (threadIdx.x == 0) *dst = *src;
+}
+
+rbe2d_status forces_noalloc(const rbe2d_params *p, const int32_t *kset, int64_t N, const double *pos,
+                            const double *q, double *F, double *energy, uint32_t flags, int32_t *err_word,
+                            hipStream_t s) {
+    rbe2d_status st = validate(p, nullptr);
+    if (st) return st;
+    if (p->n_max > kStaticMaxN || p->P > kStaticMaxP)
+        return fail(nullptr, RBE2D_E_INVAL,
+                    "rbe2d_forces_noalloc handles n_max <= %lld and P <= %d (got n_max = %lld, P = %d)",
+                    (long long)kStaticMaxN, kStaticMaxP, (long long)p->n_max, p->P);
+    if (N < 0 || N > p->n_max)
+        return fail(nullptr, RBE2D_E_INVAL, "N = %lld outside [0, n_max = %lld]", (long long)N,
+                    (long long)p->n_max);
+    if (flags & ~(uint32_t)(RBE2D_ALL | RBE2D_ACCUMULATE)) return fail(nullptr, RBE2D_E_INVAL, "unknown flags");
+    if (N > 0 && (!pos || !q || !F)) return fail(nullptr, RBE2D_E_INVAL, "pos, q or F is NULL");
+    if (!kset && (flags & RBE2D_KSPACE)) return fail(nullptr, RBE2D_E_INVAL, "kset is NULL");
+    int dev = 0;
+    const hipError_t ge = hipGetDevice(&dev);
+    if (ge != hipSuccess) return hipfail(nullptr, ge, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(nullptr, RBE2D_E_INVAL, "device index %d >= %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    StaticState &S = g_static[dev];
+    if (!S.base) {
+        // once per device, with that device current: the array's address on it
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hipfail(nullptr, e, "hipGetSymbolAddress(scratch)");
+        S.base = (unsigned char *)ptr;
+    }
+    rbe2d_ctx *h = &S.h;
+    if (!S.have || std::memcmp(&S.last, p, sizeof *p) != 0) {
+        // host set-up of the system (only when the parameters change)
+        S.have = false;
+        h->sys.resize(1);
+        st = setup_system(p, h->sys[0]);
+        if (st) return st;
+        const rbe2d_params &pp = h->sys[0].p;
+        SysDesc &d = h->sys[0].d;
+        d.cbase = 0;
+        h->n_sys = 1;
+        h->batch = false;
+        h->precision = pp.precision;
+        h->P = pp.P;
+        h->P_pad = (h->P + kPPad - 1) / kPPad * kPPad;
+        h->n_cap = pp.n_max;
+        h->cap_particles = std::max<int64_t>((pp.n_max + kTileMax - 1) / kTileMax * kTileMax, kTileMax);
+        h->cap_sorted = std::max<int64_t>((pp.n_max + kWave - 1) / kWave * kWave, kWave);
+        h->total_cells = d.ncx * d.ncy * d.ncz;
+        h->iso = d.iso != 0;
+        h->fpart_blocks = std::min<int64_t>(64 * (h->cap_particles / kBlock), kStaticFparts);
+        h->one_stream = true;
+        h->side = nullptr;
+        // carve the workspaces from the array (256-byte aligned)
+        size_t used = 0;
+        auto carve = [&](auto **ptr, size_t cnt) {
+            using T = std::remove_reference_t<decltype(**ptr)>;
+            used = (used + 255) & ~(size_t)255;
+            *ptr = (T *)(S.base + used);
+            used += std::max<size_t>(cnt, 1) * sizeof(T);
+        };
+        plan_workspace(h, 1, false, carve);
+        if (used > kScratchBytes)
+            return fail(nullptr, RBE2D_E_INVAL, "rbe2d_forces_noalloc: %zu bytes of workspace exceed the %zu-byte array",
+                        used, kScratchBytes);
+        S.last = *p;
+        S.have = true;
+    }
+    h->w.kset = const_cast<int32_t *>(kset);
+    h->kset_valid = true;
+    int64_t cnt = N;
+    PutDesc pd;
+    st = compute_layout(h, &cnt, pd.lay);
+    if (st) return st;
+    // tables and layout: stream-ordered kernel writes (the array keeps the
+    // last call's contents; every call rewrites what it reads)
+    const SysHost &sh = h->sys[0];
+    pd.d = sh.d;
+    hipLaunchKernelGGL(k_put_desc, dim3(1), dim3(64), 0, s, pd, h->w.sys, h->w.lay.off, h->w.lay.pbase,
+                       h->w.lay.bbase, h->w.lay.tbase, h->w.lay.sbase, h->w.err);
+    hipLaunchKernelGGL(k_put_img, dim3(1), dim3(64), 0, s, sh.img, h->w.img);
+    for (int f0 = 0; f0 < (int)sh.fam.size(); f0 += kFamPerPut) {
+        PutFam pf;
+        pf.first = f0;
+        pf.count = std::min<int>(kFamPerPut, (int)sh.fam.size() - f0);
+        for (int i = 0; i < pf.count; i++) pf.f[i] = sh.fam[f0 + i];
+        hipLaunchKernelGGL(k_put_fam, dim3(1), dim3(64), 0, s, pf, h->w.fam);
+    }
+    RBE2D_TRY(nullptr, hipGetLastError(), "table upload");
+    const uint32_t parts = flags & RBE2D_ALL;
+    st = compute_forces(h, pos, q, F, parts, (flags & RBE2D_ACCUMULATE) != 0, nullptr, 0.0, s, nullptr);
+    if (st) return fail(nullptr, st, "%s", h->err.c_str());
+    if (energy) RBE2D_TRY(nullptr, launch_energy(h, energy, parts, nullptr, nullptr, s), "energy launch");
+    if (err_word) hipLaunchKernelGGL(k_copy_err, dim3(1), dim3(64), 0, s, h->w.err, err_word);
+    RBE2D_TRY(nullptr, hipGetLastError(), "launch");
     return RBE2D_OK;
 }
 
@@ -1138,7 +1322,7 @@ rbe2d_status rbe2d_autotune(rbe2d_handle h, const int64_t *offsets, const double
     }
     tbest = 1e30f;
     for (int ks = 1; st == RBE2D_OK && ks <= 64 && total > 0; ks <<= 1) {
-        if ((int64_t)ks * h->n_blocks > std::min<int64_t>(64 * (h->cap_particles / kBlock), 4096)) break;
+        if ((int64_t)ks * h->n_blocks > h->fpart_blocks) break;
         h->force_ksplit = ks;
         float t = 0.0f;
         // the real-space output array serves as scratch for the forces
@@ -1215,6 +1399,12 @@ rbe2d_status rbe2d_profile_read(rbe2d_handle h, double *ms, int64_t *launches, i
         p.used[sl] = 0;
     }
     return RBE2D_OK;
+}
+
+rbe2d_status rbe2d_forces_noalloc(const rbe2d_params *p, const int32_t *kset, int64_t N, const double *pos,
+                                  const double *q, double *F, double *energy, uint32_t flags, int32_t *err_word,
+                                  void *stream) {
+    return forces_noalloc(p, kset, N, pos, q, F, energy, flags, err_word, (hipStream_t)stream);
 }
 
 rbe2d_status rbe2d_check(rbe2d_handle h, void *stream) {

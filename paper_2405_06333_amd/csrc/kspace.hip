@@ -724,9 +724,8 @@ hipError_t launch_kforce(rbe2d_ctx *h, const double *pos, const double *q, doubl
     if (a.do_kspace) {
         split = h->force_ksplit ? h->force_ksplit
                                 : (h->tuned_now && h->tune.ksplit ? h->tune.ksplit : choose_ksplit(h->n_blocks, h->P));
-        // the partial buffer holds 4096 blocks' worth (or 64 splits of every block)
-        while (split > 1 && (int64_t)split * h->n_blocks > std::min<int64_t>(64 * (h->cap_particles / kBlock), 4096))
-            split >>= 1;
+        // the partial buffer holds fpart_blocks blocks' worth
+        while (split > 1 && (int64_t)split * h->n_blocks > h->fpart_blocks) split >>= 1;
     }
     a.k_per_split = (h->P + split - 1) / split;
     a.split = split > 1;

@@ -170,6 +170,8 @@ struct rbe2d_ctx {
     int total_cells = 0;
     bool iso = false;                // every system has the isotropic fixed-point frame
     int64_t split_cap = 0;           // targets per split of the partial real-space outputs
+    int64_t fpart_blocks = 0;        // particle blocks' worth of force-pass partials (k-range splits)
+    bool one_stream = false;         // run the k-space chain on the caller's stream too (no side stream)
     bool kset_valid = false;
     // current layout (host mirror); a layout is uploaded when it changes
     std::vector<int> lay_host;       // 5 x (n_sys + 1): off, pbase, bbase, tbase, sbase

@@ -25,7 +25,8 @@ EXPORTS = ("rbe2d_create", "rbe2d_destroy", "rbe2d_query", "rbe2d_draw_kset", "r
            "rbe2d_energy_backward", "rbe2d_md_run", "rbe2d_profile_enable", "rbe2d_profile_read",
            "rbe2d_check", "rbe2d_last_error", "rbe2d_batch_create", "rbe2d_query_system",
            "rbe2d_batch_forces", "rbe2d_batch_md_run", "rbe2d_autotune", "rbe2d_short_forces",
-           "rbe2d_md_run_ex", "rbe2d_suggest_params", "rbe2d_force_variance", "rbe2d_profile_classes")
+           "rbe2d_md_run_ex", "rbe2d_suggest_params", "rbe2d_force_variance", "rbe2d_profile_classes",
+           "rbe2d_forces_noalloc")
 PROF_SLOTS = ("prep", "sf_pass", "assemble", "cell_build", "real_pairs", "force_scatter", "energy",
               "integrator", "ksample", "short_range", "add_real")
 
@@ -97,6 +98,8 @@ def lib():
         L.rbe2d_force_variance.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
         L.rbe2d_profile_enable.argtypes = [_vp, ctypes.c_int32]
         L.rbe2d_profile_read.argtypes = [_vp, _vp, _vp, ctypes.c_int32]
+        L.rbe2d_forces_noalloc.argtypes = [ctypes.POINTER(Params), _vp, ctypes.c_int64, _vp, _vp, _vp, _vp,
+                                           ctypes.c_uint32, _vp, _vp]
         L.rbe2d_check.argtypes = [_vp, _vp]
         L.rbe2d_last_error.argtypes = [_vp]
         L.rbe2d_last_error.restype = ctypes.c_char_p
@@ -136,6 +139,27 @@ def suggest_params(N, Lx, Ly, H, gamma_top, gamma_bot, tol, P=100, precision="fp
         raise RBE2DError(st, lib().rbe2d_last_error(None).decode())
     return dict(Lx=p.Lx, Ly=p.Ly, H=p.H, gamma_top=p.gamma_top, gamma_bot=p.gamma_bot, alpha=p.alpha, r_c=p.r_c,
                 P=p.P, M=p.M, Lz_ext=p.Lz_ext, eps_lz=p.eps_lz)
+
+
+def forces_noalloc(params: Params, kset, pos, q, flags=ALL, want_energy=False, out=None, energy_out=None,
+                   err_out=None):
+    """rbe2d_forces_noalloc: forces (and energies) without a handle; every
+    workspace comes from the library's static device array.  kset: device
+    int32 (P, 3).  err_out: optional device int32 scalar that receives the
+    call's device error word."""
+    import torch
+    N = int(q.shape[0])
+    F = torch.empty((N, 3), dtype=torch.float64, device=pos.device) if out is None else out
+    E = None
+    if want_energy:
+        E = torch.empty(5, dtype=torch.float64, device=pos.device) if energy_out is None else energy_out
+    st = lib().rbe2d_forces_noalloc(ctypes.byref(params), _dptr(kset, torch.int32, (params.P, 3), "kset"), N,
+                                    _dptr(pos, torch.float64, (N, 3), "pos"), _dptr(q, torch.float64, (N,), "q"),
+                                    _dptr(F, torch.float64, (N, 3), "F"), _dptr(E, torch.float64, (5,), "energy"),
+                                    flags, _dptr(err_out, torch.int32, (), "err"), _stream())
+    if st != RBE2D_OK:
+        raise RBE2DError(st, lib().rbe2d_last_error(None).decode())
+    return (F, E) if want_energy else F
 
 
 def _stream():
