@@ -38,6 +38,16 @@ SLOTS_FORCE = 16   # k.r (3), khat.r (1), angle offsets of the polar amplitudes 
                    # |cA| sin (1), X +- |cB| sin (2), 3 force FMAs
 SLOTS_REAL = 22    # per pair within r_c: d2 (5), cutoff (1), rsqrt (2), exp (2+1), erfc fit
                    # (rcp 2 + 7 FMA), force factor (2); pairs outside r_c not counted
+# the FP64 path (FP64 FMA issues at the FP32 rate on gfx950): software sincos
+# on revolutions (quarter-turn reduction 4, 7 + 8 polynomial FMAs, 4 products
+# and offsets: 23 per sincos)
+SLOTS_SF64 = 55      # k.r and khat.r (5), two sincos (46), 4 accumulating FMAs
+SLOTS_FORCE64 = 52   # phases (3), two half-turn-reduced sines (2 x 19) with their angle offsets
+                     # and amplitudes (2 x 3), X +- Y (2), 3 force FMAs
+SLOTS_REAL64 = 85    # per pair within r_c: d2 and cutoff (6), sqrt (8), exp (25), two FP64
+                     # divisions (2 x 12), erfcx fit (16), products (6)
+SLOTS = {"fp32": {"sf_pass": SLOTS_SF, "force_scatter": SLOTS_FORCE, "real_pairs": SLOTS_REAL},
+         "fp64": {"sf_pass": SLOTS_SF64, "force_scatter": SLOTS_FORCE64, "real_pairs": SLOTS_REAL64}}
 
 
 # HBM traffic of the dominant kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE
@@ -91,6 +101,8 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true", help="use the built-in launch heuristics")
     ap.add_argument("--parts-only", type=int, default=0,
                     help="only time this many force calls of each half alone (for counter runs)")
+    ap.add_argument("--batch-only", type=int, default=0,
+                    help="only run this many steps of the 64-replica batch (for kernel traces and counters)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (HBM counter calibration)")
     return ap.parse_args()
@@ -172,6 +184,33 @@ def run_md(R, torch, w, precision, steps, warmup, profile, use_graph=False, auto
     return (t1 - t0), prof, finite, tuned
 
 
+def roofline_of(breakdown, precision, NP, pairs, dom=None, t_dom=None):
+    """Per-kernel algorithmic fractions of the VALU issue peak from a breakdown
+    {class: (ms, launches)}, and the roofline block of the dominant
+    caller-stream kernel (its timed duration when given, else the breakdown's)."""
+    slots = SLOTS[precision]
+    units = {"sf_pass": NP, "force_scatter": NP, "real_pairs": pairs}
+    fr = {}
+    for k in ("sf_pass", "force_scatter", "real_pairs"):
+        t, n = breakdown.get(k, (0.0, 0))
+        if n:
+            fr[k] = {"ms_per_launch": round(t / n, 4),
+                     "valu_frac": round(slots[k] * units[k] / (t / n * 1e-3) / VALU_LANE_SLOTS, 4)}
+    dom = dom or dominant_kernel(breakdown)
+    if t_dom is None:
+        t, n = breakdown[dom]
+        t_dom = t / max(n, 1) * 1e-3
+    roof = None
+    if dom in slots:
+        ach = slots[dom] * units[dom] / t_dom / 1e12
+        peak = VALU_LANE_SLOTS / 1e12
+        roof = {"bound": "alu", "kernel": dom, "achieved": round(ach, 3), "peak": round(peak, 3),
+                "unit": "Tlane-slot/s", "frac": round(ach / peak, 4), "traffic": None,
+                "slots_per_unit": slots[dom],
+                "concurrent_with": list(SIDE_STREAM) if dom == "real_pairs" else []}
+    return roof, fr
+
+
 def dominant_kernel(prof):
     """The k-space chain (with its force scatter) runs on a second stream,
     overlapped with the cell list and the pair kernel: its event durations
@@ -216,7 +255,7 @@ def timed(torch, fn, steps):
     return time.perf_counter() - t0
 
 
-def run_batch(R, torch, steps, autotune=True):
+def run_batch(R, torch, steps, autotune=True, plain=True):
     """64 replicas of uneven N and different contrasts: batched MD steps
     (graph replays) in FP32 phases and in FP64, against the plain path --
     one single-system FP64 handle per replica, stepped one after another."""
@@ -227,8 +266,10 @@ def run_batch(R, torch, steps, autotune=True):
     counts = [w.N for w in ws]
     ntot = int(sum(counts))
     margin = min(w.margin for w in ws)
+    pairs = sum(expected_real_pairs(w) for w in ws)
     out = {"workload": f"replicas: {len(ws)} slabs, N in [{min(counts)}, {max(counts)}], total {ntot}, "
-                       f"2:1 ions, P={ws[0].P}, M={ws[0].M}", "particles": ntot}
+                       f"2:1 ions, P={ws[0].P}, M={ws[0].M}", "particles": ntot,
+           "expected_real_pairs": pairs}
     for prec in ("fp32", "fp64"):
         b = R.BatchedSlab([dict(w.slab_kwargs(), precision=prec, n_max=w.N) for w in ws])
         off = b.offsets(counts)
@@ -244,7 +285,25 @@ def run_batch(R, torch, steps, autotune=True):
                                           use_graph=True), 1)
         b.check()
         out[f"batch_{prec}_graph"] = ntot * steps / t
+        out[f"batch_{prec}_ms_per_step"] = t * 1e3 / steps
+        # per-kernel breakdown of the same step from eager steps with every
+        # kernel class bracketed by events (a captured graph holds none)
+        nb = 3
+        b.profile_enable(nb + 4)
+        b.profile_read()
+        b.md_run(off, P_, V_, Q_, F_, ws[0].dt, margin, ws[0].seed, 3 + steps, nb, use_graph=False)
+        bd = b.profile_read()
+        b.profile_enable(0)
+        b.check()
+        roof, fr = roofline_of(bd, prec, ntot * ws[0].P, pairs)
+        out[f"roofline_{prec}"] = roof
+        out[f"kernels_{prec}"] = {k: {"ms_per_launch": (t_ / n_ if n_ else None), "launches": n_}
+                                  for k, (t_, n_) in bd.items() if n_}
+        for k, v in fr.items():
+            out[f"kernels_{prec}"][k]["valu_frac"] = v["valu_frac"]
         del b
+    if not plain:
+        return out
     slabs = [R.Slab(**w.slab_kwargs(), precision="fp64", n_max=w.N) for w in ws]
     offs = np.concatenate([[0], np.cumsum(counts)])
     P_ = torch.as_tensor(pos, device="cuda")
@@ -407,6 +466,9 @@ def main():
         return 0
     from paper_2405_06333_amd import inputs, rbe2d as R
     R.lib()
+    if a.batch_only:
+        print(json.dumps(run_batch(R, torch, a.batch_only, autotune=not a.no_autotune, plain=False)), flush=True)
+        return 0
     w = inputs.LARGE_MD
     secs, prof, finite, tuned = run_md(R, torch, w, a.precision, a.steps, a.warmup, profile=True,
                                        autotune=not a.no_autotune)
@@ -452,8 +514,16 @@ def main():
 
     fp64 = None
     if a.fp64_steps > 0 and a.precision != "fp64":
-        s64, _, _, _ = run_md(R, torch, w, "fp64", a.fp64_steps, 1, profile=False, autotune=not a.no_autotune)
-        fp64 = {"value": w.N * a.fp64_steps / s64, "unit": "particle-steps/s", "steps": a.fp64_steps}
+        s64, p64, _, _ = run_md(R, torch, w, "fp64", a.fp64_steps, 1, profile=True, autotune=not a.no_autotune)
+        fp64 = {"value": w.N * a.fp64_steps / s64, "unit": "particle-steps/s", "steps": a.fp64_steps,
+                "ms_per_step": s64 * 1e3 / a.fp64_steps}
+        t64 = p64["timed"][0] / max(p64["timed"][1], 1) * 1e-3
+        fp64["roofline"], fp64["kernels"] = roofline_of(p64["breakdown"], "fp64", NP, pairs_real,
+                                                         p64["dominant"], t64)
+        if a.side_steps > 0:
+            alone64 = run_parts(R, torch, w, "fp64", max(2, a.side_steps // 2))
+            _, fp64["kernels_alone"] = roofline_of({**alone64["kspace"], "real_pairs": alone64["real"]["real_pairs"]},
+                                                   "fp64", NP, pairs_real, dom="real_pairs")
 
     graph = batch = grad = langevin = parts = None
     if a.side_steps > 0:

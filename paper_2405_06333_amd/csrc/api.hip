@@ -714,6 +714,9 @@ rbe2d_status vv_run(rbe2d_ctx *h, double *pos, double *vel, const double *q, dou
             RBE2D_TRY(h, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "capture stream");
             const int prof_n = h->prof.n;
             h->prof.n = 0;   // no profiling events inside the graph
+            // a captured unit starts from counted cells and ends by counting
+            // them for the next one; a failed capture leaves the state as it was
+            const bool counted0 = h->cells_counted;
             hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
             rbe2d_status st = RBE2D_OK;
             if (e == hipSuccess) {
@@ -733,6 +736,7 @@ rbe2d_status vv_run(rbe2d_ctx *h, double *pos, double *vel, const double *q, dou
             }
             h->prof.n = prof_n;
             (void)hipStreamDestroy(cs);
+            h->cells_counted = counted0;
             if (st) { free_graph(h); return st; }
             h->md_key = key;
         }
@@ -953,6 +957,10 @@ rbe2d_status forces_noalloc(const rbe2d_params *p, const int32_t *kset, int64_t 
         for (int i = 0; i < pf.count; i++) pf.f[i] = sh.fam[f0 + i];
         hipLaunchKernelGGL(k_put_fam, dim3(1), dim3(64), 0, s, pf, h->w.fam);
     }
+    // the cell counts start at zero in every build (the array may hold
+    // another call's values)
+    RBE2D_TRY(nullptr, launch_fill(h->w.count, (int64_t)h->total_cells * 4, s), "count clear");
+    h->cells_counted = false;
     RBE2D_TRY(nullptr, hipGetLastError(), "table upload");
     const uint32_t parts = flags & RBE2D_ALL;
     st = compute_forces(h, pos, q, F, parts, (flags & RBE2D_ACCUMULATE) != 0, nullptr, 0.0, s, nullptr);

@@ -38,6 +38,9 @@ struct PrepArgs {
     const double *F;
     const double4 *freal;       // MD == 2: the pair kernel's part of the force
     double dt, zlo, zhi_from_top;
+    // MD > 0 with count set: the cell and in-cell slot of each moved
+    // particle for the next cell-list build (the counts start at zero)
+    int *cell, *slot, *count;
 };
 
 // MD: 0 none; 1 opening half kick with F and drift; 2 closing half kick and
@@ -76,6 +79,12 @@ __global__ __launch_bounds__(kBlock) void k_prep(PrepArgs a) {
                 a.pos_md[3 * g + c] = rr[c];
             }
             x = rr[0]; y = rr[1]; z = rr[2];
+            if (a.count) {
+                double xw, yw;
+                const int c = d.cbase + cell_of(x, y, z, d, &xw, &yw);
+                a.cell[g] = c;
+                a.slot[g] = atomicAdd(&a.count[c], 1);
+            }
         } else {
             x = a.pos[3 * g]; y = a.pos[3 * g + 1]; z = a.pos[3 * g + 2];
         }
@@ -197,10 +206,14 @@ hipError_t launch_prep_md(rbe2d_ctx *h, double *pos, double *vel, const double *
     PrepArgs a = prep_args(h, pos, q);
     a.pos_md = pos; a.vel = vel; a.F = F; a.freal = h->w.freal;
     a.dt = dt; a.zlo = zlo; a.zhi_from_top = zhi_from_top;
+    // a force evaluation with real space follows: count the particles per
+    // cell here, where their new positions are at hand
+    a.cell = h->w.cell; a.slot = h->w.slot; a.count = h->w.count;
     prof_begin(h, 7, s);
     if (with_real) launch_prep_kernel<2>(h, a, s);
     else launch_prep_kernel<1>(h, a, s);
     prof_end(h, 7, s);
+    h->cells_counted = h->n_total > 0;
     return hipGetLastError();
 }
 

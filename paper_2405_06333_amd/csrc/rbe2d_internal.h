@@ -172,6 +172,7 @@ struct rbe2d_ctx {
     int64_t split_cap = 0;           // targets per split of the partial real-space outputs
     int64_t fpart_blocks = 0;        // particle blocks' worth of force-pass partials (k-range splits)
     bool one_stream = false;         // run the k-space chain on the caller's stream too (no side stream)
+    bool cells_counted = false;      // the last MD pass counted the particles per cell (next build skips it)
     bool kset_valid = false;
     // current layout (host mirror); a layout is uploaded when it changes
     std::vector<int> lay_host;       // 5 x (n_sys + 1): off, pbase, bbase, tbase, sbase
@@ -271,6 +272,19 @@ inline void prof_end(rbe2d_ctx *h, int slot, hipStream_t s) {
     Profiler &p = h->prof;
     if (p.n > 0 && ((p.mask >> slot) & 1u) && p.used[slot] < p.n)
         (void)hipEventRecord(p.ev[slot][1][p.used[slot]++], s);
+}
+
+// Local cell of a particle: z-layer slowest, then x, then y (rows along y
+// are contiguous); xw, yw receive the wrapped lateral position.
+__device__ __forceinline__ int cell_of(double x, double y, double z, const SysDesc &d, double *xw, double *yw) {
+    double fx = x / d.Lx; fx -= floor(fx);
+    double fy = y / d.Ly; fy -= floor(fy);
+    *xw = fx * d.Lx;
+    *yw = fy * d.Ly;
+    const int cx = min(d.ncx - 1, max(0, (int)(*xw / d.hx)));
+    const int cy = min(d.ncy - 1, max(0, (int)(*yw / d.hy)));
+    const int cz = min(d.ncz - 1, max(0, (int)(z / d.hz)));   // z outside (0,H) is flagged by prep
+    return (cz * d.ncx + cx) * d.ncy + cy;
 }
 
 // Largest r in [0, n) with a[r] <= x, for a nondecreasing prefix array a[0..n].

@@ -67,20 +67,7 @@ __device__ __forceinline__ uint32_t to_fixed(double v, double scale) {
     return (uint32_t)(unsigned long long)llrint(v * scale);
 }
 
-// local cell of a particle: z-layer slowest, then x, then y (rows along y are contiguous)
-__device__ __forceinline__ int cell_of(double x, double y, double z, const SysDesc &d, double *xw,
-                                       double *yw) {
-    double fx = x / d.Lx; fx -= floor(fx);
-    double fy = y / d.Ly; fy -= floor(fy);
-    *xw = fx * d.Lx;
-    *yw = fy * d.Ly;
-    const int cx = min(d.ncx - 1, max(0, (int)(*xw / d.hx)));
-    const int cy = min(d.ncy - 1, max(0, (int)(*yw / d.hy)));
-    const int cz = min(d.ncz - 1, max(0, (int)(z / d.hz)));   // z outside (0,H) is flagged by prep
-    return (cz * d.ncx + cx) * d.ncy + cy;
-}
-
-__global__ __launch_bounds__(kBlock) void k_cell_assign(CellArgs a) {
+__global__ __launch_bounds__(kBlock) void k_cell_count(CellArgs a) {
     const int g = blockIdx.x * kBlock + threadIdx.x;
     if (g >= a.n_total) return;
     const int r = find_sys(a.lay.off, a.n_sys, g);
@@ -92,63 +79,84 @@ __global__ __launch_bounds__(kBlock) void k_cell_assign(CellArgs a) {
     a.slot[g] = atomicAdd(&a.count[c], 1);
 }
 
-// exclusive scan of count[0..ncells) into start[0..ncells] in three phases:
-// per-block totals, a scan of the block totals, per-block scans plus offset.
-constexpr int kScanBlock = 1024;
+// exclusive scan of count[0..ncells) into start[0..ncells] in two launches:
+// per-block totals of 4096 cells, then each block adds the totals before it
+// (at most a few hundred) to the scan of its own cells.  The second launch
+// also clears the counts for the next build.  Integer sums: the order does
+// not matter.
+constexpr int kScanPer = 16;                      // cells per thread
+constexpr int kScanCells = kBlock * kScanPer;     // cells per scan block
 
-__device__ __forceinline__ int block_exclusive_scan(int v, int *sh, int *total) {
-    // Hillis-Steele inclusive scan in shared memory (blockDim.x = kScanBlock)
-    sh[threadIdx.x] = v;
-    __syncthreads();
-    for (int o = 1; o < kScanBlock; o <<= 1) {
-        const int add = (int)threadIdx.x >= o ? sh[threadIdx.x - o] : 0;
-        __syncthreads();
-        sh[threadIdx.x] += add;
-        __syncthreads();
+__device__ __forceinline__ void load_counts(const int *count, int n, int c0, int (&v)[kScanPer]) {
+    if (c0 + kScanPer <= n && (c0 & 3) == 0) {
+        const int4 *p = reinterpret_cast<const int4 *>(count + c0);
+#pragma unroll
+        for (int k = 0; k < kScanPer / 4; k++) {
+            const int4 w = p[k];
+            v[4 * k] = w.x; v[4 * k + 1] = w.y; v[4 * k + 2] = w.z; v[4 * k + 3] = w.w;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < kScanPer; k++) v[k] = c0 + k < n ? count[c0 + k] : 0;
     }
-    const int incl = sh[threadIdx.x];
-    *total = sh[kScanBlock - 1];
-    __syncthreads();
-    return incl - v;
 }
 
-__global__ __launch_bounds__(kScanBlock) void k_scan_totals(const int *count, int n, int *btot) {
-    __shared__ int sh[kScanBlock / 64];
-    const int c = blockIdx.x * kScanBlock + threadIdx.x;
-    int v = c < n ? count[c] : 0;
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+__global__ __launch_bounds__(kBlock) void k_scan_totals(const int *count, int n, int *btot) {
+    __shared__ int sh[kBlock / 64];
+    int v[kScanPer];
+    load_counts(count, n, blockIdx.x * kScanCells + threadIdx.x * kScanPer, v);
+    int t = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; k++) t += v[k];
+    t = wave_sum(t);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = t;
     __syncthreads();
     if (threadIdx.x == 0) {
-        int t = 0;
-        for (int w = 0; w < kScanBlock / 64; w++) t += sh[w];
-        btot[blockIdx.x] = t;
+        int b = 0;
+        for (int w = 0; w < kBlock / 64; w++) b += sh[w];
+        btot[blockIdx.x] = b;
     }
 }
 
-// one block: exclusive scan of the block totals (nb may exceed the block size)
-__global__ __launch_bounds__(kScanBlock) void k_scan_blocks(int *btot, int nb) {
-    __shared__ int sh[kScanBlock];
-    int carry = 0;
-    for (int base = 0; base < nb; base += kScanBlock) {
-        const int i = base + threadIdx.x;
-        const int v = i < nb ? btot[i] : 0;
-        int tot;
-        const int ex = block_exclusive_scan(v, sh, &tot);
-        if (i < nb) btot[i] = carry + ex;
-        carry += tot;
+__global__ __launch_bounds__(kBlock) void k_scan_apply(int *count, int n, const int *btot, int *start) {
+    __shared__ int sh_wave[kBlock / 64];
+    __shared__ int sh_base;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (wid == 0) {
+        // cells before this block: the totals of the blocks before it
+        int b = 0;
+        for (int k = lane; k < (int)blockIdx.x; k += 64) b += btot[k];
+        b = wave_sum(b);
+        if (lane == 0) sh_base = b;
     }
-}
-
-__global__ __launch_bounds__(kScanBlock) void k_scan_apply(const int *count, int n, const int *btot,
-                                                           int *start) {
-    __shared__ int sh[kScanBlock];
-    const int c = blockIdx.x * kScanBlock + threadIdx.x;
-    const int v = c < n ? count[c] : 0;
-    int tot;
-    const int ex = block_exclusive_scan(v, sh, &tot);
-    if (c < n) start[c] = btot[blockIdx.x] + ex;
-    if (c == n - 1) start[n] = btot[blockIdx.x] + ex + v;
+    const int c0 = blockIdx.x * kScanCells + threadIdx.x * kScanPer;
+    int v[kScanPer];
+    load_counts(count, n, c0, v);
+    int t = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; k++) t += v[k];
+    // inclusive scan of the thread totals over the wave, then over the waves
+    int incl = t;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int u = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += u;
+    }
+    if (lane == 63) sh_wave[wid] = incl;
+    __syncthreads();
+    int before = sh_base;
+    for (int w = 0; w < wid; w++) before += sh_wave[w];
+    int run = before + incl - t;
+#pragma unroll
+    for (int k = 0; k < kScanPer; k++) {
+        const int c = c0 + k;
+        if (c < n) {
+            start[c] = run;
+            count[c] = 0;       // the next build counts from zero
+        }
+        run += v[k];
+        if (c == n - 1) start[n] = run;
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_cell_scatter(CellArgs a) {
@@ -816,12 +824,13 @@ hipError_t launch_cells(rbe2d_ctx *h, const double *pos, const double *q, hipStr
     c.tmp = h->w.tmp; c.sidx = h->w.sidx; c.scell = h->w.scell; c.sorted = h->w.sorted; c.src16 = h->w.src16;
     const int nb = (int)((h->n_total + kBlock - 1) / kBlock);
     prof_begin(h, 3, s);
-    (void)launch_fill(h->w.count, (int64_t)h->total_cells * 4, s);
-    hipLaunchKernelGGL(k_cell_assign, dim3(nb), dim3(kBlock), 0, s, c);
-    const int nsb = (h->total_cells + kScanBlock - 1) / kScanBlock;
-    hipLaunchKernelGGL(k_scan_totals, dim3(nsb), dim3(kScanBlock), 0, s, h->w.count, h->total_cells, h->w.scanbuf);
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kScanBlock), 0, s, h->w.scanbuf, nsb);
-    hipLaunchKernelGGL(k_scan_apply, dim3(nsb), dim3(kScanBlock), 0, s, h->w.count, h->total_cells, h->w.scanbuf,
+    // the counts start at zero (the previous build's scan cleared them); the
+    // MD pass that moved the particles may have counted them already
+    if (!h->cells_counted) hipLaunchKernelGGL(k_cell_count, dim3(nb), dim3(kBlock), 0, s, c);
+    h->cells_counted = false;
+    const int nsb = (h->total_cells + kScanCells - 1) / kScanCells;
+    hipLaunchKernelGGL(k_scan_totals, dim3(nsb), dim3(kBlock), 0, s, h->w.count, h->total_cells, h->w.scanbuf);
+    hipLaunchKernelGGL(k_scan_apply, dim3(nsb), dim3(kBlock), 0, s, h->w.count, h->total_cells, h->w.scanbuf,
                        h->w.start);
     hipLaunchKernelGGL(k_cell_scatter, dim3(nb), dim3(kBlock), 0, s, c);
     hipLaunchKernelGGL(k_cell_rank, dim3(nb), dim3(kBlock), 0, s, c);
