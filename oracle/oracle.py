@@ -75,6 +75,8 @@ def _declare(L):
     L.orc_self.restype = ctypes.c_double
     L.orc_real.argtypes = [ctypes.c_int64, _D, _D, ctypes.POINTER(_Box), ctypes.c_int64, _I64,
                            _D, _D, _D, _D]
+    L.orc_surface.argtypes = [ctypes.c_int64, _D, _D, ctypes.POINTER(_Box), ctypes.c_double, ctypes.c_double,
+                              ctypes.c_int64, _I64, _D, _D, _D, _D]
     L.orc_short.argtypes = [ctypes.c_int64, _D, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                             ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double, _D, _D, _D]
 
@@ -336,15 +338,35 @@ def real_space(slab: Slab, pos, q, targets=None, want_dgamma=False, box=None):
     return E[0], F, phi, dphig
 
 
+def surface(slab: Slab, pos, q, sig_top, sig_bot, targets=None, box=None):
+    """Surface charge densities sig_top on z = H and sig_bot on z = 0 (the
+    remark after Eq. (3.26); readings R7, R8 in rbe2d_oracle.c): the sheets'
+    field on the ions and the net-charge term of the Lz-periodic k-sum.
+    Returns (E, F (n_t, 3), phi (n_t,), dE/dgamma (2,))."""
+    pos, q = _prep(pos, q)
+    tgt = None if targets is None else np.ascontiguousarray(targets, dtype=np.int64)
+    nt = len(q) if tgt is None else len(tgt)
+    E = np.zeros(1)
+    F = np.zeros((nt, 3))
+    phi = np.zeros(nt)
+    dg = np.zeros(2)
+    b = slab.box() if box is None else box
+    lib().orc_surface(len(q), _p(pos), _p(q), ctypes.byref(b), float(sig_top), float(sig_bot), nt,
+                      _p(tgt, _I64), _p(E), _p(F), _p(phi), _p(dg))
+    return E[0], F, phi, dg
+
+
 def self_energy(slab: Slab, q):
     q = np.ascontiguousarray(q, dtype=np.float64)
     return lib().orc_self(len(q), _p(q), slab.alpha)
 
 
 def evaluate(slab: Slab, pos, q, n, c=None, explicit_images=False, targets=None,
-             parts=("real", "kspace", "ibc")) -> Result:
+             parts=("real", "kspace", "ibc"), sigma=None) -> Result:
     """Energy components, forces and dE/dq of the RBE2D splitting for a given
-    k-set ``n`` with weights ``c`` (default: RBE weights of Eq. (3.26))."""
+    k-set ``n`` with weights ``c`` (default: RBE weights of Eq. (3.26)).
+    sigma = (sig_top, sig_bot): surface charge densities on the interfaces;
+    their terms (``surface``) go with the IBC part."""
     pos, q = _prep(pos, q)
     nt = len(q) if targets is None else len(targets)
     z3 = np.zeros((nt, 3))
@@ -359,16 +381,19 @@ def evaluate(slab: Slab, pos, q, n, c=None, explicit_images=False, targets=None,
         Ek, Fk, phk, *_ = kspace(slab, pos, q, n, c, explicit_images, targets)
     if "ibc" in parts:
         Ei, Fi, phi_, _ = ibc(slab, pos, q, targets)
+        if sigma is not None and (sigma[0] != 0.0 or sigma[1] != 0.0):
+            Eu, Fu, phu, _ = surface(slab, pos, q, sigma[0], sigma[1], targets)
+            Ei, Fi, phi_ = Ei + Eu, Fi + Fu, phi_ + phu
     Es = self_energy(slab, q) if "kspace" in parts else 0.0
     tq = q if targets is None else q[np.asarray(targets)]
     ph = phr + phk + phi_ + (-2.0 * slab.alpha / math.sqrt(math.pi) * tq if "kspace" in parts else 0.0)
     return Result(Er + Ek + Es + Ei, Er, Ek, Es, Ei, Fr + Fk + Fi, Fr, Fk, Fi, ph)
 
 
-def dE_dgamma(slab: Slab, pos, q, n, c=None):
+def dE_dgamma(slab: Slab, pos, q, n, c=None, sigma=None):
     """dE/dgamma_top, dE/dgamma_bot of the RBE2D energy at fixed k-set:
-    real-space image weights (Eq. (3.12)), rho^M (Eq. (3.17)) and the IBC
-    image dipole (Theorem 3.3)."""
+    real-space image weights (Eq. (3.12)), rho^M (Eq. (3.17)), the IBC
+    image dipole (Theorem 3.3) and, with sigma, the surface terms."""
     pos, q = _prep(pos, q)
     if c is None:
         c = rbe_weights(slab, n)
@@ -380,6 +405,8 @@ def dE_dgamma(slab: Slab, pos, q, n, c=None):
     dk = np.array([lib().orc_kspace_dgamma(len(q), _p(pos), _p(q), ctypes.byref(b), len(n),
                                            _p(n, _I32), _p(c), w) for w in (0, 1)])
     _, _, _, dibc = ibc(slab, pos, q)
+    if sigma is not None and (sigma[0] != 0.0 or sigma[1] != 0.0):
+        dibc = dibc + surface(slab, pos, q, sigma[0], sigma[1])[3]
     return dreal + dk + dibc
 
 

@@ -417,6 +417,130 @@ void orc_ibc(int64_t N, const double *pos, const double *q, const orc_box *b,
     free(gm);
 }
 
+/* ------------------------------------------------------------------ */
+/* Surface charges on the interfaces (remark after Eq. (3.26); the     */
+/* supplement it refers to is not available -- readings R7, R8 below) */
+/* ------------------------------------------------------------------ */
+
+/*
+ * R7  A uniform surface charge density sigma_bot on the interface z = 0 and
+ *     sigma_top on z = H are sheets of charge taken just inside the slab.
+ *     Their images follow the image series of Sec. 3.1 (a sheet is a
+ *     charge distribution like any other: its order-l images are sheets at
+ *     the image heights with the image weights).  A uniform sheet s at
+ *     height z_s has the potential -2 pi s |z - z_s| in the doubly periodic
+ *     geometry (the zero lateral mode), so an ion q_i at z_i gains
+ *       E = q_i phi_s(z_i),  phi_s(z) = -2 pi sum_{sheets, images} w sigma |z - z_w|,
+ *       F_z = 2 pi q_i sum w sigma sign(z_i - z_w).
+ * R8  With surface charges the ions are not neutral (Q = sum q_i != 0).
+ *     Theorem 3.3 assumes neutrality: its k-sum over the Lz-periodic box
+ *     drops k = 0.  Writing out the k_x = k_y = 0 part of that sum for the
+ *     pair potential (4 pi / V) sum_{kz != 0} e^{i kz d}/kz^2 = -(2 pi/(Lx Ly))|d|
+ *     + (2 pi / V) d^2 + const shows that, besides the IBC term
+ *     (2 pi / V) mu mu^M, the slab energy needs
+ *       U_Q = -(pi / V) sum_{i, j, images w} q_i q_j w (z_i^2 + (z_j^w)^2),
+ *     which vanishes for neutral ions.  Position-independent terms are
+ *     dropped, so with Q != 0 the energy is defined up to a constant (and
+ *     dE/dq up to a term proportional to Q); forces are unique.
+ *
+ * orc_surface returns the two additions (sheet field and U_Q): the energy
+ * E, the forces F (n_t x 3, z only), phi = dE/dq_i for the targets and,
+ * with dEdg, dE/dgamma_{top,bot}.
+ */
+void orc_surface(int64_t N, const double *pos, const double *q, const orc_box *b, double sig_top,
+                 double sig_bot, int64_t n_t, const int64_t *tgt, double *E, double *F, double *phi,
+                 double *dEdg)
+{
+    double V = b->Lx * b->Ly * b->Lz;
+    double *gp = malloc(sizeof(double) * (b->M + 1));
+    double *gm = malloc(sizeof(double) * (b->M + 1));
+    orc_image_coeffs(b->M, b->g_top, b->g_bot, gp, gm);
+    /* weights and their gamma derivatives of the sources: w[0] = real, then
+     * the + and - image of each order; the image heights of a charge at z
+     * are z_w = s_w z + c_w with s_w = (-1)^l */
+    int nw = 1 + 2 * b->M;
+    double *w = malloc(sizeof(double) * nw), *dwt = malloc(sizeof(double) * nw), *dwb = malloc(sizeof(double) * nw);
+    w[0] = 1.0; dwt[0] = 0.0; dwb[0] = 0.0;
+    for (int o = 1; o <= b->M; o++) {
+        for (int k = 0; k < 2; k++) {
+            int sgn = k == 0 ? +1 : -1, a, bb;
+            orc_image_exponents(o, sgn, &a, &bb);
+            int idx = 2 * o - 1 + k;
+            w[idx] = sgn > 0 ? gp[o - 1] : gm[o - 1];
+            dwt[idx] = a ? a * ipow(b->g_top, a - 1) * ipow(b->g_bot, bb) : 0.0;
+            dwb[idx] = bb ? bb * ipow(b->g_bot, bb - 1) * ipow(b->g_top, a) : 0.0;
+        }
+    }
+#define ZW(idx, z) ((idx) == 0 ? (z) : orc_image_z(((idx) + 1) / 2, ((idx) % 2) ? +1 : -1, (z), b->H))
+#define SW(idx) ((idx) == 0 ? 1.0 : ((((idx) + 1) / 2) % 2 ? -1.0 : 1.0))
+    /* sums over the sources: Q^M = sum_{j,w} q_j w, QZ2 = sum_{j,w} q_j w z_j^w^2,
+     * S2 = sum q z^2, Q = sum q, and their gamma derivatives */
+    double Q = 0, S2 = 0, QM = 0, QZ2 = 0, dQM[2] = {0, 0}, dQZ2[2] = {0, 0};
+    for (int64_t j = 0; j < N; j++) {
+        double z = pos[3 * j + 2];
+        Q += q[j];
+        S2 += q[j] * z * z;
+        for (int k = 0; k < nw; k++) {
+            double zw = ZW(k, z);
+            QM += q[j] * w[k];
+            QZ2 += q[j] * w[k] * zw * zw;
+            dQM[0] += q[j] * dwt[k]; dQM[1] += q[j] * dwb[k];
+            dQZ2[0] += q[j] * dwt[k] * zw * zw; dQZ2[1] += q[j] * dwb[k] * zw * zw;
+        }
+    }
+    double UQ = -ORC_PI / V * (S2 * QM + Q * QZ2);
+    /* the two sheets (bottom at z = 0, top at z = H, from inside) and their images */
+    const double zs[2] = {0.0, b->H}, sg[2] = {sig_bot, sig_top};
+    double Es = 0.0, dEs[2] = {0, 0};
+    for (int64_t i = 0; i < N; i++) {
+        double z = pos[3 * i + 2], ph = 0.0, dph[2] = {0, 0};
+        for (int s = 0; s < 2; s++)
+            for (int k = 0; k < nw; k++) {
+                double d = fabs(z - ZW(k, zs[s]));
+                ph += -2.0 * ORC_PI * sg[s] * w[k] * d;
+                dph[0] += -2.0 * ORC_PI * sg[s] * dwt[k] * d;
+                dph[1] += -2.0 * ORC_PI * sg[s] * dwb[k] * d;
+            }
+        Es += q[i] * ph;
+        dEs[0] += q[i] * dph[0];
+        dEs[1] += q[i] * dph[1];
+    }
+    if (E) *E = UQ + Es;
+    if (dEdg)
+        for (int c = 0; c < 2; c++) dEdg[c] = -ORC_PI / V * (S2 * dQM[c] + Q * dQZ2[c]) + dEs[c];
+    int64_t nt = tgt ? n_t : N;
+    for (int64_t t = 0; t < nt; t++) {
+        int64_t i = tgt ? tgt[t] : t;
+        double z = pos[3 * i + 2];
+        /* d/dz_i of sum_w w z_i^w^2 = sum_w w 2 s_w z_i^w; of the sheet potential */
+        double dZ2 = 0.0, Z2i = 0.0, Wi = 0.0, fs = 0.0, phs = 0.0;
+        for (int k = 0; k < nw; k++) {
+            double zw = ZW(k, z);
+            dZ2 += w[k] * 2.0 * SW(k) * zw;
+            Z2i += w[k] * zw * zw;
+            Wi += w[k];
+        }
+        for (int s = 0; s < 2; s++)
+            for (int k = 0; k < nw; k++) {
+                double dz = z - ZW(k, zs[s]);
+                fs += 2.0 * ORC_PI * sg[s] * w[k] * (dz > 0 ? 1.0 : (dz < 0 ? -1.0 : 0.0));
+                phs += -2.0 * ORC_PI * sg[s] * w[k] * fabs(dz);
+            }
+        if (F) {
+            F[3 * t] = 0.0;
+            F[3 * t + 1] = 0.0;
+            /* -d U_Q / d z_i: U_Q has q_i z_i^2 Q^M and Q q_i sum_w w z_i^w^2 */
+            F[3 * t + 2] = ORC_PI / V * (2.0 * q[i] * z * QM + Q * q[i] * dZ2) + q[i] * fs;
+        }
+        if (phi) phi[t] = -ORC_PI / V * (z * z * QM + S2 * Wi + QZ2 + Q * Z2i) + phs;
+    }
+#undef ZW
+#undef SW
+    free(w); free(dwt); free(dwb);
+    free(gp);
+    free(gm);
+}
+
 /* Self-energy correction -alpha/sqrt(pi) sum q_i^2 (Eq. (3.16)). */
 double orc_self(int64_t N, const double *q, double alpha)
 {

@@ -42,11 +42,12 @@ def test_single_interface_is_one_jackson_image(orc):
     assert orc.image_z(1, +1, 0.7, H) == pytest.approx(2 * H - 0.7)
 
 
-def _layered_reflection(h, z, zp, H, g_top, g_bot):
+def _layered_reflection(h, z, zp, H, g_top, g_bot, deriv=False):
     """Reflected part of the xy-Fourier-transformed potential of a unit charge
     at z' in the middle layer of a three-layer dielectric (eps_c = 1),
     obtained by imposing continuity of phi and of eps dphi/dz at z = 0 and
-    z = H (4x4 linear solve).  Returns R(z) with phi_hat = 2pi/h e^{-h|z-z'|} + R."""
+    z = H (4x4 linear solve).  Returns R(z) with phi_hat = 2pi/h e^{-h|z-z'|} + R
+    (with deriv, dR/dz instead)."""
     e_top = (1 - g_top) / (1 + g_top)
     e_bot = (1 - g_bot) / (1 + g_bot)
     G0 = 2 * np.pi / h
@@ -65,6 +66,8 @@ def _layered_reflection(h, z, zp, H, g_top, g_bot):
         G0 * np.exp(-h * (H - zp)),
     ])
     A, B, C, D = np.linalg.solve(Amat, rhs)
+    if deriv:
+        return h * (B * np.exp(h * z) - C * np.exp(-h * z))
     return B * np.exp(h * z) + C * np.exp(-h * z)
 
 
@@ -273,6 +276,109 @@ def test_fold_z_is_specular_reflection(orc):
     assert orc.fold_z(zhi + 0.5, 2.0, zlo, zhi) == pytest.approx((zhi - 0.5, -2.0))
     z, v = orc.fold_z(zlo - (W + 0.5), -7.0, zlo, zhi)
     assert (z, v) == pytest.approx((zhi - 0.5, -7.0))
+
+
+# --------------------------------------------------------------------------
+# Surface charges on the interfaces (remark after Eq. (3.26); readings R7,
+# R8 of the oracle)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("g_top,g_bot", [(0.7, -0.4), (-0.9, 0.95), (0.5, 0.5), (0.0, 0.8), (-0.6, 0.0)])
+def test_sheet_field_is_the_layered_solution(orc, g_top, g_bot):
+    """The field of a uniform sheet on either interface inside the slab is the
+    zero lateral mode of the layered-medium Poisson problem (its h -> 0
+    limit, Richardson-extrapolated from h = 1e-5 and 1e-6, with the
+    interface conditions imposed directly): it does not depend on z, and for
+    one interface it is 2 pi sigma (1 + gamma)."""
+    H = 1.3
+    s = orc.Slab(Lx=10, Ly=10, H=H, g_top=g_top, g_bot=g_bot, alpha=1.0, rc=4.9, M=400, P=10)
+    z = np.array([0.2, 0.7, 1.1])
+    pos = np.c_[np.ones(3), np.ones(3), z]
+    q = np.ones(3)
+    _, F0, _, _ = orc.surface(s, pos, q, 0.0, 0.0)           # the net-charge term alone
+    for top in (False, True):
+        zp = H - 1e-9 if top else 1e-9
+        _, F1, _, _ = orc.surface(s, pos, q, 1.0 if top else 0.0, 0.0 if top else 1.0)
+        field = (F1 - F0)[:, 2]
+        for zz, f in zip(z, field):
+            def lay(h):
+                dR = _layered_reflection(h, zz, zp, H, g_top, g_bot, deriv=True)
+                return 2 * np.pi * np.sign(zz - zp) * np.exp(-h * abs(zz - zp)) - dR
+            ref = (10.0 * lay(1e-6) - lay(1e-5)) / 9.0
+            assert f == pytest.approx(ref, rel=1e-6, abs=1e-7)
+    if g_top == 0.0:
+        _, F1, _, _ = orc.surface(s, pos, q, 0.0, 1.0)
+        assert (F1 - F0)[0, 2] == pytest.approx(2 * np.pi * (1 + g_bot), rel=1e-12)
+
+
+def _lattice(L, n, z, sigma):
+    g = (np.arange(n) + 0.5) * L / n
+    X, Y = np.meshgrid(g, g, indexing="ij")
+    return np.c_[X.ravel(), Y.ravel(), np.full(n * n, z)], np.full(n * n, sigma * L * L / (n * n))
+
+
+@pytest.mark.parametrize("g_top,g_bot,M", [(0.0, 0.0, 0), (0.6, -0.3, 3), (-0.8, 0.7, 4)])
+def test_surface_charges_match_point_charge_lattice(orc, g_top, g_bot, M):
+    """Non-neutral ions between charged interfaces (the whole system neutral):
+    the ions' forces with the surface terms (sheet field R7 and net-charge
+    term R8) equal those of the same ions plus a 24 x 24 lattice of point
+    charges standing in for each sheet (1e-3 inside the slab), evaluated
+    with the neutral reformulation of Theorem 3.3 and the full k-sum.  The
+    sheet field alone, or no surface term, is off by 1e-2 to 1e-1.  Energy
+    differences between two ion configurations agree as well."""
+    L, H = 10.0, 4.0
+    rng = np.random.default_rng(5)
+    qi = np.array([1.0, -1.0, 2.0, 1.0, -1.0, 1.0])           # Q = 3
+    sb, st = -0.01, -0.02                                        # -Q / L^2 on the two sheets
+    s = orc.Slab(Lx=L, Ly=L, H=H, g_top=g_top, g_bot=g_bot, alpha=1.0, rc=4.9, M=M, P=10)
+    kn, kc = orc.full_kset(s, 40.0)
+    pb, qb = _lattice(L, 24, 1e-3, sb)
+    pt, qt = _lattice(L, 24, H - 1e-3, st)
+    energies = []
+    for conf in range(2):
+        ions = np.c_[rng.uniform(0, L, 6), rng.uniform(0, L, 6), rng.uniform(1.2, H - 1.2, 6)]
+        ref = orc.evaluate(s, np.r_[ions, pb, pt], np.r_[qi, qb, qt], kn, kc, targets=np.arange(6))
+        sur = orc.evaluate(s, ions, qi, kn, kc, sigma=(st, sb))
+        scale = np.abs(ref.F).max()
+        assert np.abs(sur.F - ref.F).max() <= 1e-8 * scale
+        lit = orc.evaluate(s, ions, qi, kn, kc)
+        sheets_only = lit.F + orc.surface(s, ions, qi, st, sb)[1] - orc.surface(s, ions, qi, 0.0, 0.0)[1]
+        assert np.abs(lit.F - ref.F).max() > 1e-2 * scale
+        assert np.abs(sheets_only - ref.F).max() > 1e-3 * scale
+        full = orc.evaluate(s, np.r_[ions, pb, pt], np.r_[qi, qb, qt], kn, kc)
+        energies.append((full.E_total, sur.E_total))
+    d_ref = energies[1][0] - energies[0][0]
+    d_sur = energies[1][1] - energies[0][1]
+    assert d_sur == pytest.approx(d_ref, rel=1e-7, abs=1e-9)
+
+
+def test_surface_terms_are_derivatives(orc):
+    """F = -dE/dz, phi = dE/dq and dE/dgamma of the surface terms against
+    central finite differences."""
+    H = 3.0
+    s = orc.Slab(Lx=8, Ly=8, H=H, g_top=0.55, g_bot=-0.7, alpha=1.0, rc=3.9, M=5, P=10)
+    rng = np.random.default_rng(8)
+    pos = np.c_[rng.uniform(0, 8, 5), rng.uniform(0, 8, 5), rng.uniform(0.3, H - 0.3, 5)]
+    q = np.array([1.0, -2.0, 1.5, 1.0, 0.5])
+    sig = (0.02, -0.035)
+    E, F, phi, dg = orc.surface(s, pos, q, *sig)
+    h = 1e-6
+    for i in range(5):
+        p1, p2 = pos.copy(), pos.copy()
+        p1[i, 2] += h
+        p2[i, 2] -= h
+        fd = -(orc.surface(s, p1, q, *sig)[0] - orc.surface(s, p2, q, *sig)[0]) / (2 * h)
+        assert F[i, 2] == pytest.approx(fd, rel=1e-6, abs=1e-9)
+        q1, q2 = q.copy(), q.copy()
+        q1[i] += h
+        q2[i] -= h
+        fdq = (orc.surface(s, pos, q1, *sig)[0] - orc.surface(s, pos, q2, *sig)[0]) / (2 * h)
+        assert phi[i] == pytest.approx(fdq, rel=1e-6, abs=1e-9)
+    for c, key in ((0, "g_top"), (1, "g_bot")):
+        b1 = s.box(**{key: getattr(s, key) + h})
+        b2 = s.box(**{key: getattr(s, key) - h})
+        fdg = (orc.surface(s, pos, q, *sig, box=b1)[0] - orc.surface(s, pos, q, *sig, box=b2)[0]) / (2 * h)
+        assert dg[c] == pytest.approx(fdg, rel=1e-6, abs=1e-9)
 
 
 # --------------------------------------------------------------------------
