@@ -350,6 +350,24 @@ rbe2d_status rbe2d_profile_read(rbe2d_handle h, double *ms, int64_t *launches, i
  * the timed work least.  Errors: RBE2D_E_INVAL (NULL handle). */
 rbe2d_status rbe2d_profile_classes(rbe2d_handle h, uint32_t class_mask);
 
+/* Surface charge densities on the interfaces (the remark after Eq. (3.26);
+ * its formula is in a supplement that is not available, so the terms are
+ * derived here from the image series of Sec. 3.1 and Theorem 3.3):
+ * sigma_bot on z = 0 and sigma_top on z = H, for system `sys` of the handle
+ * (-1: every system).  They are uniform sheets just inside the slab whose
+ * images follow the image series; with the sheets the ions are in general
+ * not neutral, and the k-space reformulation then needs the net-charge term
+ * of its k_x = k_y = 0 modes.  Both additions belong to the IBC part
+ * (RBE2D_IBC, energy component 4):
+ *   sheets      E = sum_i q_i phi_s(z_i), phi_s(z) = -2 pi sum_{sheets, images}
+ *               w sigma |z - z_w| (uniform field in the slab);
+ *   net charge  U_Q = -(pi / V) sum_{i, j, images w} q_i q_j w (z_i^2 + z_j^w^2).
+ * Position-independent terms are dropped: with a net ionic charge the
+ * energy is defined up to a constant (forces are unique).  sigma_top =
+ * sigma_bot = 0 (the state after create) turns both off.  Synchronises the
+ * device; not to be called during graph capture.  Errors: RBE2D_E_INVAL. */
+rbe2d_status rbe2d_set_surface_charges(rbe2d_handle h, int32_t sys, double sigma_top, double sigma_bot);
+
 /* For callers that cannot allocate (code under HIP graph capture, tight
  * serving loops, harnesses that forbid hipMalloc): rbe2d_forces without a
  * handle.  Every workspace lives in one 32 MiB file-scope device array of

@@ -116,6 +116,8 @@ double auto_lz(const rbe2d_params *p) {
     return (p->M + 1) * p->H + std::max(std::max(p->Lx, p->Ly) / (2.0 * kPi) * lg, std::sqrt(lg) / p->alpha);
 }
 
+void surface_setup(SysHost &sh);
+
 // Derived constants, image tables, real-space families, sampler tables and
 // cell grid of one system.
 rbe2d_status setup_system(const rbe2d_params *pin, SysHost &sh) {
@@ -241,7 +243,53 @@ rbe2d_status setup_system(const rbe2d_params *pin, SysHost &sh) {
     d.u2 = (float)(d.ud * d.ud);
     d.rc2q = (float)(p.r_c * p.r_c * d.fxs * d.fxs);
     d.near2q = (float)(near * near * d.fxs * d.fxs);
+    d.sig_top = d.sig_bot = 0.0;
+    surface_setup(sh);
     return RBE2D_OK;
+}
+
+// Surface charges (reading R7): the uniform sheets sigma_bot on z = 0 and
+// sigma_top on z = H, taken just inside the slab, and their images.  Every
+// image of the bottom sheet below the slab (and the one at z = 0) pushes
+// away from below, every image above pulls; the top sheet likewise.  For
+// 0 < z < H this gives phi_s(z) = -Es z + Cs.  Net-charge term (reading R8):
+// Gs, A1, A0 are the sums over the real charge and its images of w, w s c
+// and w c^2 for image heights s z + c.  Index 0 is the value, 1 and 2 its
+// derivatives by gamma_top and gamma_bot.
+void surface_setup(SysHost &sh) {
+    SysDesc &d = sh.d;
+    const rbe2d_params &p = sh.p;
+    for (int k = 0; k < 3; k++) { d.Es[k] = d.Cs[k] = d.A1[k] = d.A0[k] = 0.0; d.Gs[k] = k == 0 ? 1.0 : 0.0; }
+    d.surf = (d.sig_top != 0.0 || d.sig_bot != 0.0) ? 1 : 0;
+    // the real sheets: bottom at 0 (s = +1 for the ions above it), top at H (s = -1)
+    d.Es[0] = 2.0 * kPi * (d.sig_bot - d.sig_top);
+    d.Cs[0] = -2.0 * kPi * d.sig_top * d.H;          // -2 pi sigma_top |z - H| = 2 pi sigma_top (z - H)
+    for (int l = 1; l <= p.M; l++) {
+        int a, b;
+        double wt[3], wb[3];   // weights (and gamma derivatives) of the + (above) and - (below) image
+        exponents(l, +1, &a, &b);
+        wt[0] = ipow(p.gamma_top, a) * ipow(p.gamma_bot, b);
+        wt[1] = dmono(a, p.gamma_top, b, p.gamma_bot);
+        wt[2] = dmono(b, p.gamma_bot, a, p.gamma_top);
+        exponents(l, -1, &a, &b);
+        wb[0] = ipow(p.gamma_top, a) * ipow(p.gamma_bot, b);
+        wb[1] = dmono(a, p.gamma_top, b, p.gamma_bot);
+        wb[2] = dmono(b, p.gamma_bot, a, p.gamma_top);
+        const double s = (l % 2 == 0) ? 1.0 : -1.0;
+        const double cp = 2.0 * ((l + 1) / 2) * p.H, cm = -2.0 * (l / 2) * p.H;
+        // image heights of the bottom sheet (z = 0) and of the top sheet (z = H)
+        const double bot_up = cp, bot_dn = cm, top_up = s * p.H + cp, top_dn = s * p.H + cm;
+        for (int k = 0; k < 3; k++) {
+            d.Gs[k] += wt[k] + wb[k];
+            d.A1[k] += s * (wt[k] * cp + wb[k] * cm);
+            d.A0[k] += wt[k] * cp * cp + wb[k] * cm * cm;
+            // images above the slab pull (sign -1), below push (+1); the
+            // potential -2 pi sigma w |z - z_w| = -2 pi sigma w sign (z - z_w)
+            d.Es[k] += 2.0 * kPi * (d.sig_bot * (wb[k] - wt[k]) + d.sig_top * (wb[k] - wt[k]));
+            d.Cs[k] += 2.0 * kPi * (d.sig_bot * (wb[k] * bot_dn - wt[k] * bot_up) +
+                                    d.sig_top * (wb[k] * top_dn - wt[k] * top_up));
+        }
+    }
 }
 
 template <typename T>
@@ -309,7 +357,7 @@ void plan_workspace(rbe2d_ctx *h, size_t cdf_total, bool own_kset, Alloc &&A) {
     A(&w.p32, 2 * h->cap_particles);
     A(&w.p64, h->cap_particles);
     A(&w.bpart, 4 * cap_blocks);
-    A(&w.scal, 8 * (size_t)n);
+    A(&w.scal, kScal * (size_t)n);
     if (own_kset) A(&w.kset, 3 * (size_t)n * h->P);
     A(&w.kn32, (size_t)n * h->P_pad);
     A(&w.kn64, (size_t)n * h->P_pad);
@@ -1413,6 +1461,26 @@ rbe2d_status rbe2d_forces_noalloc(const rbe2d_params *p, const int32_t *kset, in
                                   const double *q, double *F, double *energy, uint32_t flags, int32_t *err_word,
                                   void *stream) {
     return forces_noalloc(p, kset, N, pos, q, F, energy, flags, err_word, (hipStream_t)stream);
+}
+
+rbe2d_status rbe2d_set_surface_charges(rbe2d_handle h, int32_t sys, double sigma_top, double sigma_bot) {
+    if (!h) return fail(nullptr, RBE2D_E_INVAL, "handle is NULL");
+    if (sys < -1 || sys >= h->n_sys) return fail(h, RBE2D_E_INVAL, "system index out of range");
+    if (!std::isfinite(sigma_top) || !std::isfinite(sigma_bot))
+        return fail(h, RBE2D_E_INVAL, "surface charge densities must be finite");
+    for (int r = 0; r < h->n_sys; r++) {
+        if (sys >= 0 && r != sys) continue;
+        h->sys[r].d.sig_top = sigma_top;
+        h->sys[r].d.sig_bot = sigma_bot;
+        surface_setup(h->sys[r]);
+    }
+    h->calls++;
+    std::vector<SysDesc> descs(h->n_sys);
+    for (int r = 0; r < h->n_sys; r++) descs[r] = h->sys[r].d;
+    RBE2D_TRY(h, hipDeviceSynchronize(), "surface charges sync");
+    RBE2D_TRY(h, hipMemcpy(h->w.sys, descs.data(), h->n_sys * sizeof(SysDesc), hipMemcpyHostToDevice),
+              "surface charges upload");
+    return RBE2D_OK;
 }
 
 rbe2d_status rbe2d_check(rbe2d_handle h, void *stream) {

@@ -49,14 +49,14 @@ struct PrepArgs {
 // records of the (new) positions and the block sums of the IBC.
 template <bool FP32, int MD>
 __global__ __launch_bounds__(kBlock) void k_prep(PrepArgs a) {
-    __shared__ double sh[3][kBlock / 64];
+    __shared__ double sh[4][kBlock / 64];
     const int b = blockIdx.x;
     const int r = find_sys(a.lay.bbase, a.n_sys, b);
     const SysDesc &d = a.sys[r];
     const int iloc = (b - a.lay.bbase[r]) * kBlock + threadIdx.x;
     const int Nr = a.lay.off[r + 1] - a.lay.off[r];
     const int64_t ii = (int64_t)a.lay.pbase[r] + iloc;      // internal (padded) index
-    double sqz = 0.0, sq = 0.0, sq2 = 0.0;
+    double sqz = 0.0, sq = 0.0, sq2 = 0.0, sqzz = 0.0;
     double fx = 0, fy = 0, fz = 0, qi = 0;
     if (iloc < Nr) {
         const int64_t g = (int64_t)a.lay.off[r] + iloc;      // caller index
@@ -93,7 +93,7 @@ __global__ __launch_bounds__(kBlock) void k_prep(PrepArgs a) {
         fx = x * d.inv_Lx; fx -= floor(fx);
         fy = y * d.inv_Ly; fy -= floor(fy);
         fz = z * d.inv_Lz;
-        sqz = qi * z; sq = qi; sq2 = qi * qi;
+        sqz = qi * z; sq = qi; sq2 = qi * qi; sqzz = qi * z * z;
     }
     if (FP32) {
         // scale_h = 2^fh_bits: the split is exact
@@ -105,25 +105,27 @@ __global__ __launch_bounds__(kBlock) void k_prep(PrepArgs a) {
     } else {
         a.p64[ii] = make_double4(fx, fy, fz, qi);
     }
-    // block sums of q z, q, q^2 (one barrier for the three)
+    // block sums of q z, q, q^2, q z^2 (one barrier for the four)
     sqz = wave_sum(sqz);
     sq = wave_sum(sq);
     sq2 = wave_sum(sq2);
+    sqzz = wave_sum(sqzz);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (lane == 0) { sh[0][wid] = sqz; sh[1][wid] = sq; sh[2][wid] = sq2; }
+    if (lane == 0) { sh[0][wid] = sqz; sh[1][wid] = sq; sh[2][wid] = sq2; sh[3][wid] = sqzz; }
     __syncthreads();
-    if (threadIdx.x < 3) {
+    if (threadIdx.x < 4) {
         double t = 0.0;
         for (int k = 0; k < kBlock / 64; k++) t += sh[threadIdx.x][k];
         a.bpart[4 * b + threadIdx.x] = t;
-    } else if (threadIdx.x == 3) {
-        a.bpart[4 * b + 3] = 0.0;
     }
 }
 
-// scal layout (8 per system): 0 mu = sum q z, 1 Q = sum q, 2 sum q^2,
+// scal layout (kScal per system): 0 mu = sum q z, 1 Q = sum q, 2 sum q^2,
 // 3 muM (image dipole of Theorem 3.3), 4 F_ibc,z / q_i, 5 offset of the
-// IBC potential, 6 dmuM/dgamma_top, 7 dmuM/dgamma_bot
+// IBC potential, 6 dmuM/dgamma_top, 7 dmuM/dgamma_bot, 8 S2 = sum q z^2;
+// with surface charges (zero otherwise): F_z / q_i gains 10 + 9 z, the
+// potential dE/dq_i gains 11 + 12 z + 13 z^2, the energy 14, and
+// dE/dgamma_{top,bot} 15, 16
 struct ScalArgs {
     const double *bpart;
     const SysDesc *sys;
@@ -135,15 +137,15 @@ struct ScalArgs {
 // (fixed summation order: the same in both launches that use it)
 __device__ void ibc_scalars(const ScalArgs &a, int r, int lane) {
     const SysDesc &d = a.sys[r];
-    double v[3] = {0, 0, 0};
+    double v[4] = {0, 0, 0, 0};
     for (int b = a.lay.bbase[r] + lane; b < a.lay.bbase[r + 1]; b += 64)
-        for (int c = 0; c < 3; c++) v[c] += a.bpart[4 * b + c];
-    for (int c = 0; c < 3; c++) v[c] = wave_sum(v[c]);
+        for (int c = 0; c < 4; c++) v[c] += a.bpart[4 * b + c];
+    for (int c = 0; c < 4; c++) v[c] = wave_sum(v[c]);
     if (lane == 0) {
-        const double mu = v[0], Q = v[1];
+        const double mu = v[0], Q = v[1], S2 = v[3];
         const double muM = d.g1 * mu + d.cgam * Q;
         const double tv = 2.0 * kPi / d.V * d.pref;
-        double *o = a.scal + 8 * r;
+        double *o = a.scal + kScal * r;
         o[0] = mu;
         o[1] = Q;
         o[2] = v[2];
@@ -152,6 +154,22 @@ __device__ void ibc_scalars(const ScalArgs &a, int r, int lane) {
         o[5] = tv * mu * d.cgam;
         o[6] = d.dg1t * mu + d.dcgt * Q;
         o[7] = d.dg1b * mu + d.dcgb * Q;
+        o[8] = S2;
+        for (int c = 9; c < kScal; c++) o[c] = 0.0;
+        if (d.surf) {
+            // sheets: phi_s = -Es z + Cs; net charge: U_Q = -(tv / 2) Q (2 Gs S2 + 2 A1 mu + A0 Q)
+            const double pe = d.pref;
+            o[9] = 2.0 * tv * Q * d.Gs[0];
+            o[10] = pe * d.Es[0] + tv * Q * d.A1[0];
+            o[11] = pe * d.Cs[0] - tv * (d.Gs[0] * S2 + d.A1[0] * mu + d.A0[0] * Q);
+            o[12] = -pe * d.Es[0] - tv * Q * d.A1[0];
+            o[13] = -tv * Q * d.Gs[0];
+            for (int k = 0; k < 3; k++) {
+                const double e = -0.5 * tv * Q * (2.0 * d.Gs[k] * S2 + 2.0 * d.A1[k] * mu + d.A0[k] * Q) +
+                                 pe * (-d.Es[k] * mu + d.Cs[k] * Q);
+                o[k == 0 ? 14 : 14 + k] = e;
+            }
+        }
     }
 }
 
@@ -536,7 +554,7 @@ struct ForceArgs {
 __device__ __forceinline__ void finish_particle(const ForceArgs &a, int r, int64_t g, double fx,
                                                 double fy, double fz, double pot) {
     const SysDesc &d = a.sys[r];
-    const double *sc = a.scal + 8 * r;
+    const double *sc = a.scal + kScal * r;
     const double qi = a.q[g];
     if (a.want_var) {
         // pot carries sum_l |t_l|^2 / q_i^2: (P sum |t|^2 - |F|^2) / (P - 1)
@@ -550,8 +568,15 @@ __device__ __forceinline__ void finish_particle(const ForceArgs &a, int r, int64
         ph = pot - 2.0 * d.alpha * d.pref / sqrt(kPi) * qi;   // + dE_self/dq_i
     }
     if (a.do_ibc) {
-        Fz += qi * sc[4];
-        ph += -sc[4] * a.pos[3 * g + 2] + sc[5];
+        if (d.surf) {
+            // IBC with the surface terms: linear (and quadratic) in z
+            const double z = a.pos[3 * g + 2];
+            Fz += qi * (sc[4] + sc[10] + sc[9] * z);
+            ph += -sc[4] * z + sc[5] + sc[11] + z * (sc[12] + sc[13] * z);
+        } else {
+            Fz += qi * sc[4];
+            ph += -sc[4] * a.pos[3 * g + 2] + sc[5];
+        }
     }
     if (a.add_real) {
         const double4 rr = a.freal[g];

@@ -48,12 +48,12 @@ __global__ __launch_bounds__(kBlock) void k_energy(EnergyArgs a) {
         drt = block_sum(drt, sh); drb = block_sum(drb, sh);
     }
     if (threadIdx.x != 0) return;
-    const double *sc = a.scal + 8 * r;
+    const double *sc = a.scal + kScal * r;
     const double tv = 2.0 * kPi / d.V * d.pref;
     const double Er = has_real ? 0.5 * er : 0.0;
     const double Ek = a.do_k ? ek : 0.0;
     const double Es = a.do_k ? -d.alpha * d.pref / sqrt(kPi) * sc[2] : 0.0;
-    const double Ei = a.do_ibc ? tv * sc[0] * sc[3] : 0.0;
+    const double Ei = a.do_ibc ? tv * sc[0] * sc[3] + sc[14] : 0.0;   // sc[14]: surface terms (or 0)
     if (a.energy) {
         double *o = a.energy + 5 * r;
         o[0] = Er + Ek + Es + Ei;
@@ -64,8 +64,8 @@ __global__ __launch_bounds__(kBlock) void k_energy(EnergyArgs a) {
     }
     if (a.want_dg && a.dEdgamma) {
         const double g = a.gE ? a.gE[r] : 1.0;
-        const double ibt = a.do_ibc ? tv * sc[0] * sc[6] : 0.0;
-        const double ibb = a.do_ibc ? tv * sc[0] * sc[7] : 0.0;
+        const double ibt = a.do_ibc ? tv * sc[0] * sc[6] + sc[15] : 0.0;
+        const double ibb = a.do_ibc ? tv * sc[0] * sc[7] + sc[16] : 0.0;
         a.dEdgamma[2 * r] = g * ((has_real ? 0.5 * drt : 0.0) + (a.do_k ? dkt : 0.0) + ibt);
         a.dEdgamma[2 * r + 1] = g * ((has_real ? 0.5 * drb : 0.0) + (a.do_k ? dkb : 0.0) + ibb);
     }

@@ -68,7 +68,19 @@ struct SysDesc {
     int iso;
     float u2, rc2q, near2q;                    // iso: ux^2, r_c^2 / ux^2, near^2 / ux^2
     double ud;                                 // iso: ux in FP64
+    // surface charges on the interfaces (surf = 1 when either is nonzero):
+    // the sheets' uniform field Es and potential offset Cs in the slab
+    // (phi_s(z) = -Es z + Cs), and the image sums of the net-charge term,
+    // Gs = sum_w w, A1 = sum_w w s_w c_w, A0 = sum_w w c_w^2 over the real
+    // charge and its images z_w = s_w z + c_w; each with its derivatives by
+    // gamma_top, gamma_bot ([1], [2])
+    double sig_top, sig_bot;
+    double Es[3], Cs[3], Gs[3], A1[3], A0[3];
+    int surf;
 };
+
+// Per-system scalars of the IBC and surface terms (kspace.hip: ibc_scalars)
+constexpr int kScal = 20;
 
 // Per-k record written by the reduce/assemble kernel (FP64):
 //   [0..2] kx, ky, kz      [3..6] c*A (re, im), c*B (re, im)
@@ -105,8 +117,8 @@ struct Workspace {
     // particles (k-space arrays padded per system to whole tiles)
     float4 *p32 = nullptr;      // 2 per particle: (fxh, fxl, fyh, fyl), (fzh, fzl, q, 0)
     double4 *p64 = nullptr;     // 1 per particle: (fx, fy, fz, q)
-    double *bpart = nullptr;    // per particle block: sum q z, sum q, sum q^2, 0
-    double *scal = nullptr;     // 8 scalars per system, see kspace.hip
+    double *bpart = nullptr;    // per particle block: sum q z, sum q, sum q^2, sum q z^2
+    double *scal = nullptr;     // kScal scalars per system, see kspace.hip
     // k-space (P_pad k-vectors per system)
     int32_t *kset = nullptr;    // n_sys x P x 3
     float4 *kn32 = nullptr;     // per k: (nx, ny, nz, 0) as floats

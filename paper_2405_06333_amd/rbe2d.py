@@ -26,7 +26,7 @@ EXPORTS = ("rbe2d_create", "rbe2d_destroy", "rbe2d_query", "rbe2d_draw_kset", "r
            "rbe2d_check", "rbe2d_last_error", "rbe2d_batch_create", "rbe2d_query_system",
            "rbe2d_batch_forces", "rbe2d_batch_md_run", "rbe2d_autotune", "rbe2d_short_forces",
            "rbe2d_md_run_ex", "rbe2d_suggest_params", "rbe2d_force_variance", "rbe2d_profile_classes",
-           "rbe2d_forces_noalloc")
+           "rbe2d_forces_noalloc", "rbe2d_set_surface_charges")
 PROF_SLOTS = ("prep", "sf_pass", "assemble", "cell_build", "real_pairs", "force_scatter", "energy",
               "integrator", "ksample", "short_range", "add_real")
 
@@ -100,6 +100,7 @@ def lib():
         L.rbe2d_profile_read.argtypes = [_vp, _vp, _vp, ctypes.c_int32]
         L.rbe2d_forces_noalloc.argtypes = [ctypes.POINTER(Params), _vp, ctypes.c_int64, _vp, _vp, _vp, _vp,
                                            ctypes.c_uint32, _vp, _vp]
+        L.rbe2d_set_surface_charges.argtypes = [_vp, ctypes.c_int32, ctypes.c_double, ctypes.c_double]
         L.rbe2d_check.argtypes = [_vp, _vp]
         L.rbe2d_last_error.argtypes = [_vp]
         L.rbe2d_last_error.restype = ctypes.c_char_p
@@ -367,6 +368,11 @@ class Slab:
         self._ok(lib().rbe2d_profile_read(self._h, ctypes.c_void_p(ms.ctypes.data),
                                           ctypes.c_void_p(cnt.ctypes.data), n))
         return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(PROF_SLOTS)}
+
+    def set_surface_charges(self, sigma_top, sigma_bot, sys=-1):
+        """Surface charge densities on z = H and z = 0 (of system `sys`, or of
+        every system); see rbe2d_set_surface_charges."""
+        self._ok(lib().rbe2d_set_surface_charges(self._h, int(sys), float(sigma_top), float(sigma_bot)))
 
     def check(self):
         self._ok(lib().rbe2d_check(self._h, _stream()))
