@@ -90,10 +90,10 @@ BREAKDOWN_STEPS = 5   # profiled steps for the per-kernel breakdown, before the 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=100, help="timed MD steps (the workload's run is 100 steps)")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
-    ap.add_argument("--fp64-steps", type=int, default=3, help="steps of the plain FP64 path (0 = skip)")
+    ap.add_argument("--fp64-steps", type=int, default=20, help="steps of the plain FP64 path (0 = skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=20000, help="particles in the oracle's rho sample")
     ap.add_argument("--cpu-targets", type=int, default=32, help="oracle force targets")

@@ -575,7 +575,9 @@ void k_real(RealArgs a) {
         // on either side of the target's (one long where the other is short)
         // evens out the lanes' trip counts.  A lone run is B empty.  Loads are
         // issued U at a time, double-buffered: the next U records are in
-        // flight while these are tested (and while a drain runs).
+        // flight while these are tested (and while a drain runs); the two
+        // buffers swap roles every batch (the loop body is unrolled by two),
+        // so no records are copied between them.
         auto scan32 = [&](int jbA, int lenA, double xtA, double ytA, int jbB, int lenB, double xtB, double ytB) {
             if constexpr (FP32) {
                 const int c4a = (lenA + U - 1) / U * U;
@@ -591,19 +593,7 @@ void k_real(RealArgs a) {
                 // each to FP32; exact FP64 geometry for pairs within `near`
                 const float rc2s = ISO ? d.rc2q : d.rc2f;
                 const float near2s = ISO ? d.near2q : d.near2f;
-                uint4 sv[U];
-                {
-                    const uint4 *pq = a.src16 + rec(0);
-#pragma unroll
-                    for (int k = 0; k < U; k++) sv[k] = pq[k];
-                }
-                for (int m0 = 0; m0 < maxtot; m0 += U) {
-                    uint4 nx[U];
-                    if (m0 + U < maxtot) {
-                        const uint4 *pq = a.src16 + rec(m0 + U);
-#pragma unroll
-                        for (int k = 0; k < U; k++) nx[k] = pq[k];
-                    }
+                auto body = [&](const uint4 (&sv)[U], int m0) {
                     if (qu.full()) qu.drain();
                     const bool inA = m0 < c4a;
                     const int lim = inA ? lenA : tot;          // candidates m < lim
@@ -631,8 +621,27 @@ void k_real(RealArgs a) {
                         }
                         qu.push(acc, dx, dy, dz, __uint_as_float(sv[k].w));
                     }
+                };
+                uint4 sa[U], sb[U];
+                {
+                    const uint4 *pq = a.src16 + rec(0);
 #pragma unroll
-                    for (int k = 0; k < U; k++) sv[k] = nx[k];
+                    for (int k = 0; k < U; k++) sa[k] = pq[k];
+                }
+                for (int m0 = 0; m0 < maxtot; m0 += 2 * U) {
+                    if (m0 + U < maxtot) {
+                        const uint4 *pq = a.src16 + rec(m0 + U);
+#pragma unroll
+                        for (int k = 0; k < U; k++) sb[k] = pq[k];
+                    }
+                    body(sa, m0);
+                    if (m0 + U >= maxtot) break;
+                    if (m0 + 2 * U < maxtot) {
+                        const uint4 *pq = a.src16 + rec(m0 + 2 * U);
+#pragma unroll
+                        for (int k = 0; k < U; k++) sa[k] = pq[k];
+                    }
+                    body(sb, m0 + U);
                 }
             }
         };
