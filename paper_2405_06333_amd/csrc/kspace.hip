@@ -405,6 +405,15 @@ __device__ __forceinline__ double dmono(int e_self, double g_self, int e_other, 
     return r;
 }
 
+// a double held by lane `src`, read by every lane
+__device__ __forceinline__ double lane_value(double v, int src) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), src),
+                            __builtin_amdgcn_readlane(__double2loint(v), src));
+}
+
+// One wave per (system, k).  DG: also the gamma derivatives of Y_odd and
+// Y_even (for dE/dgamma; zero otherwise).
+template <bool DG>
 __global__ __launch_bounds__(64) void k_assemble(AssembleArgs a) {
     if ((int)blockIdx.x >= a.n_sys * a.P) {
         ibc_scalars(a.sc, blockIdx.x - a.n_sys * a.P, threadIdx.x);
@@ -414,40 +423,50 @@ __global__ __launch_bounds__(64) void k_assemble(AssembleArgs a) {
     const SysDesc &d = a.sys[r];
     const ImgTable &it = a.img[r];
     const int lane = threadIdx.x;
-    double s[4] = {0, 0, 0, 0};
+    // v[0..3]: this lane's share of rho and rhohat (lanes split the tiles);
+    // v[4..7]: Yo, Ye; v[8..15]: dYo/dg_top, dYe/dg_top, dYo/dg_bot,
+    // dYe/dg_bot (lanes split the image orders o = lane+1, lane+65, ...)
+    constexpr int NV = DG ? 16 : 8;
+    double v[NV];
+#pragma unroll
+    for (int c = 0; c < NV; c++) v[c] = 0.0;
     for (int t = a.tbase[r] + lane; t < a.tbase[r + 1]; t += 64) {
         const int64_t o = ((int64_t)t * a.P_pad + l) * 4;
-        for (int c = 0; c < 4; c++) s[c] += a.part[o + c];
+        for (int c = 0; c < 4; c++) v[c] += a.part[o + c];
     }
-    for (int c = 0; c < 4; c++) s[c] = wave_sum(s[c]);
-    // Y_odd, Y_even and their gamma derivatives; lane handles order o = lane+1, lane+65, ...
     const int64_t kg = (int64_t)r * a.P + l;
     const int nx = a.kset[3 * kg], ny = a.kset[3 * kg + 1], nz = a.kset[3 * kg + 2];
     const double rev_per_H = (double)nz * d.H / d.Lz;   // kz H / (2 pi)
-    double y[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};  // Yo, Ye, dYo/dt, dYe/dt, dYo/db, dYe/db
     for (int o = lane + 1; o <= d.M; o += 64) {
         const double gpl = it.gp[o - 1], gml = it.gm[o - 1];
         double mp, mm;   // multiples of kz H in the exponents of the + and - terms
         int slot;
-        if (o & 1) { mp = (double)(o + 1); mm = -(double)(o - 1); slot = 0; }
-        else       { mp = (double)o;       mm = -(double)o;       slot = 2; }
+        if (o & 1) { mp = (double)(o + 1); mm = -(double)(o - 1); slot = 4; }
+        else       { mp = (double)o;       mm = -(double)o;       slot = 6; }
         double sp, cp, sm, cm;
         sincos_rev64(mp * rev_per_H, &sp, &cp);
         sincos_rev64(mm * rev_per_H, &sm, &cm);
-        y[slot] += gpl * cp + gml * cm;
-        y[slot + 1] += gpl * sp + gml * sm;
-        const double dpt = dmono(it.ea_p[o - 1], d.g_top, it.eb_p[o - 1], d.g_bot);
-        const double dmt = dmono(it.ea_m[o - 1], d.g_top, it.eb_m[o - 1], d.g_bot);
-        const double dpb = dmono(it.eb_p[o - 1], d.g_bot, it.ea_p[o - 1], d.g_top);
-        const double dmb = dmono(it.eb_m[o - 1], d.g_bot, it.ea_m[o - 1], d.g_top);
-        y[4 + slot] += dpt * cp + dmt * cm;
-        y[5 + slot] += dpt * sp + dmt * sm;
-        y[8 + slot] += dpb * cp + dmb * cm;
-        y[9 + slot] += dpb * sp + dmb * sm;
+        v[slot] += gpl * cp + gml * cm;
+        v[slot + 1] += gpl * sp + gml * sm;
+        if constexpr (DG) {
+            const double dpt = dmono(it.ea_p[o - 1], d.g_top, it.eb_p[o - 1], d.g_bot);
+            const double dmt = dmono(it.ea_m[o - 1], d.g_top, it.eb_m[o - 1], d.g_bot);
+            const double dpb = dmono(it.eb_p[o - 1], d.g_bot, it.ea_p[o - 1], d.g_top);
+            const double dmb = dmono(it.eb_m[o - 1], d.g_bot, it.ea_m[o - 1], d.g_top);
+            v[4 + slot] += dpt * cp + dmt * cm;
+            v[5 + slot] += dpt * sp + dmt * sm;
+            v[8 + slot] += dpb * cp + dmb * cm;
+            v[9 + slot] += dpb * sp + dmb * sm;
+        }
     }
-    for (int c = 0; c < 12; c++) y[c] = wave_sum(y[c]);
-    if (lane != 0) return;
-    const double rr = s[0], ri = s[1], hr = s[2], hi = s[3];
+    // the NV wave sums at once (fixed-order butterfly): lane c then holds
+    // the sum of value c, which every lane reads
+    wave_transpose_reduce<NV>(v, lane);
+    double S[NV];
+#pragma unroll
+    for (int c = 0; c < NV; c++) S[c] = lane_value(v[0], c);
+    const double rr = S[0], ri = S[1], hr = S[2], hi = S[3];
+    const double *y = S + 4;   // Yo, Ye (re, im), then the derivatives
     const double kx = 2.0 * kPi * nx / d.Lx, ky = 2.0 * kPi * ny / d.Ly, kz = 2.0 * kPi * nz / d.Lz;
     const double k2 = kx * kx + ky * ky + kz * kz;
     const double c = d.cfac / k2;
@@ -460,14 +479,28 @@ __global__ __launch_bounds__(64) void k_assemble(AssembleArgs a) {
     const double Ai = mi + er * ri - ei * rr;
     const double Br = y[0] * rr + y[1] * ri;
     const double Bi = y[0] * ri - y[1] * rr;
+    // polar form for the force passes, Im(e^{-i ph} cA) = |cA| sin(arg cA - ph):
+    // lane 1 for A, lane 2 for B, in parallel
+    constexpr double inv2pi = 0.15915494309189535;
+    double mag = 0.0, arg = 0.0;
+    if (lane == 1 || lane == 2) {
+        const double xr = lane == 1 ? Ar : Br, xi = lane == 1 ? Ai : Bi;
+        mag = c * hypot(xr, xi);
+        arg = atan2(xi, xr) * inv2pi;
+    }
+    const double magA = lane_value(mag, 1), argA = lane_value(arg, 1);
+    const double magB = lane_value(mag, 2), argB = lane_value(arg, 2);
+    if (lane != 0) return;
     const double e = c * (rr * mr + ri * mi);
     // d e / d gamma = c Re(rho conj(dYe rho + dYo rhohat))
-    double de[2];
-    for (int w = 0; w < 2; w++) {
-        const double *dy = y + 4 + 4 * w;
-        const double tr = dy[2] * rr - dy[3] * ri + dy[0] * hr - dy[1] * hi;
-        const double ti = dy[2] * ri + dy[3] * rr + dy[0] * hi + dy[1] * hr;
-        de[w] = c * (rr * tr + ri * ti);
+    double de[2] = {0.0, 0.0};
+    if constexpr (DG) {
+        for (int w = 0; w < 2; w++) {
+            const double *dy = y + 4 + 4 * w;
+            const double tr = dy[2] * rr - dy[3] * ri + dy[0] * hr - dy[1] * hi;
+            const double ti = dy[2] * ri + dy[3] * rr + dy[0] * hi + dy[1] * hr;
+            de[w] = c * (rr * tr + ri * ti);
+        }
     }
     double *rec = a.krec + kg * kKRec;
     rec[0] = kx; rec[1] = ky; rec[2] = kz;
@@ -475,13 +508,10 @@ __global__ __launch_bounds__(64) void k_assemble(AssembleArgs a) {
     rec[7] = e; rec[8] = de[0]; rec[9] = de[1];
     rec[10] = nx; rec[11] = ny; rec[12] = nz;
     rec[13] = rr; rec[14] = ri; rec[15] = kx * kx + ky * ky;
-    // polar form for the force passes: Im(e^{-i ph} cA) = |cA| sin(arg cA - ph)
-    constexpr double inv2pi = 0.15915494309189535;
-    rec[16] = c * hypot(Ar, Ai); rec[17] = atan2(Ai, Ar) * inv2pi;
-    rec[18] = c * hypot(Br, Bi); rec[19] = atan2(Bi, Br) * inv2pi;
+    rec[16] = magA; rec[17] = argA; rec[18] = magB; rec[19] = argB;
     a.kf32[3 * kg] = make_float4((float)kx, (float)ky, (float)kz, (float)(kx * kx + ky * ky));
     a.kf32[3 * kg + 1] = make_float4((float)(c * Ar), (float)(c * Ai), (float)(c * Br), (float)(c * Bi));
-    a.kf32[3 * kg + 2] = make_float4((float)rec[16], (float)rec[17], (float)rec[18], (float)rec[19]);
+    a.kf32[3 * kg + 2] = make_float4((float)magA, (float)argA, (float)magB, (float)argB);
 }
 
 int choose_tile(int64_t N, int n_kchunks) {
@@ -496,7 +526,7 @@ int choose_tile(int64_t N, int n_kchunks) {
     return per;
 }
 
-hipError_t launch_kcoef_sf(rbe2d_ctx *h, hipStream_t s, bool with_scalars) {
+hipError_t launch_kcoef_sf(rbe2d_ctx *h, hipStream_t s, bool with_scalars, bool want_dg) {
     const bool fp32 = h->precision == RBE2D_PREC_FP32_PHASE;
     prof_begin(h, 1, s);
     if (h->n_tiles > 0) {
@@ -518,7 +548,9 @@ hipError_t launch_kcoef_sf(rbe2d_ctx *h, hipStream_t s, bool with_scalars) {
     a.krec = h->w.krec; a.kf32 = h->w.kf32;
     a.n_sys = h->n_sys; a.with_scalars = with_scalars; a.sc = scal_args(h);
     prof_begin(h, 2, s);
-    hipLaunchKernelGGL(k_assemble, dim3(h->n_sys * h->P + (with_scalars ? h->n_sys : 0)), dim3(64), 0, s, a);
+    const dim3 ga(h->n_sys * h->P + (with_scalars ? h->n_sys : 0));
+    if (want_dg) hipLaunchKernelGGL(k_assemble<true>, ga, dim3(64), 0, s, a);
+    else hipLaunchKernelGGL(k_assemble<false>, ga, dim3(64), 0, s, a);
     prof_end(h, 2, s);
     return hipGetLastError();
 }

@@ -237,7 +237,8 @@ namespace rbe2d {
 hipError_t launch_prep(rbe2d_ctx *h, const double *pos, const double *q, hipStream_t s, bool scalars = true);
 // structure factors and per-k assembly; with_scalars: the assembly launch
 // also computes the IBC scalars (otherwise the prep launch does)
-hipError_t launch_kcoef_sf(rbe2d_ctx *h, hipStream_t s, bool with_scalars = false);
+// want_dg: also the per-k gamma derivatives of the energy (for dE/dgamma)
+hipError_t launch_kcoef_sf(rbe2d_ctx *h, hipStream_t s, bool with_scalars = false, bool want_dg = false);
 // k-vector tables of the current k-set (kn32, kn64)
 void launch_ktable(rbe2d_ctx *h, hipStream_t s);
 hipError_t launch_kforce(rbe2d_ctx *h, const double *pos, const double *q, double *F, double *dEdq,
