@@ -15,6 +15,7 @@ replicas) and the differentiable energy (forward + adjoint), each next to
 the plain single-system FP64 path on the same GPU.
 """
 import argparse
+import subprocess
 import json
 import math
 import os
@@ -103,6 +104,8 @@ def parse():
                     help="only time this many force calls of each half alone (for counter runs)")
     ap.add_argument("--batch-only", type=int, default=0,
                     help="only run this many steps of the 64-replica batch (for kernel traces and counters)")
+    ap.add_argument("--cpu-only", action="store_true",
+                    help="only time the CPU oracle on its sample (prints one JSON object; no GPU)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (HBM counter calibration)")
     return ap.parse_args()
@@ -453,6 +456,24 @@ def main():
     if a.gpus != 1:
         print(f"bench.py: runs on one GPU only (the kernels work on one GPU's share); --gpus {a.gpus} is not supported", file=sys.stderr)
         return 2
+    if a.cpu_only:
+        from paper_2405_06333_amd import inputs as _inputs
+        print(json.dumps(cpu_baseline(_inputs.LARGE_MD, a.cpu_sample, a.cpu_targets)), flush=True)
+        return 0
+    # the single-threaded oracle figure, in a child process started before
+    # this one touches the GPU: an eighth of the rho sample and a sixteenth
+    # of the targets (about 25 s) at OMP_NUM_THREADS=1
+    single = None
+    if not (a.no_cpu_baseline or a.parts_only or a.batch_only or a.copy_mib):
+        env = dict(os.environ, OMP_NUM_THREADS="1")
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-only",
+                            "--cpu-sample", str(max(1000, a.cpu_sample // 8)),
+                            "--cpu-targets", str(max(2, a.cpu_targets // 16))],
+                           env=env, capture_output=True, text=True, timeout=600)
+        if r.returncode == 0 and r.stdout.strip():
+            single = json.loads(r.stdout.strip().splitlines()[-1])
+        else:
+            print(f"bench.py: single-threaded oracle run failed: {r.stderr[-400:]}", file=sys.stderr)
     import torch
     if a.copy_mib:
         copy_probe(torch, a.copy_mib)
@@ -548,6 +569,9 @@ def main():
         batch = run_batch(R, torch, a.side_steps, autotune=not a.no_autotune)
         grad = run_grad(R, torch, a.side_steps, autotune=not a.no_autotune)
     cpu = None if a.no_cpu_baseline else cpu_baseline(w, a.cpu_sample, a.cpu_targets)
+    if cpu is not None and single is not None:
+        cpu["single_thread"] = {"value": single["value"], "unit": single["unit"], "cores": single["cores"],
+                                "sample": single["sample"]}
     out = {
         "metric": METRIC,
         "value": value,
