@@ -13,7 +13,9 @@ namespace rbe2d {
 __device__ __forceinline__ void sincos_rev64(double r, double *s_out, double *c_out) {
     const double qd = rint(4.0 * r);
     const double f = fma(-0.25, qd, r);
-    const int qi = (int)(((long long)qd) & 3);
+    // quarter turns mod 4 (|4 r| < 2^31 for every phase of the method; the
+    // two's-complement low bits are the residue for negative counts too)
+    const int qi = (int)qd;
     const double t = f * (2.0 * kPi);
     const double t2 = t * t;
     double ps = -1.0 / 1307674368000.0;           // -1/15!
@@ -33,11 +35,14 @@ __device__ __forceinline__ void sincos_rev64(double r, double *s_out, double *c_
     pc = fma(pc, t2, 1.0 / 24.0);                 // 1/4!
     pc = fma(pc, t2, -0.5);
     const double cs = fma(t2, pc, 1.0);
+    // rotate by qi quarter turns: swap for odd qi, then flip the sign bits
+    // (sin for qi = 2, 3; cos for qi = 1, 2 mod 4)
     const bool swap = qi & 1;
     const double s0 = swap ? cs : sn;
     const double c0 = swap ? sn : cs;
-    *s_out = (qi & 2) ? -s0 : s0;
-    *c_out = ((qi + 1) & 2) ? -c0 : c0;
+    const int ssign = (qi & 2) << 30, csign = ((qi + 1) & 2) << 30;
+    *s_out = __hiloint2double(__double2hiint(s0) ^ ssign, __double2loint(s0));
+    *c_out = __hiloint2double(__double2hiint(c0) ^ csign, __double2loint(c0));
 }
 
 // sin of 2 pi r alone: r is reduced to the nearest half turn (exact, as
@@ -60,7 +65,9 @@ __device__ __forceinline__ double sin_rev64(double r) {
     p = fma(p, t2, 1.0 / 120.0);                   // 1/5!
     p = fma(p, t2, -1.0 / 6.0);                    // -1/3!
     const double s = fma(t * t2, p, t);
-    return (((long long)kd) & 1) ? -s : s;
+    // an odd half turn flips the sign bit (|2 r| < 2^31, as above)
+    const int sign = ((int)kd & 1) << 31;
+    return __hiloint2double(__double2hiint(s) ^ sign, __double2loint(s));
 }
 
 // x += dt v, then x, y wrapped into the box and z folded into [zlo, zhi]:
