@@ -263,17 +263,28 @@ __device__ __forceinline__ void pair_terms(float r2, const PairConst32 &c, float
     *fs = fmaf(c.c2a, e, v) * (rinv * rinv);
 }
 // FP64: erfc(x) = exp(-x^2) erfcx(x) with the fitted erfcx (relative error
-// below 2e-13), sharing the exponential of the force term; for x beyond the
-// fitted range erfc(x) < 1.2e-29 and the term is dropped.
+// below 2e-11), sharing the exponential of the force term; for x beyond the
+// fitted range erfc(x) < 1.2e-29 and the term is dropped.  1/sqrt(r^2) and
+// 1/(1 + p x) are the hardware estimates refined by two Newton steps each
+// (relative error near 1e-16; r^2 > 0 for every accepted pair).
 // The coefficients are read from LDS (`coef`, a copy of rbe2d_erfcx64_a): as
-// FP64 literals they would hold 32 registers for the whole kernel.
+// FP64 literals they would hold 24 registers for the whole kernel.
 __device__ __forceinline__ void pair_terms(double r2, double alpha, double c2a, double *ec, double *fs,
                                            const double *coef) {
-    const double d = sqrt(r2);
-    const double rinv2 = 1.0 / r2;
+    double y = __builtin_amdgcn_rsq(r2);
+#pragma unroll
+    for (int it = 0; it < 2; it++) {
+        const double en = fma(-r2 * y, y, 1.0);     // 1 - r^2 y^2
+        y = fma(0.5 * y, en, y);
+    }
+    const double d = r2 * y;
+    const double rinv2 = y * y;
     const double e = exp(-alpha * alpha * r2);
     const double x = alpha * d;
-    const double t = 1.0 / fma(RBE2D_ERFCX64_P, x, 1.0);
+    const double a1 = fma(RBE2D_ERFCX64_P, x, 1.0);
+    double t = __builtin_amdgcn_rcp(a1);
+#pragma unroll
+    for (int it = 0; it < 2; it++) t = fma(t, fma(-a1, t, 1.0), t);
     double p = coef[RBE2D_ERFCX64_DEG - 1];
 #pragma unroll
     for (int k = RBE2D_ERFCX64_DEG - 2; k >= 0; k--) p = fma(p, t, coef[k]);
