@@ -97,7 +97,8 @@ def parse():
     ap.add_argument("--fp64-steps", type=int, default=20, help="steps of the plain FP64 path (0 = skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=20000, help="particles in the oracle's rho sample")
-    ap.add_argument("--cpu-targets", type=int, default=32, help="oracle force targets")
+    ap.add_argument("--cpu-targets", type=int, default=256,
+                    help="oracle real-space targets (the oracle parallelises over targets in chunks of 16)")
     ap.add_argument("--side-steps", type=int, default=10, help="steps of each side measurement (0 = skip)")
     ap.add_argument("--no-autotune", action="store_true", help="use the built-in launch heuristics")
     ap.add_argument("--parts-only", type=int, default=0,
@@ -416,9 +417,12 @@ def copy_probe(torch, mib):
 
 
 def cpu_baseline(w, n_sample, n_targets):
-    """The CPU oracle on a bounded sample of the workload: rho over n_sample
-    particles and the full force (k-space + real space + IBC) on n_targets
-    particles of the N-particle system; scaled to one full step."""
+    """The CPU oracle on a bounded sample of the workload, scaled to one full
+    step: its k-space pass (rho over the particles, then the force on each,
+    both linear in the particle count) timed on n_sample particles, and its
+    real-space sum (every real charge and image within r_c of the target,
+    linear in the number of targets) timed for n_targets particles of the
+    whole N-particle system."""
     from oracle import oracle as orc
     from paper_2405_06333_amd import inputs
     pos, q = inputs.sample(w)
@@ -429,24 +433,21 @@ def cpu_baseline(w, n_sample, n_targets):
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     sub = slice(0, n_sample)
     t0 = time.perf_counter()
-    orc.kspace(o, pos[sub], q[sub], n, c, targets=np.zeros(0, dtype=np.int64))
-    t_rho = time.perf_counter() - t0
+    orc.kspace(o, pos[sub], q[sub], n, c)
+    t_k = time.perf_counter() - t0
     rng = np.random.default_rng(5)
     tg = np.sort(rng.choice(w.N, n_targets, replace=False))
     t0 = time.perf_counter()
-    orc.evaluate(o, pos, q, n, c, targets=tg)
-    t_full_targets = time.perf_counter() - t0
-    # the targets run also recomputed rho over all N once: remove that share
-    t_rho_all = t_rho * w.N / n_sample
-    t_per_target = max(t_full_targets - t_rho_all, 0.0) / n_targets
-    t_step = t_rho_all + t_per_target * w.N
+    orc.real_space(o, pos, q, targets=tg)
+    t_r = time.perf_counter() - t0
+    t_step = t_k * w.N / n_sample + t_r * w.N / n_targets
     return {
         "value": w.N / t_step,
         "unit": "particle-steps/s",
         "cores": threads,
         "kind": "oracle",
-        "sample": (f"oracle rho(k) over {n_sample} of the {w.N} particles ({t_rho:.2f} s) and full "
-                   f"forces on {n_targets} sampled particles of the whole system ({t_full_targets:.2f} s), "
+        "sample": (f"oracle k-space (rho and forces) over {n_sample} of the {w.N} particles ({t_k:.2f} s) "
+                   f"and real space for {n_targets} sampled particles of the whole system ({t_r:.2f} s), "
                    f"scaled to one step of all {w.N} particles ({t_step:.3g} s/step)"),
     }
 
@@ -461,14 +462,14 @@ def main():
         print(json.dumps(cpu_baseline(_inputs.LARGE_MD, a.cpu_sample, a.cpu_targets)), flush=True)
         return 0
     # the single-threaded oracle figure, in a child process started before
-    # this one touches the GPU: an eighth of the rho sample and a sixteenth
-    # of the targets (about 25 s) at OMP_NUM_THREADS=1
+    # this one touches the GPU: an eighth of the k-space sample and four
+    # real-space targets at OMP_NUM_THREADS=1
     single = None
     if not (a.no_cpu_baseline or a.parts_only or a.batch_only or a.copy_mib):
         env = dict(os.environ, OMP_NUM_THREADS="1")
         r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-only",
                             "--cpu-sample", str(max(1000, a.cpu_sample // 8)),
-                            "--cpu-targets", str(max(2, a.cpu_targets // 16))],
+                            "--cpu-targets", str(max(2, a.cpu_targets // 64))],
                            env=env, capture_output=True, text=True, timeout=600)
         if r.returncode == 0 and r.stdout.strip():
             single = json.loads(r.stdout.strip().splitlines()[-1])
