@@ -139,6 +139,8 @@ rbe2d_status setup_system(const rbe2d_params *pin, SysHost &sh) {
     d.V = p.Lx * p.Ly * Lz;
     d.S = theta_axis(p.alpha, p.Lx) * theta_axis(p.alpha, p.Ly) * theta_axis(p.alpha, Lz) - 1.0;
     d.alpha = p.alpha; d.rc = p.r_c; d.rc2 = p.r_c * p.r_c; d.pref = p.coulomb_prefactor;
+    d.rc_lay = p.r_c + 1e-9 * p.r_c;   // the margin covers the division that assigned the layers
+    d.H_rc = p.H + p.r_c;
     d.g_top = p.gamma_top; d.g_bot = p.gamma_bot; d.M = p.M;
     d.cfac = 2.0 * kPi * d.S * d.pref / (d.V * p.P);
 

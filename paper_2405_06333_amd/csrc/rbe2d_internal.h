@@ -54,6 +54,7 @@ struct SysDesc {
     double cfac;                               // 2 pi S pref / (V P)
     double scale_h;                            // 2^fh_bits (FP32 phase split)
     double hx, hy, hz, inv_hx, inv_hy, inv_hz;  // cell sizes
+    double rc_lay, H_rc;                       // r_c (1 + 1e-9): layer ranges; H + r_c: image families in reach
     double inv_Lx, inv_Ly, inv_Lz;
     int ncx, ncy, ncz, reach, reach_y, nfam, M, fh_bits, cbase;
     int nmax[3], cdf_off[3];                   // sampler tables in the shared CDF array

@@ -557,7 +557,6 @@ void k_real(RealArgs a) {
     const float hxf = (float)d.hx, inv_hyf = (float)d.inv_hy;
     const float rcm2 = (float)(d.rc2 * (1.0 + 1e-4));
     const float rmarg = (float)(1e-5 * d.rc);
-    const double rmarg64 = 1e-9 * d.rc;             // layer range (cells assigned by division)
     Queue qu = [&]() {
         if constexpr (FP32) return Queue(lds, tid, d);
         else return make_wave_queue<kWaveQ, U, WANT_DG>(lds, tid, coef64, d.alpha);
@@ -569,13 +568,13 @@ void k_real(RealArgs a) {
             sz = fm.sz; czs = fm.cz; w = fm.w; zsign = fm.zsign; dwt = fm.dwt; dwb = fm.dwb;
         }
         const double tz = sz * me.z + czs;
-        const bool fam_on = active && tz > -d.rc && tz < d.H + d.rc;
+        const bool fam_on = active && tz > -d.rc && tz < d.H_rc;
         if (__ballot(fam_on) == 0) continue;
         const uint32_t tzf = fam_on ? to_fixed(tz + d.zoff, d.fzs) : 0u;
         int lzlo = d.ncz, lzhi = -1;
         if (fam_on) {
-            lzlo = max(0, (int)floor((tz - d.rc - rmarg64) * d.inv_hz));
-            lzhi = min(d.ncz - 1, (int)floor((tz + d.rc + rmarg64) * d.inv_hz));
+            lzlo = max(0, (int)floor((tz - d.rc_lay) * d.inv_hz));
+            lzhi = min(d.ncz - 1, (int)floor((tz + d.rc_lay) * d.inv_hz));
         }
         const int wzlo = wave_min(lzlo), wzhi = wave_max(lzhi);
         qu.family(w, zsign, dwt, dwb);
@@ -586,9 +585,9 @@ void k_real(RealArgs a) {
         // on either side of the target's (one long where the other is short)
         // evens out the lanes' trip counts.  A lone run is B empty.  Loads are
         // issued U at a time, double-buffered: the next U records are in
-        // flight while these are tested (and while a drain runs); the two
-        // buffers swap roles every batch (the loop body is unrolled by two),
-        // so no records are copied between them.
+        // flight while these are tested (and while a drain runs); without
+        // the gamma derivatives the two buffers swap roles every batch (the
+        // loop body is unrolled by two), so no records are copied between them.
         auto scan32 = [&](int jbA, int lenA, double xtA, double ytA, int jbB, int lenB, double xtB, double ytB) {
             if constexpr (FP32) {
                 const int c4a = (lenA + U - 1) / U * U;
@@ -639,20 +638,35 @@ void k_real(RealArgs a) {
 #pragma unroll
                     for (int k = 0; k < U; k++) sa[k] = pq[k];
                 }
-                for (int m0 = 0; m0 < maxtot; m0 += 2 * U) {
-                    if (m0 + U < maxtot) {
-                        const uint4 *pq = a.src16 + rec(m0 + U);
+                if constexpr (WANT_DG) {
+                    // the gamma-derivative sums hold more registers: one loop
+                    // body, the prefetched records copied into place
+                    for (int m0 = 0; m0 < maxtot; m0 += U) {
+                        if (m0 + U < maxtot) {
+                            const uint4 *pq = a.src16 + rec(m0 + U);
 #pragma unroll
-                        for (int k = 0; k < U; k++) sb[k] = pq[k];
-                    }
-                    body(sa, m0);
-                    if (m0 + U >= maxtot) break;
-                    if (m0 + 2 * U < maxtot) {
-                        const uint4 *pq = a.src16 + rec(m0 + 2 * U);
+                            for (int k = 0; k < U; k++) sb[k] = pq[k];
+                        }
+                        body(sa, m0);
 #pragma unroll
-                        for (int k = 0; k < U; k++) sa[k] = pq[k];
+                        for (int k = 0; k < U; k++) sa[k] = sb[k];
                     }
-                    body(sb, m0 + U);
+                } else {
+                    for (int m0 = 0; m0 < maxtot; m0 += 2 * U) {
+                        if (m0 + U < maxtot) {
+                            const uint4 *pq = a.src16 + rec(m0 + U);
+#pragma unroll
+                            for (int k = 0; k < U; k++) sb[k] = pq[k];
+                        }
+                        body(sa, m0);
+                        if (m0 + U >= maxtot) break;
+                        if (m0 + 2 * U < maxtot) {
+                            const uint4 *pq = a.src16 + rec(m0 + 2 * U);
+#pragma unroll
+                            for (int k = 0; k < U; k++) sa[k] = pq[k];
+                        }
+                        body(sb, m0 + U);
+                    }
                 }
             }
         };
