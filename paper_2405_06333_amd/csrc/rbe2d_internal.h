@@ -130,7 +130,8 @@ struct Workspace {
                                 // (|cA|, arg cA / 2 pi, |cB|, arg cB / 2 pi)
     double *fpart = nullptr;    // force-pass partials [ksplit][blocks * kBlock][4]
     // real space
-    int *cell = nullptr, *slot = nullptr, *count = nullptr, *start = nullptr, *tmp = nullptr;
+    int *cell = nullptr, *slot = nullptr, *count = nullptr, *start = nullptr;
+    int2 *tmp = nullptr;        // unordered cell lists: (caller index, global cell)
     int *scanbuf = nullptr;     // per-scan-block totals of the cell counts
     double4 *sorted = nullptr;  // (x - x0(cell), y, z, q) in cell order, padded per system
     uint4 *src16 = nullptr;     // the same particles as fixed-point (x, y, z) and FP32 q (FP32 kernel)

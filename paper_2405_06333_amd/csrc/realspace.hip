@@ -57,7 +57,9 @@ struct CellArgs {
     const SysDesc *sys;
     Layout lay;
     int n_sys, n_total, ncells;
-    int *cell, *slot, *count, *start, *tmp, *sidx, *scell;
+    int *cell, *slot, *count, *start, *sidx, *scell;
+    int2 *tmp;      // unordered cell lists: (caller index, global cell)
+    int n_waves;    // padded sorted positions / 64 (the rank pass runs one wave per system chunk)
     double4 *sorted;
     uint4 *src16;   // written when set (FP32 pair kernel)
 };
@@ -162,24 +164,28 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(int *count, int n, const 
 __global__ __launch_bounds__(kBlock) void k_cell_scatter(CellArgs a) {
     const int g = blockIdx.x * kBlock + threadIdx.x;
     if (g >= a.n_total) return;
-    a.tmp[a.start[a.cell[g]] + a.slot[g]] = g;
+    const int c = a.cell[g];
+    a.tmp[a.start[c] + a.slot[g]] = make_int2(g, c);
 }
 
 // position within the cell = number of members with a smaller caller index;
 // sorted positions are padded per system to whole waves.  One thread per
-// slot j of the unordered cell lists (tmp): the particle it holds is
-// gathered, and its record is written within the same cell, so the stores of
-// a wave stay within a few neighbouring cells.
+// padded sorted position, so a wave belongs to one system (its constants
+// are scalar loads); the thread takes slot j of the unordered cell lists
+// (tmp), gathers the particle it holds and writes its record within the
+// same cell, so the stores of a wave stay within a few neighbouring cells.
 __global__ __launch_bounds__(kBlock) void k_cell_rank(CellArgs a) {
-    const int j = blockIdx.x * kBlock + threadIdx.x;
-    if (j >= a.n_total) return;
-    const int g = a.tmp[j];
-    const int r = find_sys(a.lay.off, a.n_sys, g);
-    const SysDesc &d = a.sys[r];
-    const int c = a.cell[g];
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= a.n_waves * kWave) return;
+    const int r = __builtin_amdgcn_readfirstlane(find_sys(a.lay.sbase, a.n_sys, t & ~(kWave - 1)));
+    const SysDesc d = a.sys[r];   // a copy: wave-uniform values in scalar registers
+    const int j = t - a.lay.sbase[r] + a.lay.off[r];   // position in the unpadded cell lists
+    if (j >= a.lay.off[r + 1]) return;                   // padding of this system
+    const int2 gc = a.tmp[j];
+    const int g = gc.x, c = gc.y;
     const int b = a.start[c], e = a.start[c + 1];
     int rank = 0;
-    for (int j = b; j < e; j++) rank += a.tmp[j] < g;
+    for (int k = b; k < e; k++) rank += a.tmp[k].x < g;
     const int s = b + rank + (a.lay.sbase[r] - a.lay.off[r]);
     double xw, yw;
     const int cl = cell_of(a.pos[3 * (int64_t)g], a.pos[3 * (int64_t)g + 1], a.pos[3 * (int64_t)g + 2], d, &xw, &yw);
@@ -855,7 +861,7 @@ hipError_t launch_cells(rbe2d_ctx *h, const double *pos, const double *q, hipStr
     c.pos = pos; c.q = q; c.sys = h->w.sys; c.lay = h->w.lay; c.n_sys = h->n_sys;
     c.n_total = (int)h->n_total; c.ncells = h->total_cells;
     c.cell = h->w.cell; c.slot = h->w.slot; c.count = h->w.count; c.start = h->w.start;
-    c.tmp = h->w.tmp; c.sidx = h->w.sidx; c.scell = h->w.scell; c.sorted = h->w.sorted; c.src16 = h->w.src16;
+    c.tmp = h->w.tmp; c.n_waves = h->n_swaves; c.sidx = h->w.sidx; c.scell = h->w.scell; c.sorted = h->w.sorted; c.src16 = h->w.src16;
     const int nb = (int)((h->n_total + kBlock - 1) / kBlock);
     prof_begin(h, 3, s);
     // the counts start at zero (the previous build's scan cleared them); the
@@ -867,7 +873,7 @@ hipError_t launch_cells(rbe2d_ctx *h, const double *pos, const double *q, hipStr
     hipLaunchKernelGGL(k_scan_apply, dim3(nsb), dim3(kBlock), 0, s, h->w.count, h->total_cells, h->w.scanbuf,
                        h->w.start);
     hipLaunchKernelGGL(k_cell_scatter, dim3(nb), dim3(kBlock), 0, s, c);
-    hipLaunchKernelGGL(k_cell_rank, dim3(nb), dim3(kBlock), 0, s, c);
+    hipLaunchKernelGGL(k_cell_rank, dim3((h->n_swaves * kWave + kBlock - 1) / kBlock), dim3(kBlock), 0, s, c);
     prof_end(h, 3, s);
     return hipGetLastError();
 }
