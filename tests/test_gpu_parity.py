@@ -130,6 +130,22 @@ def test_box_shapes(torch, R, orc, precision, box):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("box", [(300, 40.0, 40.0, 6.0), (400, 30.0, 24.0, 14.0), (60, 12.0, 12.0, 4.0)],
+                         ids=["thin", "thick-rect", "small-box"])
+def test_sparse_cells(torch, R, orc, precision, box):
+    """Systems with few particles per cutoff sphere (n / volume * r_c^3 < 20)
+    get x-cells of r_c, three columns, and a slab thinner than 2 r_c at most
+    two layers; the small box is narrower than three such columns, so every
+    column is searched once."""
+    N, Lx, Ly, H = box
+    r_c = 5.0
+    assert N / (Lx * Ly * H) * r_c ** 3 < 20.0
+    w = inputs.Workload(f"sparse{Lx:g}x{Ly:g}x{H:g}", N, Lx, Ly, H, 0.85, -0.6, 0.7, r_c, 40, 5, seed=29)
+    F, E, ref, _ = run_pair(torch, R, orc, w, precision)
+    assert_parity(F, E, ref, TOL[precision])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_close_pairs(torch, R, orc, precision):
     """Pairs far closer than the FP32 kernel's fixed-point quantum allows
     (its FP64 recompute), across the periodic boundaries, and ions next to
