@@ -3,13 +3,14 @@
 #pragma once
 
 #include "rbe2d_internal.h"
+#include "sincos_fit.h"
 
 namespace rbe2d {
 
 // sin and cos of 2 pi r: r is reduced to the nearest quarter turn
-// (r - q/4 is exact by Sterbenz' lemma), then Taylor polynomials of sin
-// (to t^15) and cos (to t^16) on |t| <= pi/4, whose truncation errors are
-// below 5e-17.
+// (r - q/4 is exact by Sterbenz' lemma), then the polynomials of
+// sincos_fit.h (Chebyshev interpolants in t^2, gen_sincos_fit.py) on
+// |t| <= pi/4, within 1.2e-16 of sin and cos.
 __device__ __forceinline__ void sincos_rev64(double r, double *s_out, double *c_out) {
     const double qd = rint(4.0 * r);
     const double f = fma(-0.25, qd, r);
@@ -18,21 +19,13 @@ __device__ __forceinline__ void sincos_rev64(double r, double *s_out, double *c_
     const int qi = (int)qd;
     const double t = f * (2.0 * kPi);
     const double t2 = t * t;
-    double ps = -1.0 / 1307674368000.0;           // -1/15!
-    ps = fma(ps, t2, 1.0 / 6227020800.0);         // 1/13!
-    ps = fma(ps, t2, -1.0 / 39916800.0);          // -1/11!
-    ps = fma(ps, t2, 1.0 / 362880.0);             // 1/9!
-    ps = fma(ps, t2, -1.0 / 5040.0);              // -1/7!
-    ps = fma(ps, t2, 1.0 / 120.0);                // 1/5!
-    ps = fma(ps, t2, -1.0 / 6.0);                 // -1/3!
+    double ps = kSinQuarter[kSinQuarterTerms - 1];
+#pragma unroll
+    for (int k = kSinQuarterTerms - 2; k >= 0; k--) ps = fma(ps, t2, kSinQuarter[k]);
     const double sn = fma(t * t2, ps, t);
-    double pc = 1.0 / 20922789888000.0;           // 1/16!
-    pc = fma(pc, t2, -1.0 / 87178291200.0);       // -1/14!
-    pc = fma(pc, t2, 1.0 / 479001600.0);          // 1/12!
-    pc = fma(pc, t2, -1.0 / 3628800.0);           // -1/10!
-    pc = fma(pc, t2, 1.0 / 40320.0);              // 1/8!
-    pc = fma(pc, t2, -1.0 / 720.0);               // -1/6!
-    pc = fma(pc, t2, 1.0 / 24.0);                 // 1/4!
+    double pc = kCosQuarter[kCosQuarterTerms - 1];
+#pragma unroll
+    for (int k = kCosQuarterTerms - 2; k >= 0; k--) pc = fma(pc, t2, kCosQuarter[k]);
     pc = fma(pc, t2, -0.5);
     const double cs = fma(t2, pc, 1.0);
     // rotate by qi quarter turns: swap for odd qi, then flip the sign bits
@@ -46,24 +39,16 @@ __device__ __forceinline__ void sincos_rev64(double r, double *s_out, double *c_
 }
 
 // sin of 2 pi r alone: r is reduced to the nearest half turn (exact, as
-// above), then the Taylor polynomial of sin to t^23 on |t| <= pi/2, whose
-// truncation error is below 1e-20; an odd half turn flips the sign.
+// above), then the half-turn polynomial of sincos_fit.h on |t| <= pi/2,
+// within 2.3e-16 of sin; an odd half turn flips the sign.
 __device__ __forceinline__ double sin_rev64(double r) {
     const double kd = rint(2.0 * r);
     const double f = fma(-0.5, kd, r);
     const double t = f * (2.0 * kPi);
     const double t2 = t * t;
-    double p = -1.0 / 25852016738884976640000.0;  // -1/23!
-    p = fma(p, t2, 1.0 / 51090942171709440000.0);  // 1/21!
-    p = fma(p, t2, -1.0 / 121645100408832000.0);   // -1/19!
-    p = fma(p, t2, 1.0 / 355687428096000.0);       // 1/17!
-    p = fma(p, t2, -1.0 / 1307674368000.0);        // -1/15!
-    p = fma(p, t2, 1.0 / 6227020800.0);            // 1/13!
-    p = fma(p, t2, -1.0 / 39916800.0);             // -1/11!
-    p = fma(p, t2, 1.0 / 362880.0);                // 1/9!
-    p = fma(p, t2, -1.0 / 5040.0);                 // -1/7!
-    p = fma(p, t2, 1.0 / 120.0);                   // 1/5!
-    p = fma(p, t2, -1.0 / 6.0);                    // -1/3!
+    double p = kSinHalf[kSinHalfTerms - 1];
+#pragma unroll
+    for (int k = kSinHalfTerms - 2; k >= 0; k--) p = fma(p, t2, kSinHalf[k]);
     const double s = fma(t * t2, p, t);
     // an odd half turn flips the sign bit (|2 r| < 2^31, as above)
     const int sign = ((int)kd & 1) << 31;
