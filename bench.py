@@ -40,13 +40,14 @@ SLOTS_FORCE = 16   # k.r (3), khat.r (1), angle offsets of the polar amplitudes 
 SLOTS_REAL = 22    # per pair within r_c: d2 (5), cutoff (1), rsqrt (2), exp (2+1), erfc fit
                    # (rcp 2 + 7 FMA), force factor (2); pairs outside r_c not counted
 # the FP64 path (FP64 FMA issues at the FP32 rate on gfx950): software sincos
-# on revolutions (quarter-turn reduction 4, 7 + 8 polynomial FMAs, 4 products
-# and offsets: 23 per sincos)
-SLOTS_SF64 = 55      # k.r and khat.r (5), two sincos (46), 4 accumulating FMAs
-SLOTS_FORCE64 = 52   # phases (3), two half-turn-reduced sines (2 x 19) with their angle offsets
+# on revolutions (quarter-turn reduction 4, 6 + 7 polynomial FMAs and products,
+# t^2, 4 for the quadrant rotation: 21 per sincos)
+SLOTS_SF64 = 51      # k.r and khat.r (5), two sincos (42), 4 accumulating FMAs
+SLOTS_FORCE64 = 46   # phases (3), two half-turn-reduced sines (2 x 16) with their angle offsets
                      # and amplitudes (2 x 3), X +- Y (2), 3 force FMAs
-SLOTS_REAL64 = 85    # per pair within r_c: d2 and cutoff (6), sqrt (8), exp (25), two FP64
-                     # divisions (2 x 12), erfcx fit (16), products (6)
+SLOTS_REAL64 = 66    # per pair within r_c: d2 and cutoff (6), 1/sqrt refined twice (9), d and
+                     # 1/r^2 (2), exp (25), 1/(1 + p x) refined twice (6), erfcx fit (12),
+                     # products (6)
 SLOTS = {"fp32": {"sf_pass": SLOTS_SF, "force_scatter": SLOTS_FORCE, "real_pairs": SLOTS_REAL},
          "fp64": {"sf_pass": SLOTS_SF64, "force_scatter": SLOTS_FORCE64, "real_pairs": SLOTS_REAL64}}
 
