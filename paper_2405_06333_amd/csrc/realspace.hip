@@ -60,6 +60,11 @@ struct CellArgs {
     int *cell, *slot, *count, *start, *sidx, *scell;
     int2 *tmp;      // unordered cell lists: (caller index, global cell)
     int n_waves;    // padded sorted positions / 64 (the rank pass runs one wave per system chunk)
+    // set when the MD pass that moved the particles (and counted them) also
+    // wrote their k-space records on this stream: the rank pass reads those
+    // (one aligned record per particle) instead of positions and charges
+    const float4 *p32;
+    const double4 *p64;
     double4 *sorted;
     uint4 *src16;   // written when set (FP32 pair kernel)
 };
@@ -187,19 +192,39 @@ __global__ __launch_bounds__(kBlock) void k_cell_rank(CellArgs a) {
     int rank = 0;
     for (int k = b; k < e; k++) rank += a.tmp[k].x < g;
     const int s = b + rank + (a.lay.sbase[r] - a.lay.off[r]);
-    double xw, yw;
-    const int cl = cell_of(a.pos[3 * (int64_t)g], a.pos[3 * (int64_t)g + 1], a.pos[3 * (int64_t)g + 2], d, &xw, &yw);
+    double xw, yw, z, qg;
+    int cl;
+    if (a.p32 || a.p64) {
+        // the particle's k-space record: fractional x, y (wrapped) and z / L_z,
+        // split hi + lo in FP32 (46 significant bits) or exact in FP64, and q
+        // (FP32 in the FP32 records, as the FP32 pair kernel uses it)
+        const int64_t ii = (int64_t)a.lay.pbase[r] + (g - a.lay.off[r]);
+        double fx, fy, fz;
+        if (a.p32) {
+            const float4 u = a.p32[2 * ii], v = a.p32[2 * ii + 1];
+            fx = (double)u.x + (double)u.y; fy = (double)u.z + (double)u.w; fz = (double)v.x + (double)v.y;
+            qg = (double)v.z;
+        } else {
+            const double4 u = a.p64[ii];
+            fx = u.x; fy = u.y; fz = u.z; qg = u.w;
+        }
+        xw = fx * d.Lx; yw = fy * d.Ly; z = fz * d.Lz;
+        cl = c - d.cbase;   // the cell it was counted in
+    } else {
+        cl = cell_of(a.pos[3 * (int64_t)g], a.pos[3 * (int64_t)g + 1], a.pos[3 * (int64_t)g + 2], d, &xw, &yw);
+        z = a.pos[3 * (int64_t)g + 2];
+        qg = a.q[g];
+    }
     // x relative to the cell's lower x edge (a row along y shares it), y wrapped, z as given
     const int cx = (cl / d.ncy) % d.ncx;
-    const double z = a.pos[3 * (int64_t)g + 2];
-    a.sorted[s] = make_double4(xw - cx * d.hx, yw, z, a.q[g]);
+    a.sorted[s] = make_double4(xw - cx * d.hx, yw, z, qg);
     a.sidx[s] = g;
     a.scell[s] = cl;
     if (a.src16) {
         // z clamped into the frame (z outside (0, H) is flagged by prep)
         const double zc = fmin(fmax(z, -d.rc), d.H + d.rc);
         a.src16[s] = make_uint4(to_fixed(xw, d.fxs), to_fixed(yw, d.fys), to_fixed(zc + d.zoff, d.fzs),
-                                __float_as_uint((float)a.q[g]));
+                                __float_as_uint((float)qg));
     }
 }
 
@@ -862,6 +887,10 @@ hipError_t launch_cells(rbe2d_ctx *h, const double *pos, const double *q, hipStr
     c.n_total = (int)h->n_total; c.ncells = h->total_cells;
     c.cell = h->w.cell; c.slot = h->w.slot; c.count = h->w.count; c.start = h->w.start;
     c.tmp = h->w.tmp; c.n_waves = h->n_swaves; c.sidx = h->w.sidx; c.scell = h->w.scell; c.sorted = h->w.sorted; c.src16 = h->w.src16;
+    // counted by the MD pass: its k-space records of these positions precede this build on s
+    const bool fp32 = h->precision == RBE2D_PREC_FP32_PHASE;
+    c.p32 = h->cells_counted && fp32 ? h->w.p32 : nullptr;
+    c.p64 = h->cells_counted && !fp32 ? h->w.p64 : nullptr;
     const int nb = (int)((h->n_total + kBlock - 1) / kBlock);
     prof_begin(h, 3, s);
     // the counts start at zero (the previous build's scan cleared them); the
