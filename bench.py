@@ -405,6 +405,35 @@ def run_langevin(R, torch, w, precision, steps, autotune=True):
             "kinetic_T_after": round(kin, 4), "finite": bool(torch.isfinite(P_).all().item())}
 
 
+def run_surface(R, torch, w, precision, steps, sigma=0.01, autotune=True):
+    """The large slab between two like-charged interfaces: density -sigma on
+    z = 0 and on z = H, the ions' signs set so that their net charge cancels
+    the sheets' (2 sigma Lx Ly more cations than anions); velocity-Verlet
+    steps replayed from a hipGraph, as md_graph."""
+    from paper_2405_06333_amd import inputs
+    pos, _ = inputs.sample(w)
+    excess = int(round(2.0 * sigma * w.Lx * w.Ly))
+    if (w.N + excess) % 2:
+        excess += 1
+    q = np.where(np.arange(w.N) < (w.N + excess) // 2, 1.0, -1.0)
+    P_ = torch.as_tensor(pos, device="cuda")
+    Q_ = torch.as_tensor(q, device="cuda")
+    V_ = torch.zeros_like(P_)
+    slab = R.Slab(**w.slab_kwargs(), precision=precision, n_max=w.N)
+    slab.set_surface_charges(-sigma, -sigma)
+    slab.sample_kset(w.seed, 0)
+    if autotune:
+        slab.autotune(P_, Q_)
+    F_ = slab.forces(P_, Q_)
+    zlo, zhi = w.margin, w.H - w.margin
+    slab.md_run(P_, V_, Q_, F_, w.dt, zlo, zhi, w.seed, 1, 2, use_graph=True)
+    t = timed(torch, lambda: slab.md_run(P_, V_, Q_, F_, w.dt, zlo, zhi, w.seed, 3, steps, use_graph=True), 1)
+    slab.check()
+    return {"value": w.N * steps / t, "unit": "particle-steps/s", "steps": steps,
+            "sigma_top": -sigma, "sigma_bot": -sigma, "net_ionic_charge": float(q.sum()),
+            "finite": bool(torch.isfinite(P_).all().item() and torch.isfinite(F_).all().item())}
+
+
 def copy_probe(torch, mib):
     """A plain device copy of `mib` MiB, three times: the reference reading
     for the HBM byte counters."""
@@ -548,7 +577,7 @@ def main():
             _, fp64["kernels_alone"] = roofline_of({**alone64["kspace"], "real_pairs": alone64["real"]["real_pairs"]},
                                                    "fp64", NP, pairs_real, dom="real_pairs")
 
-    graph = batch = grad = langevin = parts = None
+    graph = batch = grad = langevin = surface = parts = None
     if a.side_steps > 0:
         alone = run_parts(R, torch, w, a.precision, a.side_steps)
         parts = {"calls": a.side_steps, "unit": "ms per launch"}
@@ -568,6 +597,7 @@ def main():
                              autotune=not a.no_autotune)
         graph = {"value": w.N * a.steps / sg, "unit": "particle-steps/s", "steps": a.steps}
         langevin = run_langevin(R, torch, w, a.precision, a.side_steps, autotune=not a.no_autotune)
+        surface = run_surface(R, torch, w, a.precision, a.side_steps, autotune=not a.no_autotune)
         batch = run_batch(R, torch, a.side_steps, autotune=not a.no_autotune)
         grad = run_grad(R, torch, a.side_steps, autotune=not a.no_autotune)
     cpu = None if a.no_cpu_baseline else cpu_baseline(w, a.cpu_sample, a.cpu_targets)
@@ -597,6 +627,7 @@ def main():
         "plain_fp64_gpu": fp64,
         "md_graph": graph,
         "md_langevin_wca": langevin,
+        "md_surface_charges": surface,
         "batched_replicas": batch,
         "differentiable": grad,
         "launch_params": tuned["launch_params"] if tuned else None,
