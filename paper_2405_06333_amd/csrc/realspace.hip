@@ -22,7 +22,8 @@
 // latency exposed, the drain threshold hardly matters).  Register cap: the
 // double-buffered scan of paired columns fits 4 waves per SIMD without
 // spills (122 VGPRs); at 5 waves it spills and is 5 % slower, uncapped at 3
-// waves slower still.
+// waves slower still.  The FP64 variant is capped at 4 waves per SIMD too
+// (no spills; 4.5 % faster alone than at its uncapped 3).
 #ifndef RBE2D_REAL_U32
 #define RBE2D_REAL_U32 4      // source loads per batch (two batches in flight per lane)
 #endif
@@ -531,14 +532,18 @@ __device__ WaveQueue<QW, U, DG> make_wave_queue(unsigned char *lds, int tid, con
 }
 
 template <bool FP32, bool WANT_DG, bool ISO>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(FP32 ? RBE2D_REAL_WAVES32 : 1, 8)))
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(FP32 ? RBE2D_REAL_WAVES32 : 4, 8)))
 void k_real(RealArgs a) {
     static_assert(FP32 || !ISO, "the isotropic frame is a property of the fixed-point records");
     using T = typename RealTypes<FP32>::T;
     constexpr int U = RealTypes<FP32>::U;
     constexpr int NW = kBlock / kWave;
     constexpr int kRingQ = RBE2D_RING_Q;   // FP32: ring entries per lane
-    constexpr int kWaveQ = 256;    // FP64: queue entries per wave
+    // FP64: queue entries per wave.  A drain leaves at most 63 and a batch
+    // adds at most U * 64, so the queue never holds more than 191; 240
+    // keeps the block's LDS under 40 KB (four blocks, four waves per SIMD)
+    constexpr int kWaveQ = 240;
+    static_assert(FP32 || kWaveQ >= (kWave - 1) + U * kWave, "a batch must fit behind a drained queue");
     using Queue = typename std::conditional<FP32, LaneRings<kRingQ, U, ISO, WANT_DG>,
                                             WaveQueue<kWaveQ, U, WANT_DG>>::type;
     constexpr size_t kLds = FP32 ? sizeof(float4) * kRingQ * kBlock
