@@ -115,7 +115,8 @@ def parse():
 
 def expected_real_pairs(w, nz=4000):
     """Expected number of (target, source) pairs within r_c for uniform
-    density in [margin, H - margin], real sources plus first images."""
+    density in [margin, H - margin], real sources plus first images; a
+    target's own image counts too (at distance 2 z below, 2 (H - z) above)."""
     rho = w.N / (w.Lx * w.Ly * (w.H - 2 * w.margin))
     z = np.linspace(w.margin, w.H - w.margin, nz)
     rc = w.r_c
@@ -130,7 +131,9 @@ def expected_real_pairs(w, nz=4000):
     lo, hi = w.margin, w.H - w.margin
     direct = cap_volume(z, lo, hi)
     img = cap_volume(-z, lo, hi) + cap_volume(2 * w.H - z, lo, hi)   # first-order images
-    return float(rho * w.N * np.mean(direct + img))
+    # a target's own image is within r_c below for z < r_c / 2, above for H - z < r_c / 2
+    own = (min(max(0.5 * rc - lo, 0.0), hi - lo) + min(max(hi - (w.H - 0.5 * rc), 0.0), hi - lo)) / (hi - lo)
+    return float(w.N * (rho * np.mean(direct + img) + own))
 
 
 def run_md(R, torch, w, precision, steps, warmup, profile, use_graph=False, autotune=True):

@@ -28,7 +28,7 @@ def counted_pairs(w, n_targets, seed):
     real charges (minimum image in x and y, the target itself excluded) plus
     the first-order images, i.e. sources within r_c of the target reflected
     in z = 0 and in z = H (Sec. 3.1; higher orders lie beyond r_c when
-    H > r_c)."""
+    H > r_c), the target's own image included."""
     assert w.H > w.r_c
     pos, _ = inputs.sample(w)
     # z is not periodic: a period of 4 H exceeds every distance that matters
@@ -57,17 +57,29 @@ def test_expected_real_pairs_matches_count():
     assert 160 < expected / w.N < 168
 
 
+def test_expected_real_pairs_of_the_replica_batch():
+    """The 64-replica batch's pair count (the batch roofline's unit) is the sum
+    of the replicas' closed forms; checked on every replica against the count
+    over all of its ions (thin slabs, H = 10 < 2 r_c, where both faces cut
+    most spheres)."""
+    ws = inputs.replicas()
+    expected = sum(bench.expected_real_pairs(w) for w in ws)
+    counted = sum(counted_pairs(w, min(w.N, 2000), seed=12) for w in ws)
+    assert abs(counted - expected) <= 0.005 * expected, (counted, expected)
+
+
 def test_expected_real_pairs_is_not_the_full_sphere():
     """The slab's faces cut the spheres: fewer pairs than the unbounded
-    4/3 pi r_c^3 rho, and the image terms put some back."""
+    4/3 pi r_c^3 rho; with the faces far away, the full sphere plus the few
+    targets within r_c / 2 of a face that meet their own image."""
     w = inputs.LARGE_MD
     rho = w.N / (w.Lx * w.Ly * (w.H - 2 * w.margin))
-    full = rho * w.N * 4.0 / 3.0 * math.pi * w.r_c ** 3
-    no_img = w.with_(H=1e6 * w.H)   # faces far away: the full sphere
-    assert bench.expected_real_pairs(w) < full
-    assert bench.expected_real_pairs(no_img) == pytest.approx(
-        no_img.N / (no_img.Lx * no_img.Ly * (no_img.H - 2 * no_img.margin)) * no_img.N * 4.0 / 3.0 * math.pi
-        * no_img.r_c ** 3, rel=1e-3)
+    assert bench.expected_real_pairs(w) < rho * w.N * 4.0 / 3.0 * math.pi * w.r_c ** 3
+    far = w.with_(H=1e6 * w.H)
+    span = far.H - 2 * far.margin
+    sphere = far.N / (far.Lx * far.Ly * span) * far.N * 4.0 / 3.0 * math.pi * far.r_c ** 3
+    own = far.N * 2.0 * (0.5 * far.r_c - far.margin) / span
+    assert bench.expected_real_pairs(far) == pytest.approx(sphere + own, rel=2e-4)
 
 
 def test_roofline_block_definition():
