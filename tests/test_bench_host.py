@@ -98,3 +98,21 @@ def test_roofline_block_definition():
     # a live duration replaces the breakdown's
     roof2, _ = bench.roofline_of(breakdown, "fp32", NP, pairs, dom="real_pairs", t_dom=1.0e-3)
     assert roof2["frac"] == pytest.approx(bench.SLOTS_REAL * pairs / 1.0e-3 / bench.VALU_LANE_SLOTS, abs=1e-4)
+
+
+def test_traffic_figure_only_for_the_sources_it_was_measured_on(tmp_path, monkeypatch):
+    """roofline.traffic comes from the committed counter summary only while
+    the pair kernel's sources hash to the value recorded with it."""
+    good = tmp_path / "good.txt"
+    good.write_text("bench_kernel: real_pairs\nsource_sha256: %s\ntraffic_bytes_per_launch: 1234\n"
+                    % bench.kernel_source_hash())
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(good))
+    assert bench.measured_traffic("real_pairs") == 1234.0
+    assert bench.measured_traffic("sf_pass") is None          # recorded for another kernel
+    stale = tmp_path / "stale.txt"
+    stale.write_text("bench_kernel: real_pairs\nsource_sha256: %s\ntraffic_bytes_per_launch: 1234\n" % ("0" * 64))
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(stale))
+    assert bench.measured_traffic("real_pairs") is None       # other kernel sources
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "missing.txt"))
+    assert bench.measured_traffic("real_pairs") is None
+
